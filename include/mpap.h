@@ -1,0 +1,193 @@
+/*
+ * mpap.h - C ABI of the MI355X wavefront multiobjective perception-aware
+ * search library (libmpap.so).
+ *
+ * The library implements the search stage of the Multiobjective
+ * Perception-Aware Planning algorithm (Ichter, Landry, Schmerling, Pavone,
+ * "Perception-Aware Motion Planning via Multiobjective Search on GPUs"):
+ * Sec. 3, Alg. 3 (Explore) over a roadmap built by Alg. 2 (BuildGraph), with
+ * the drift heuristic of Sec. 4.1 as the perception heuristic.
+ *
+ * Conventions for every call:
+ *  - All functions are extern "C", return an int status (MPAP_OK == 0) and
+ *    never throw.  On failure a message is available from mpap_last_error()
+ *    (thread-local, valid until the next call on the same thread).
+ *  - Pointers named host_* or documented as "host" are ordinary CPU memory;
+ *    the library copies what it needs and does not keep them.
+ *  - Opaque handles (mpap_graph, mpap_result) own device memory on the
+ *    device that was current when they were created; free them with the
+ *    matching *_free call.  A handle must not be used from two threads at
+ *    once; use one stream per concurrent search.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it and the call returns once the results it reports
+ *    are complete.
+ *  - Floating point: IEEE float32, round to nearest, no fused multiply-add on
+ *    the label path, no flush of denormals.
+ */
+#ifndef MPAP_H
+#define MPAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define MPAP_OK 0
+#define MPAP_ERR_INVAL 1      /* bad argument (null, range, NaN, shape) */
+#define MPAP_ERR_NOGOAL 2     /* no roadmap node lies in the goal region */
+#define MPAP_ERR_NOMEM 3      /* device or host allocation failed */
+#define MPAP_ERR_HIP 4        /* a HIP runtime call failed */
+#define MPAP_ERR_OVERFLOW 5   /* a capacity limit was hit after all retries */
+#define MPAP_ERR_NOCONVERGE 6 /* max_waves reached with plans still open */
+#define MPAP_ERR_CAPACITY 7   /* caller buffer too small; *count holds the need */
+#define MPAP_ERR_DEVICE 8     /* no usable gfx950 device / feature missing */
+
+typedef struct mpap_graph mpap_graph;   /* device-resident roadmap */
+typedef struct mpap_result mpap_result; /* outcome of one search */
+
+/* ----------------------------------------------------------- environment */
+/* A mapped environment and roadmap samples (Sec. 2 problem data; Sec. 4.2
+ * axis-aligned box obstacles; Sec. 4.1 mapped perception features, here as
+ * isotropic Gaussian blobs whose summed density is the quality q(x)). */
+typedef struct {
+    int32_t dim;              /* 2 or 3 */
+    int32_t n_nodes;          /* number of roadmap nodes; node 0 is x_init */
+    const float *pos;         /* host [n_nodes][dim] node positions */
+    int32_t n_boxes;          /* obstacle count (>= 0) */
+    const float *box_lo;      /* host [n_boxes][dim] lower corners */
+    const float *box_hi;      /* host [n_boxes][dim] upper corners (closed) */
+    int32_t n_blobs;          /* feature blob count (>= 0) */
+    const float *blob_mu;     /* host [n_blobs][dim] centres */
+    const float *blob_sigma;  /* host [n_blobs] widths (> 0) */
+    const float *blob_amp;    /* host [n_blobs] amplitudes */
+    float goal[3];            /* goal ball centre (first dim entries used) */
+    float goal_radius;        /* goal ball radius (closed ball) */
+} mpap_env;
+
+typedef struct {
+    float radius;     /* r_n: an edge u->v exists iff Cost(u,v) < radius (Alg. 2, Near) */
+    float check_step; /* sub-step length of Collision and of the drift integral */
+    float reset_q;    /* a node relocalises (drift resets to 0) iff q(x) > reset_q */
+} mpap_graph_params;
+
+/*
+ * mpap_build_graph - Alg. 2 (BuildGraph) plus the per-edge heuristic inputs
+ * (Alg. 1, step 2), on the GPU.
+ *   Edges: u->v for v != u with Cost(u,v) = |x_v - x_u| < radius (float32,
+ *   separately rounded ops) whose straight segment, checked at points
+ *   x_a + (k/K)(x_b - x_a), k = 0..K, K = ceil(Cost/check_step), (a, b) the
+ *   pair in id order, misses every closed box.  Per edge: cost = Cost and
+ *   drift = Cost * (1 - mean q over the K sub-step midpoints).  Per node:
+ *   reset = q(x) > reset_q, goal = |x - goal|^2 <= goal_radius^2.
+ *   q(x) = clamp(sum_j amp_j exp(-|x - mu_j|^2 / (2 sigma_j^2)), 0, 1),
+ *   evaluated in float32 with the device expf (not bit-identical to a host
+ *   libm; drift and reset agree with a float64 evaluation within a few ulp).
+ * Errors: MPAP_ERR_INVAL (null, dim not 2/3, n_nodes < 1, non-finite
+ * position, radius <= 0), MPAP_ERR_NOGOAL (no node in the goal ball; no
+ * graph is returned), MPAP_ERR_NOMEM, MPAP_ERR_HIP.
+ */
+int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *stream,
+                     mpap_graph **out);
+
+/*
+ * mpap_graph_from_csr - import a roadmap given as forward CSR (host memory).
+ *   row_ptr[n_nodes+1] (row_ptr[0] == 0, non-decreasing), col[E] targets in
+ *   [0, n_nodes), self loops not allowed; cost[E] > 0 finite; drift[E] >= 0
+ *   finite; reset[n_nodes], goal[n_nodes] are 0/1 flags.  Inputs are copied.
+ * Errors: MPAP_ERR_INVAL on any violated condition, MPAP_ERR_NOMEM,
+ * MPAP_ERR_HIP.  (A graph with no goal node is accepted; its searches return
+ * an empty goal front.)
+ */
+int mpap_graph_from_csr(int32_t n_nodes, const int32_t *row_ptr, const int32_t *col,
+                        const float *cost, const float *drift, const uint8_t *reset,
+                        const uint8_t *goal, void *stream, mpap_graph **out);
+
+/* Sizes of a graph. Any output pointer may be NULL. */
+int mpap_graph_info(const mpap_graph *g, int32_t *n_nodes, int64_t *n_edges, int32_t *n_goal);
+
+/* Copy a graph back to host memory in the forward-CSR form taken by
+ * mpap_graph_from_csr (rows sorted by target id).  Buffers are caller-owned
+ * and sized from mpap_graph_info. */
+int mpap_graph_export(const mpap_graph *g, int32_t *row_ptr, int32_t *col, float *cost,
+                      float *drift, uint8_t *reset, uint8_t *goal);
+
+void mpap_graph_free(mpap_graph *g);
+
+/* ---------------------------------------------------------------- search */
+typedef struct {
+    float beta;        /* bound on the drift heuristic, eq. (2); +inf = off */
+    float lambda;      /* group cost factor of Alg. 3 (0 < lambda); 0.5 in Sec. 4.2 */
+    float radius;      /* r_n of the roadmap; groups advance by lambda * radius */
+    int32_t n_obj;     /* 2: (cost, drift); 3: (cost, drift, max drift so far) */
+    int32_t init_node; /* root of every plan (x_init), usually 0 */
+    int32_t max_waves; /* cap on Explore iterations; 0 = 1 << 18 */
+} mpap_search_params;
+
+/*
+ * mpap_search - Alg. 3 (Explore) run until no plan is open, on the GPU.
+ *   Labels (head, cost c, drift d [, max drift m], parent) are expanded in
+ *   groups of open labels whose cost is at most the current threshold, which
+ *   rises by lambda * radius per iteration (skipping empty groups).  A child
+ *   along edge e = u->v has c + cost_e, d_pre = d + drift_e; it is dropped if
+ *   d_pre > beta; its drift is 0 if reset[v] else d_pre; m = max(m, d_pre).
+ *   RemoveDominated is weak Pareto dominance per head node (a label is removed
+ *   if another at the same node is <= in every objective; equal vectors are
+ *   kept once).  All sums are float32 in path order, so the per-node fronts
+ *   are exactly the Pareto-minimal vectors of the plans to each node.
+ *   Capacity limits (label arena, bucket pool) grow and the search restarts
+ *   automatically; MPAP_ERR_OVERFLOW only after that fails.
+ * Errors: MPAP_ERR_INVAL (null, n_obj not 2/3, init_node out of range,
+ * lambda <= 0, radius <= 0, beta NaN), MPAP_ERR_NOCONVERGE, MPAP_ERR_OVERFLOW,
+ * MPAP_ERR_NOMEM, MPAP_ERR_HIP, MPAP_ERR_DEVICE.
+ * An empty goal front is a successful result with count 0.
+ */
+int mpap_search(const mpap_graph *g, const mpap_search_params *sp, void *stream,
+                mpap_result **out);
+
+/*
+ * mpap_goal_front - the Pareto front over all goal nodes (P_candidates of
+ * Alg. 3 kept whole), ascending lexicographic order of (c, d, m); entry 0 is
+ * the minimum-cost plan P_soln.  Each entry names one witness label (goal
+ * node and label id, usable with mpap_label_path).  maxdrift may be NULL;
+ * for n_obj == 2 it is filled with 0.  *count always receives the front size;
+ * if capacity < count nothing is written and MPAP_ERR_CAPACITY is returned.
+ */
+int mpap_goal_front(const mpap_result *r, float *cost, float *drift, float *maxdrift,
+                    int32_t *goal_node, int32_t *label_id, int32_t capacity, int32_t *count);
+
+/* mpap_node_front - the final label set P(node) of one node (Alg. 3), in
+ * storage order (not sorted), with each label's id.  Any output array may be
+ * NULL.  Same capacity rule as mpap_goal_front. */
+int mpap_node_front(const mpap_result *r, int32_t node, float *cost, float *drift,
+                    float *maxdrift, int32_t *label_id, int32_t capacity, int32_t *count);
+
+/* mpap_label_path - node sequence of the plan ending in label_id, root first
+ * (the plan's path field of Sec. 3).  *length receives the node count;
+ * MPAP_ERR_CAPACITY if it exceeds capacity (nothing written). */
+int mpap_label_path(const mpap_result *r, int32_t label_id, int32_t *nodes, int32_t capacity,
+                    int32_t *length);
+
+typedef struct {
+    int32_t waves;            /* Explore iterations that expanded a group */
+    int32_t retries;          /* capacity-growth restarts */
+    int64_t labels_expanded;  /* labels taken into a group (arena size) */
+    int64_t front_labels;     /* sum over nodes of the final front sizes */
+    int64_t merges;           /* per-node dominance merges */
+    int64_t candidates;       /* children generated that passed the bound */
+    float gpu_ms;             /* device time of the search launch(es) */
+} mpap_stats;
+
+int mpap_result_stats(const mpap_result *r, mpap_stats *out);
+void mpap_result_free(mpap_result *r);
+
+/* ----------------------------------------------------------------- misc */
+const char *mpap_status_string(int status);
+const char *mpap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPAP_H */

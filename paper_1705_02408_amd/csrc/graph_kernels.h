@@ -1,0 +1,42 @@
+// Kernel argument block of the roadmap construction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+constexpr int kScanTile = 4096;
+
+struct BuildArgs {
+    int n;
+    int dim;
+    const float *pos;  // device [n][dim]
+    int nbox;
+    const float *blo;  // device [nbox][dim]
+    const float *bhi;
+    int nblob;
+    const float *mu;   // device [nblob][dim]
+    const float *sig;  // [nblob]
+    const float *amp;  // [nblob]
+    float r;
+    float step;
+    float reset_q;
+    float goal[3];
+    float goal_r;
+};
+
+__global__ void k_near_count(BuildArgs g, int *cnt);
+__global__ void k_near_fill(BuildArgs g, const int *off, int *cand_u, int *cand_v,
+                            float *cand_c);
+__global__ void k_collide(BuildArgs g, long long m, const int *cand_u, const int *cand_v,
+                          const float *cand_c, int *keep);
+__global__ void k_compact_edges(long long m, const int *keep, const int *kscan,
+                                const int *cand_v, const float *cand_c, int *col, float *cost);
+__global__ void k_row_ptr(int n, long long m, const int *cand_off, const int *kscan,
+                          const int *keep, int *row_ptr);
+__global__ void k_edge_drift(BuildArgs g, int n, const int *row_ptr, const int *col,
+                             const float *cost, float *drift);
+__global__ void k_node_flags(BuildArgs g, uint8_t *flag);
+__global__ void k_flag_list(int n, const uint8_t *flag, unsigned bit, int *list, int *count);
+__global__ void k_scan_block_sums(const int *in, long long n, int *bsum);
+__global__ void k_scan_sums(int *bsum, int nb);
+__global__ void k_scan_apply(const int *in, long long n, const int *bsum, int *out);

@@ -1,0 +1,278 @@
+// Roadmap construction on the GPU: Sec. 3 Alg. 2 (BuildGraph: Near within
+// r_n, then Collision against axis-aligned boxes as in Sec. 4.2) and the
+// per-edge / per-node inputs of the perception heuristic (Alg. 1 step 2):
+// drift increment = length * (1 - mean feature quality over the collision
+// sub-steps) and the relocalisation flag q(x) > threshold (Sec. 4.1 drift
+// reading with a feature-density quality q).
+//
+// Every float32 operation on the geometry is rounded separately (built with
+// -ffp-contract=off), so neighbour sets and edge lengths are reproducible
+// bit for bit by any IEEE float32 evaluation of the same formulas.
+#include "device_common.h"
+#include "graph_kernels.h"
+
+namespace {
+
+__device__ __forceinline__ float sqdist(const float *a, const float *b, int dim) {
+    float dx = b[0] - a[0];
+    float s = dx * dx;
+    for (int k = 1; k < dim; ++k) {
+        float d = b[k] - a[k];
+        s = s + d * d;
+    }
+    return s;
+}
+
+__device__ __forceinline__ float quality(const BuildArgs &g, const float *x) {
+    float acc = 0.0f;
+    for (int j = 0; j < g.nblob; ++j) {
+        float d2 = 0.0f;
+        for (int k = 0; k < g.dim; ++k) {
+            const float t = x[k] - g.mu[j * g.dim + k];
+            d2 = d2 + t * t;
+        }
+        const float s = g.sig[j];
+        acc = acc + g.amp[j] * expf(-d2 / (2.0f * s * s));
+    }
+    return fminf(fmaxf(acc, 0.0f), 1.0f);
+}
+
+}  // namespace
+
+// Near: number of v != u with Cost(u, v) < r.  Positions are staged in LDS
+// tiles shared by the block.
+__global__ void __launch_bounds__(256) k_near_count(BuildArgs g, int *cnt) {
+    __shared__ float tile[256 * 3];
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    float xu[3] = {0.f, 0.f, 0.f};
+    if (u < g.n)
+        for (int k = 0; k < g.dim; ++k) xu[k] = g.pos[u * g.dim + k];
+    int c = 0;
+    for (int t0 = 0; t0 < g.n; t0 += 256) {
+        __syncthreads();
+        const int v = t0 + threadIdx.x;
+        if (v < g.n)
+            for (int k = 0; k < g.dim; ++k) tile[threadIdx.x * 3 + k] = g.pos[v * g.dim + k];
+        __syncthreads();
+        const int m = min(256, g.n - t0);
+        if (u < g.n)
+            for (int i = 0; i < m; ++i) {
+                const float cost = sqrtf(sqdist(xu, &tile[i * 3], g.dim));
+                c += (cost < g.r && t0 + i != u) ? 1 : 0;
+            }
+    }
+    if (u < g.n) cnt[u] = c;
+}
+
+__global__ void __launch_bounds__(256) k_near_fill(BuildArgs g, const int *off, int *cand_u,
+                                                   int *cand_v, float *cand_c) {
+    __shared__ float tile[256 * 3];
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    float xu[3] = {0.f, 0.f, 0.f};
+    if (u < g.n)
+        for (int k = 0; k < g.dim; ++k) xu[k] = g.pos[u * g.dim + k];
+    int o = (u < g.n) ? off[u] : 0;
+    for (int t0 = 0; t0 < g.n; t0 += 256) {
+        __syncthreads();
+        const int v = t0 + threadIdx.x;
+        if (v < g.n)
+            for (int k = 0; k < g.dim; ++k) tile[threadIdx.x * 3 + k] = g.pos[v * g.dim + k];
+        __syncthreads();
+        const int m = min(256, g.n - t0);
+        if (u < g.n)
+            for (int i = 0; i < m; ++i) {
+                const float cost = sqrtf(sqdist(xu, &tile[i * 3], g.dim));
+                if (cost < g.r && t0 + i != u) {
+                    cand_u[o] = u;
+                    cand_v[o] = t0 + i;
+                    cand_c[o] = cost;
+                    ++o;
+                }
+            }
+    }
+}
+
+// Collision(a, b), (a, b) the candidate pair in id order: points
+// x_a + (k/K)(x_b - x_a), k = 0..K, K = ceil(cost/step), against closed boxes.
+__global__ void __launch_bounds__(256) k_collide(BuildArgs g, long long m, const int *cand_u,
+                                                 const int *cand_v, const float *cand_c,
+                                                 int *keep) {
+    extern __shared__ float boxes[];  // lo[nbox*dim], hi[nbox*dim]
+    for (int i = threadIdx.x; i < g.nbox * g.dim; i += blockDim.x) {
+        boxes[i] = g.blo[i];
+        boxes[g.nbox * g.dim + i] = g.bhi[i];
+    }
+    __syncthreads();
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const int u = cand_u[e], v = cand_v[e];
+    const int a = min(u, v), b = max(u, v);
+    float xa[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < g.dim; ++k) {
+        xa[k] = g.pos[a * g.dim + k];
+        df[k] = g.pos[b * g.dim + k] - xa[k];
+    }
+    int K = (int)ceilf(cand_c[e] / g.step);
+    if (K < 1) K = 1;
+    const float fK = (float)K;
+    bool hit = false;
+    for (int s = 0; s <= K && !hit; ++s) {
+        const float t = (float)s / fK;
+        float p[3];
+        for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + t * df[k];
+        for (int j = 0; j < g.nbox && !hit; ++j) {
+            bool in = true;
+            for (int k = 0; k < g.dim; ++k) {
+                const float lo = boxes[j * g.dim + k];
+                const float hi = boxes[g.nbox * g.dim + j * g.dim + k];
+                in = in && (p[k] >= lo) && (p[k] <= hi);
+            }
+            hit = in;
+        }
+    }
+    keep[e] = hit ? 0 : 1;
+}
+
+__global__ void __launch_bounds__(256) k_compact_edges(long long m, const int *keep,
+                                                       const int *kscan, const int *cand_v,
+                                                       const float *cand_c, int *col,
+                                                       float *cost) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m || !keep[e]) return;
+    const int o = kscan[e];
+    col[o] = cand_v[e];
+    cost[o] = cand_c[e];
+}
+
+__global__ void __launch_bounds__(256) k_row_ptr(int n, long long m, const int *cand_off,
+                                                 const int *kscan, const int *keep,
+                                                 int *row_ptr) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n) return;
+    const long long o = (u < n) ? cand_off[u] : m;
+    row_ptr[u] = (o < m) ? kscan[o] : (m > 0 ? kscan[m - 1] + keep[m - 1] : 0);
+}
+
+// drift of edge row u -> col[e]: sum_j (len/K)(1 - q(mid_j)) over the K
+// sub-step midpoints of the id-ordered pair (a, b) (the same value for both
+// directions of an edge).
+__global__ void __launch_bounds__(256) k_edge_drift(BuildArgs g, int n, const int *row_ptr,
+                                                    const int *col, const float *cost,
+                                                    float *drift) {
+    extern __shared__ float blob[];  // mu[nblob*dim], sig[nblob], amp[nblob]
+    for (int i = threadIdx.x; i < g.nblob * g.dim; i += blockDim.x) blob[i] = g.mu[i];
+    for (int i = threadIdx.x; i < g.nblob; i += blockDim.x) {
+        blob[g.nblob * g.dim + i] = g.sig[i];
+        blob[g.nblob * g.dim + g.nblob + i] = g.amp[i];
+    }
+    __syncthreads();
+    BuildArgs gl = g;
+    gl.mu = blob;
+    gl.sig = blob + g.nblob * g.dim;
+    gl.amp = blob + g.nblob * g.dim + g.nblob;
+    const int u = blockIdx.x;  // one block per row, threads over the row's edges
+    if (u >= n) return;
+    for (int e = row_ptr[u] + threadIdx.x; e < row_ptr[u + 1]; e += blockDim.x) {
+        const int v = col[e];
+        const int a = min(u, v), b = max(u, v);
+        float xa[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < g.dim; ++k) {
+            xa[k] = g.pos[a * g.dim + k];
+            df[k] = g.pos[b * g.dim + k] - xa[k];
+        }
+        const float len = cost[e];
+        int K = (int)ceilf(len / g.step);
+        if (K < 1) K = 1;
+        const float fK = (float)K;
+        const float w = len / fK;
+        float acc = 0.0f;
+        for (int j = 0; j < K; ++j) {
+            const float s = ((float)j + 0.5f) / fK;
+            float p[3];
+            for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + s * df[k];
+            acc = acc + w * (1.0f - quality(gl, p));
+        }
+        drift[e] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_node_flags(BuildArgs g, uint8_t *flag) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    float x[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < g.dim; ++k) x[k] = g.pos[v * g.dim + k];
+    uint8_t f = 0;
+    if (quality(g, x) > g.reset_q) f |= 1u;
+    float gg[3] = {g.goal[0], g.goal[1], g.goal[2]};
+    const float r = g.goal_r;
+    if (sqdist(gg, x, g.dim) <= r * r) f |= 2u;
+    flag[v] = f;
+}
+
+// Ordered list of the nodes with flag bit `bit` set (single block).
+__global__ void __launch_bounds__(1024) k_flag_list(int n, const uint8_t *flag, unsigned bit,
+                                                    int *list, int *count) {
+    __shared__ int scan[32];
+    int carry = 0;
+    for (int t0 = 0; t0 < n; t0 += blockDim.x) {
+        const int v = t0 + threadIdx.x;
+        const int f = (v < n && (flag[v] & bit)) ? 1 : 0;
+        int tot;
+        const int ex = block_excl_scan(f, scan, &tot);
+        if (f) list[carry + ex] = v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
+// ------------------------------------------------------------------- scan
+// Exclusive prefix sum of int32 values in three passes (block sums, scan of
+// block sums in one block, add-back).  Each block covers kScanTile items.
+__global__ void __launch_bounds__(256) k_scan_block_sums(const int *in, long long n,
+                                                         int *bsum) {
+    __shared__ int scan[16];
+    const long long base = (long long)blockIdx.x * kScanTile;
+    int s = 0;
+    for (int i = threadIdx.x; i < kScanTile; i += blockDim.x)
+        if (base + i < n) s += in[base + i];
+    int tot;
+    block_excl_scan(s, scan, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_sums(int *bsum, int nb) {
+    __shared__ int scan[32];
+    int carry = 0;
+    for (int t0 = 0; t0 < nb; t0 += blockDim.x) {
+        const int i = t0 + threadIdx.x;
+        const int v = (i < nb) ? bsum[i] : 0;
+        int tot;
+        const int ex = block_excl_scan(v, scan, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const int *in, long long n,
+                                                    const int *bsum, int *out) {
+    __shared__ int scan[16];
+    const long long base = (long long)blockIdx.x * kScanTile;
+    int carry = bsum[blockIdx.x];
+    constexpr int per = kScanTile / 256;
+    // each thread owns `per` consecutive items
+    int v[per];
+    int s = 0;
+    for (int k = 0; k < per; ++k) {
+        const long long i = base + (long long)threadIdx.x * per + k;
+        v[k] = (i < n) ? in[i] : 0;
+        s += v[k];
+    }
+    int tot;
+    int ex = block_excl_scan(s, scan, &tot);
+    int run = carry + ex;
+    for (int k = 0; k < per; ++k) {
+        const long long i = base + (long long)threadIdx.x * per + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+}

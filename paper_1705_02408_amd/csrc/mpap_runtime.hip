@@ -1,0 +1,742 @@
+// Host runtime and C ABI of libmpap (see include/mpap.h).
+//
+// Owns device memory for graphs and search workspaces, validates inputs,
+// launches the kernels, grows capacities and retries when the device reports
+// an overflow, and copies results back.  No part of the search itself runs on
+// the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "graph_kernels.h"
+#include "mpap.h"
+#include "search_kernels.h"
+
+// ------------------------------------------------------------- error state
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? MPAP_ERR_NOMEM : MPAP_ERR_HIP,      \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+struct DeviceInfo {
+    int dev = -1;
+    int cus = 0;
+    int coop = 0;
+    size_t max_lds = 0;
+};
+
+int device_info(DeviceInfo *out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MPAP_ERR_DEVICE, std::string("libmpap is built for gfx950, device is ") +
+                                         prop.gcnArchName);
+    out->dev = dev;
+    out->cus = prop.multiProcessorCount;
+    int coop = 0;
+    HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    out->coop = coop;
+    out->max_lds = prop.sharedMemPerBlock;
+    if (!coop) return fail(MPAP_ERR_DEVICE, "device does not support cooperative launches");
+    return MPAP_OK;
+}
+
+template <typename T>
+int dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    HIP_TRY(hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)));
+    return MPAP_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// exclusive scan of n int32 (device); tmp holds >= div_up(n, kScanTile) ints
+int scan_i32(const int *in, int *out, long long n, int *tmp, hipStream_t s) {
+    if (n <= 0) return MPAP_OK;
+    const int nb = div_up(n, kScanTile);
+    k_scan_block_sums<<<nb, 256, 0, s>>>(in, n, tmp);
+    k_scan_sums<<<1, 1024, 0, s>>>(tmp, nb);
+    k_scan_apply<<<nb, 256, 0, s>>>(in, n, tmp, out);
+    HIP_TRY(hipGetLastError());
+    return MPAP_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ graph
+struct Workspace;
+
+struct mpap_graph {
+    int dev = -1;
+    int32_t n = 0;
+    int64_t e = 0;
+    int32_t n_goal = 0;
+    bool symmetric_alias = false;  // in-edge arrays alias the out-edge ones
+    // forward CSR
+    int32_t *optr = nullptr, *ocol = nullptr;
+    float *ocost = nullptr, *odrift = nullptr;
+    // reverse CSR (in-edges)
+    int32_t *rptr = nullptr, *rsrc = nullptr;
+    float *rcost = nullptr, *rdrift = nullptr;
+    uint8_t *nflag = nullptr;
+    int32_t *goal_list = nullptr;
+    std::vector<Workspace *> spare;
+    std::mutex mu;
+};
+
+static void graph_release(mpap_graph *g);
+
+// ------------------------------------------------------------- workspace
+struct Workspace {
+    int32_t n = 0;
+    unsigned long long pool_cap = 0;
+    long long arena_cap = 0, F_cap = 0;
+    int nblocks = 0;
+    int goal_cap = 0;
+    float4 *pool = nullptr;
+    unsigned *pool_top = nullptr;
+    int4 *nb = nullptr;
+    float *minopen = nullptr;
+    int *gcnt = nullptr;
+    int4 *fo = nullptr;
+    int *mark = nullptr;
+    int *alist = nullptr;
+    int *acnt = nullptr;
+    float4 *F = nullptr;
+    int2 *arena = nullptr;
+    long long *part_cnt = nullptr, *part_open = nullptr;
+    float *part_min = nullptr;
+    unsigned *bar = nullptr;
+    int *err = nullptr;
+    long long *out = nullptr;
+    // goal front
+    float4 *g_lab = nullptr, *g_out = nullptr;
+    int *g_node = nullptr, *g_out_node = nullptr, *g_n = nullptr, *g_count = nullptr;
+    uint8_t *g_dead = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    void free_all() {
+        dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
+        dfree(mark); dfree(alist); dfree(acnt); dfree(F); dfree(arena); dfree(part_cnt);
+        dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out);
+        dfree(g_lab); dfree(g_out); dfree(g_node); dfree(g_out_node); dfree(g_n);
+        dfree(g_count); dfree(g_dead);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        ev0 = ev1 = nullptr;
+    }
+};
+
+static int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
+    int r;
+    w->n = n;
+    w->nblocks = nblocks;
+    if ((r = dalloc(&w->pool_top, 1))) return r;
+    if ((r = dalloc(&w->nb, n))) return r;
+    if ((r = dalloc(&w->minopen, n))) return r;
+    if ((r = dalloc(&w->gcnt, n))) return r;
+    if ((r = dalloc(&w->fo, n))) return r;
+    if ((r = dalloc(&w->mark, n))) return r;
+    if ((r = dalloc(&w->alist, n))) return r;
+    if ((r = dalloc(&w->acnt, 2))) return r;
+    if ((r = dalloc(&w->part_cnt, 2 * (size_t)nblocks))) return r;
+    if ((r = dalloc(&w->part_open, 2 * (size_t)nblocks))) return r;
+    if ((r = dalloc(&w->part_min, 2 * (size_t)nblocks))) return r;
+    if ((r = dalloc(&w->bar, 1))) return r;
+    if ((r = dalloc(&w->err, 1))) return r;
+    if ((r = dalloc(&w->out, kOutWords))) return r;
+    if ((r = dalloc(&w->g_n, 1))) return r;
+    if ((r = dalloc(&w->g_count, 1))) return r;
+    HIP_TRY(hipEventCreate(&w->ev0));
+    HIP_TRY(hipEventCreate(&w->ev1));
+    return MPAP_OK;
+}
+
+static int ws_grow(Workspace *w, unsigned long long pool_cap, long long arena_cap,
+                   long long F_cap, int goal_cap) {
+    int r;
+    if (pool_cap > w->pool_cap) {
+        dfree(w->pool);
+        if ((r = dalloc(&w->pool, pool_cap))) return r;
+        w->pool_cap = pool_cap;
+    }
+    if (arena_cap > w->arena_cap) {
+        dfree(w->arena);
+        if ((r = dalloc(&w->arena, arena_cap))) return r;
+        w->arena_cap = arena_cap;
+    }
+    if (F_cap > w->F_cap) {
+        dfree(w->F);
+        if ((r = dalloc(&w->F, F_cap))) return r;
+        w->F_cap = F_cap;
+    }
+    if (goal_cap > w->goal_cap) {
+        dfree(w->g_lab); dfree(w->g_out); dfree(w->g_node); dfree(w->g_out_node);
+        dfree(w->g_dead);
+        if ((r = dalloc(&w->g_lab, goal_cap))) return r;
+        if ((r = dalloc(&w->g_out, goal_cap))) return r;
+        if ((r = dalloc(&w->g_node, goal_cap))) return r;
+        if ((r = dalloc(&w->g_out_node, goal_cap))) return r;
+        if ((r = dalloc(&w->g_dead, goal_cap))) return r;
+        w->goal_cap = goal_cap;
+    }
+    return MPAP_OK;
+}
+
+// ------------------------------------------------------------------ result
+struct mpap_result {
+    mpap_graph *g = nullptr;
+    Workspace *ws = nullptr;
+    int n_obj = 2;
+    std::vector<float4> front;
+    std::vector<int32_t> front_node;
+    mpap_stats stats{};
+    std::vector<int2> arena_host;  // filled on first mpap_label_path
+    bool arena_loaded = false;
+};
+
+extern "C" {
+
+const char *mpap_status_string(int status) {
+    switch (status) {
+        case MPAP_OK: return "ok";
+        case MPAP_ERR_INVAL: return "invalid argument";
+        case MPAP_ERR_NOGOAL: return "no roadmap node in the goal region";
+        case MPAP_ERR_NOMEM: return "out of memory";
+        case MPAP_ERR_HIP: return "HIP runtime error";
+        case MPAP_ERR_OVERFLOW: return "capacity overflow";
+        case MPAP_ERR_NOCONVERGE: return "wave limit reached";
+        case MPAP_ERR_CAPACITY: return "caller buffer too small";
+        case MPAP_ERR_DEVICE: return "unsupported device";
+        default: return "unknown status";
+    }
+}
+
+const char *mpap_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------ graph import
+int mpap_graph_from_csr(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                        const float *cost, const float *drift, const uint8_t *reset,
+                        const uint8_t *goal, void *stream, mpap_graph **out) {
+    if (!out) return fail(MPAP_ERR_INVAL, "out is null");
+    *out = nullptr;
+    if (n < 1 || !row_ptr || !reset || !goal) return fail(MPAP_ERR_INVAL, "null input or n < 1");
+    if (row_ptr[0] != 0) return fail(MPAP_ERR_INVAL, "row_ptr[0] != 0");
+    for (int32_t u = 0; u < n; ++u)
+        if (row_ptr[u + 1] < row_ptr[u]) return fail(MPAP_ERR_INVAL, "row_ptr decreases");
+    const int64_t e = row_ptr[n];
+    if (e > 0 && (!col || !cost || !drift)) return fail(MPAP_ERR_INVAL, "null edge array");
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
+            if (col[k] < 0 || col[k] >= n) return fail(MPAP_ERR_INVAL, "col out of range");
+            if (col[k] == u) return fail(MPAP_ERR_INVAL, "self loop");
+            if (!(cost[k] > 0.0f) || !std::isfinite(cost[k]))
+                return fail(MPAP_ERR_INVAL, "edge cost must be finite and > 0");
+            if (!(drift[k] >= 0.0f) || !std::isfinite(drift[k]))
+                return fail(MPAP_ERR_INVAL, "edge drift must be finite and >= 0");
+        }
+    DeviceInfo di;
+    int r = device_info(&di);
+    if (r) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    // in-edge CSR: stable counting sort of the edges by target
+    std::vector<int32_t> rptr(n + 1, 0), rsrc(e);
+    std::vector<float> rcost(e), rdrift(e);
+    for (int64_t k = 0; k < e; ++k) rptr[col[k] + 1]++;
+    for (int32_t v = 0; v < n; ++v) rptr[v + 1] += rptr[v];
+    {
+        std::vector<int32_t> fill(rptr.begin(), rptr.end() - 1);
+        for (int32_t u = 0; u < n; ++u)
+            for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
+                const int32_t p = fill[col[k]]++;
+                rsrc[p] = u;
+                rcost[p] = cost[k];
+                rdrift[p] = drift[k];
+            }
+    }
+    std::vector<uint8_t> flag(n);
+    std::vector<int32_t> glist;
+    for (int32_t v = 0; v < n; ++v) {
+        flag[v] = (uint8_t)((reset[v] ? 1u : 0u) | (goal[v] ? 2u : 0u));
+        if (goal[v]) glist.push_back(v);
+    }
+    mpap_graph *g = new mpap_graph();
+    g->dev = di.dev;
+    g->n = n;
+    g->e = e;
+    g->n_goal = (int32_t)glist.size();
+    auto bail = [&](int st) { graph_release(g); return st; };
+    if ((r = dalloc(&g->optr, n + 1)) || (r = dalloc(&g->ocol, e)) ||
+        (r = dalloc(&g->ocost, e)) || (r = dalloc(&g->odrift, e)) ||
+        (r = dalloc(&g->rptr, n + 1)) || (r = dalloc(&g->rsrc, e)) ||
+        (r = dalloc(&g->rcost, e)) || (r = dalloc(&g->rdrift, e)) ||
+        (r = dalloc(&g->nflag, n)) || (r = dalloc(&g->goal_list, glist.size())))
+        return bail(r);
+    hipError_t he = hipSuccess;
+    auto cp = [&](void *d, const void *h, size_t bytes) {
+        if (he == hipSuccess && bytes) he = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s);
+    };
+    cp(g->optr, row_ptr, sizeof(int32_t) * (n + 1));
+    cp(g->ocol, col, sizeof(int32_t) * e);
+    cp(g->ocost, cost, sizeof(float) * e);
+    cp(g->odrift, drift, sizeof(float) * e);
+    cp(g->rptr, rptr.data(), sizeof(int32_t) * (n + 1));
+    cp(g->rsrc, rsrc.data(), sizeof(int32_t) * e);
+    cp(g->rcost, rcost.data(), sizeof(float) * e);
+    cp(g->rdrift, rdrift.data(), sizeof(float) * e);
+    cp(g->nflag, flag.data(), n);
+    cp(g->goal_list, glist.data(), sizeof(int32_t) * glist.size());
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) {
+        graph_release(g);
+        return fail(MPAP_ERR_HIP, std::string("graph upload: ") + hipGetErrorString(he));
+    }
+    *out = g;
+    return MPAP_OK;
+}
+
+// ------------------------------------------------------------- graph build
+int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *stream,
+                     mpap_graph **out) {
+    if (!out) return fail(MPAP_ERR_INVAL, "out is null");
+    *out = nullptr;
+    if (!env || !gp || !env->pos) return fail(MPAP_ERR_INVAL, "null env, params or positions");
+    const int dim = env->dim, n = env->n_nodes;
+    if ((dim != 2 && dim != 3) || n < 1) return fail(MPAP_ERR_INVAL, "dim must be 2 or 3, n >= 1");
+    if (!(gp->radius > 0.0f) || !(gp->check_step > 0.0f) || !std::isfinite(gp->radius))
+        return fail(MPAP_ERR_INVAL, "radius and check_step must be > 0");
+    if (env->n_boxes < 0 || env->n_blobs < 0 ||
+        (env->n_boxes > 0 && (!env->box_lo || !env->box_hi)) ||
+        (env->n_blobs > 0 && (!env->blob_mu || !env->blob_sigma || !env->blob_amp)))
+        return fail(MPAP_ERR_INVAL, "null obstacle or blob arrays");
+    for (long long i = 0; i < (long long)n * dim; ++i)
+        if (!std::isfinite(env->pos[i])) return fail(MPAP_ERR_INVAL, "non-finite position");
+    for (int j = 0; j < env->n_blobs; ++j)
+        if (!(env->blob_sigma[j] > 0.0f)) return fail(MPAP_ERR_INVAL, "blob sigma must be > 0");
+    DeviceInfo di;
+    int r = device_info(&di);
+    if (r) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    float *d_pos = nullptr, *d_blo = nullptr, *d_bhi = nullptr, *d_mu = nullptr,
+          *d_sig = nullptr, *d_amp = nullptr, *cand_c = nullptr;
+    int *cnt = nullptr, *coff = nullptr, *cand_u = nullptr, *cand_v = nullptr, *keep = nullptr,
+        *kscan = nullptr, *tmp = nullptr, *ngoal = nullptr;
+    mpap_graph *g = nullptr;
+    auto cleanup = [&]() {
+        dfree(d_pos); dfree(d_blo); dfree(d_bhi); dfree(d_mu); dfree(d_sig); dfree(d_amp);
+        dfree(cand_c); dfree(cnt); dfree(coff); dfree(cand_u); dfree(cand_v); dfree(keep);
+        dfree(kscan); dfree(tmp); dfree(ngoal);
+    };
+    auto bail = [&](int st) {
+        cleanup();
+        if (g) graph_release(g);
+        return st;
+    };
+    const size_t nb_ = (size_t)env->n_boxes * dim, nf_ = (size_t)env->n_blobs;
+    if ((r = dalloc(&d_pos, (size_t)n * dim)) || (r = dalloc(&d_blo, nb_)) ||
+        (r = dalloc(&d_bhi, nb_)) || (r = dalloc(&d_mu, nf_ * dim)) ||
+        (r = dalloc(&d_sig, nf_)) || (r = dalloc(&d_amp, nf_)) || (r = dalloc(&cnt, n)) ||
+        (r = dalloc(&coff, n)) || (r = dalloc(&tmp, div_up(std::max(n, 1), kScanTile) + 1)) ||
+        (r = dalloc(&ngoal, 1)))
+        return bail(r);
+    hipError_t he = hipSuccess;
+    auto cp = [&](void *d, const void *h, size_t bytes) {
+        if (he == hipSuccess && bytes) he = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s);
+    };
+    cp(d_pos, env->pos, sizeof(float) * n * dim);
+    cp(d_blo, env->box_lo, sizeof(float) * nb_);
+    cp(d_bhi, env->box_hi, sizeof(float) * nb_);
+    cp(d_mu, env->blob_mu, sizeof(float) * nf_ * dim);
+    cp(d_sig, env->blob_sigma, sizeof(float) * nf_);
+    cp(d_amp, env->blob_amp, sizeof(float) * nf_);
+    if (he != hipSuccess) return bail(fail(MPAP_ERR_HIP, hipGetErrorString(he)));
+
+    BuildArgs a{};
+    a.n = n; a.dim = dim; a.pos = d_pos; a.nbox = env->n_boxes; a.blo = d_blo; a.bhi = d_bhi;
+    a.nblob = env->n_blobs; a.mu = d_mu; a.sig = d_sig; a.amp = d_amp;
+    a.r = gp->radius; a.step = gp->check_step; a.reset_q = gp->reset_q;
+    a.goal[0] = env->goal[0]; a.goal[1] = env->goal[1]; a.goal[2] = env->goal[2];
+    a.goal_r = env->goal_radius;
+
+    const int nblk = div_up(n, 256);
+    k_near_count<<<nblk, 256, 0, s>>>(a, cnt);
+    if ((r = scan_i32(cnt, coff, n, tmp, s))) return bail(r);
+    int last_cnt = 0, last_off = 0;
+    HIP_TRY(hipMemcpyAsync(&last_cnt, cnt + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&last_off, coff + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const long long m = (long long)last_cnt + last_off;
+    if ((r = dalloc(&cand_u, m)) || (r = dalloc(&cand_v, m)) || (r = dalloc(&cand_c, m)) ||
+        (r = dalloc(&keep, m)) || (r = dalloc(&kscan, m)))
+        return bail(r);
+    dfree(tmp);
+    if ((r = dalloc(&tmp, div_up(std::max(m, 1LL), kScanTile) + 1))) return bail(r);
+    k_near_fill<<<nblk, 256, 0, s>>>(a, coff, cand_u, cand_v, cand_c);
+    if (m > 0) {
+        const size_t lds = sizeof(float) * 2 * nb_;
+        k_collide<<<div_up(m, 256), 256, lds, s>>>(a, m, cand_u, cand_v, cand_c, keep);
+        if ((r = scan_i32(keep, kscan, m, tmp, s))) return bail(r);
+    }
+    int last_keep = 0, last_ks = 0;
+    if (m > 0) {
+        HIP_TRY(hipMemcpyAsync(&last_keep, keep + (m - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&last_ks, kscan + (m - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    const long long e = (long long)last_keep + last_ks;
+
+    g = new mpap_graph();
+    g->dev = di.dev;
+    g->n = n;
+    g->e = e;
+    g->symmetric_alias = true;
+    if ((r = dalloc(&g->optr, n + 1)) || (r = dalloc(&g->ocol, e)) ||
+        (r = dalloc(&g->ocost, e)) || (r = dalloc(&g->odrift, e)) ||
+        (r = dalloc(&g->nflag, n)) || (r = dalloc(&g->goal_list, n)))
+        return bail(r);
+    if (m > 0)
+        k_compact_edges<<<div_up(m, 256), 256, 0, s>>>(m, keep, kscan, cand_v, cand_c, g->ocol,
+                                                       g->ocost);
+    k_row_ptr<<<div_up(n + 1, 256), 256, 0, s>>>(n, m, coff, kscan, keep, g->optr);
+    {
+        const size_t lds = sizeof(float) * (nf_ * dim + 2 * nf_);
+        if (n > 0) k_edge_drift<<<n, 64, lds, s>>>(a, n, g->optr, g->ocol, g->ocost, g->odrift);
+    }
+    k_node_flags<<<nblk, 256, 0, s>>>(a, g->nflag);
+    k_flag_list<<<1, 1024, 0, s>>>(n, g->nflag, 2u, g->goal_list, ngoal);
+    HIP_TRY(hipGetLastError());
+    int hg = 0;
+    HIP_TRY(hipMemcpyAsync(&hg, ngoal, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g->n_goal = hg;
+    // the roadmap is symmetric (same cost, drift and collision result both
+    // ways), so the in-edge lists are the out-edge lists
+    g->rptr = g->optr; g->rsrc = g->ocol; g->rcost = g->ocost; g->rdrift = g->odrift;
+    cleanup();
+    if (hg == 0) {
+        graph_release(g);
+        return fail(MPAP_ERR_NOGOAL, "no roadmap node lies in the goal ball");
+    }
+    *out = g;
+    return MPAP_OK;
+}
+
+int mpap_graph_info(const mpap_graph *g, int32_t *n, int64_t *e, int32_t *n_goal) {
+    if (!g) return fail(MPAP_ERR_INVAL, "graph is null");
+    if (n) *n = g->n;
+    if (e) *e = g->e;
+    if (n_goal) *n_goal = g->n_goal;
+    return MPAP_OK;
+}
+
+int mpap_graph_export(const mpap_graph *g, int32_t *row_ptr, int32_t *col, float *cost,
+                      float *drift, uint8_t *reset, uint8_t *goal) {
+    if (!g || !row_ptr || !reset || !goal || (g->e > 0 && (!col || !cost || !drift)))
+        return fail(MPAP_ERR_INVAL, "null argument");
+    HIP_TRY(hipMemcpy(row_ptr, g->optr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost));
+    if (g->e > 0) {
+        HIP_TRY(hipMemcpy(col, g->ocol, sizeof(int32_t) * g->e, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(cost, g->ocost, sizeof(float) * g->e, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(drift, g->odrift, sizeof(float) * g->e, hipMemcpyDeviceToHost));
+    }
+    std::vector<uint8_t> f(g->n);
+    HIP_TRY(hipMemcpy(f.data(), g->nflag, g->n, hipMemcpyDeviceToHost));
+    for (int32_t v = 0; v < g->n; ++v) {
+        reset[v] = f[v] & 1u;
+        goal[v] = (f[v] >> 1) & 1u;
+    }
+    return MPAP_OK;
+}
+
+void mpap_graph_free(mpap_graph *g) {
+    if (g) graph_release(g);
+}
+
+// ----------------------------------------------------------------- search
+int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream,
+                mpap_result **out) {
+    if (!out) return fail(MPAP_ERR_INVAL, "out is null");
+    *out = nullptr;
+    if (!gc || !sp) return fail(MPAP_ERR_INVAL, "null graph or params");
+    mpap_graph *g = const_cast<mpap_graph *>(gc);
+    if (sp->n_obj != 2 && sp->n_obj != 3) return fail(MPAP_ERR_INVAL, "n_obj must be 2 or 3");
+    if (sp->init_node < 0 || sp->init_node >= g->n) return fail(MPAP_ERR_INVAL, "init_node out of range");
+    if (!(sp->lambda > 0.0f) || !(sp->radius > 0.0f) || std::isnan(sp->beta))
+        return fail(MPAP_ERR_INVAL, "lambda and radius must be > 0, beta not NaN");
+    const float delta = sp->lambda * sp->radius;
+    if (!(delta > 0.0f) || !std::isfinite(delta))
+        return fail(MPAP_ERR_INVAL, "lambda * radius must be finite and > 0");
+    DeviceInfo di;
+    int r = device_info(&di);
+    if (r) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    // launch shape: 256-thread blocks, LDS staging sized from the device limit
+    const int threads = 256;
+    const int capC = 1024;
+    const size_t fixed = 16 * (size_t)capC + 16 * (size_t)threads + 128 + 32 + capC;
+    // leave 1 KiB for the kernel's static LDS
+    size_t lds_budget = std::min<size_t>(di.max_lds, 160 * 1024) - 1024;
+    int capB = (int)((lds_budget - fixed) / 17);
+    capB = std::min(capB, 1 << 16);
+    capB -= capB % 64;
+    if (capB < 256) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
+    const size_t lds = fixed + 17 * (size_t)capB;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search, threads, lds));
+    if (per_cu < 1) return fail(MPAP_ERR_DEVICE, "search kernel does not fit on a CU");
+    int nblocks = di.cus * std::min(per_cu, 2);
+
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (!g->spare.empty()) {
+            w = g->spare.back();
+            g->spare.pop_back();
+        }
+    }
+    if (w && w->nblocks != nblocks) {
+        w->free_all();
+        delete w;
+        w = nullptr;
+    }
+    if (!w) {
+        w = new Workspace();
+        if ((r = ws_alloc_nodes(w, g->n, nblocks))) {
+            w->free_all();
+            delete w;
+            return r;
+        }
+    }
+    mpap_result *res = new mpap_result();
+    res->g = g;
+    res->ws = w;
+    res->n_obj = sp->n_obj;
+    auto bail = [&](int st) {
+        mpap_result_free(res);
+        return st;
+    };
+
+    unsigned long long pool_cap = std::max<unsigned long long>(w->pool_cap, 64ull * g->n + 4096);
+    long long arena_cap = std::max<long long>(w->arena_cap, 16ll * g->n + 4096);
+    long long F_cap = std::max<long long>(w->F_cap, 4ll * g->n + 4096);
+    const int max_waves = sp->max_waves > 0 ? sp->max_waves : (1 << 18);
+    long long dev_out[kOutWords];
+    int dev_err = 0;
+    int retries = 0;
+    float ms = 0.f;
+    for (;;) {
+        if ((r = ws_grow(w, pool_cap, arena_cap, F_cap, 0))) return bail(r);
+        SearchArgs a{};
+        a.n = g->n; a.rptr = g->rptr; a.rsrc = g->rsrc; a.rcost = g->rcost;
+        a.rdrift = g->rdrift; a.optr = g->optr; a.ocol = g->ocol; a.nflag = g->nflag;
+        a.beta = sp->beta; a.delta = delta; a.nobj = sp->n_obj; a.root = sp->init_node;
+        a.max_waves = max_waves; a.capB = capB; a.capC = capC; a.nblocks = nblocks;
+        a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
+        a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
+        a.alist = w->alist; a.acnt = w->acnt; a.F = w->F; a.F_cap = w->F_cap;
+        a.arena = w->arena; a.arena_cap = std::min<long long>(w->arena_cap, 0x7ffffff0ll);
+        a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_min = w->part_min;
+        a.bar = w->bar; a.err = w->err; a.out = w->out;
+
+        k_search_init<<<div_up(g->n, 256), 256, 0, s>>>(a);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(w->ev0, s));
+        void *kargs[] = {&a};
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search),
+                                           dim3(nblocks), dim3(threads), kargs, lds, s));
+        HIP_TRY(hipEventRecord(w->ev1, s));
+        k_count_front<<<std::max(1, std::min(div_up(g->n, 256), 1024)), 256, 0, s>>>(a);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(dev_out, w->out, sizeof(dev_out), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&dev_err, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+        const int status = (int)dev_out[kOutStatus];
+        if (status == kStatusOk && dev_err == 0) break;
+        if (dev_err & kErrTimeout)
+            return bail(fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)"));
+        if (status == kStatusNoConverge)
+            return bail(fail(MPAP_ERR_NOCONVERGE, "max_waves reached with open plans"));
+        if (dev_err & kErrBucket)
+            return bail(fail(MPAP_ERR_OVERFLOW, "a per-node front exceeds the LDS staging capacity (" +
+                                                    std::to_string(capB) + " labels)"));
+        if (++retries > 8) return bail(fail(MPAP_ERR_OVERFLOW, "capacity retries exhausted"));
+        if (dev_err & kErrPool) pool_cap *= 2;
+        if (status == kStatusArena) {
+            arena_cap *= 2;
+            F_cap *= 2;
+        }
+        if (pool_cap > (1ull << 31) - 1)
+            return bail(fail(MPAP_ERR_OVERFLOW, "bucket pool beyond 2^31 labels"));
+    }
+
+    // goal front (a7)
+    {
+        // every goal front holds at most capB labels
+        const long long gl = (long long)g->n_goal * capB;
+        int goal_cap = (int)std::max<long long>(gl, 1);
+        if ((r = ws_grow(w, 0, 0, 0, goal_cap))) return bail(r);
+        int count = 0;
+        if (gl > 0) {
+            GoalArgs ga{};
+            ga.n_goal = g->n_goal; ga.goal_list = g->goal_list; ga.nb = w->nb; ga.pool = w->pool;
+            ga.lab = w->g_lab; ga.lab_node = w->g_node; ga.dead = w->g_dead; ga.cap = goal_cap;
+            ga.n_lab = w->g_n; ga.out_lab = w->g_out; ga.out_node = w->g_out_node;
+            ga.out_count = w->g_count;
+            k_goal_gather<<<1, 1024, 0, s>>>(ga);
+            const int gb = std::max(1, std::min(div_up(dev_out[kOutFront], 256), 1024));
+            k_goal_dominance<<<gb, 256, 0, s>>>(ga);
+            k_goal_emit<<<gb, 256, 0, s>>>(ga);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(&count, w->g_count, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            res->front.resize(count);
+            res->front_node.resize(count);
+            if (count > 0) {
+                HIP_TRY(hipMemcpyAsync(res->front.data(), w->g_out, sizeof(float4) * count,
+                                       hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(res->front_node.data(), w->g_out_node,
+                                       sizeof(int32_t) * count, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+            }
+        }
+    }
+    res->stats.waves = (int32_t)dev_out[kOutWaves];
+    res->stats.retries = retries;
+    res->stats.labels_expanded = dev_out[kOutLabels];
+    res->stats.front_labels = dev_out[kOutFront];
+    res->stats.merges = dev_out[kOutMerges];
+    res->stats.candidates = dev_out[kOutCandidates];
+    res->stats.gpu_ms = ms;
+    *out = res;
+    return MPAP_OK;
+}
+
+int mpap_goal_front(const mpap_result *r, float *cost, float *drift, float *maxdrift,
+                    int32_t *goal_node, int32_t *label_id, int32_t capacity, int32_t *count) {
+    if (!r || !count) return fail(MPAP_ERR_INVAL, "null result or count");
+    const int32_t k = (int32_t)r->front.size();
+    *count = k;
+    if (capacity < k) return fail(MPAP_ERR_CAPACITY, "capacity below the front size");
+    for (int32_t i = 0; i < k; ++i) {
+        const float4 L = r->front[i];
+        if (cost) cost[i] = L.x;
+        if (drift) drift[i] = L.y;
+        if (maxdrift) maxdrift[i] = L.z;
+        if (goal_node) goal_node[i] = r->front_node[i];
+        if (label_id) {
+            int id;
+            std::memcpy(&id, &L.w, sizeof(int));
+            label_id[i] = id;
+        }
+    }
+    return MPAP_OK;
+}
+
+int mpap_node_front(const mpap_result *r, int32_t node, float *cost, float *drift,
+                    float *maxdrift, int32_t *label_id, int32_t capacity, int32_t *count) {
+    if (!r || !count) return fail(MPAP_ERR_INVAL, "null result or count");
+    if (node < 0 || node >= r->g->n) return fail(MPAP_ERR_INVAL, "node out of range");
+    int4 nbv;
+    HIP_TRY(hipMemcpy(&nbv, r->ws->nb + node, sizeof(int4), hipMemcpyDeviceToHost));
+    *count = nbv.z;
+    if (capacity < nbv.z) return fail(MPAP_ERR_CAPACITY, "capacity below the front size");
+    std::vector<float4> L(nbv.z);
+    if (nbv.z > 0)
+        HIP_TRY(hipMemcpy(L.data(), r->ws->pool + (unsigned)nbv.x, sizeof(float4) * nbv.z,
+                          hipMemcpyDeviceToHost));
+    for (int i = 0; i < nbv.z; ++i) {
+        if (cost) cost[i] = L[i].x;
+        if (drift) drift[i] = L[i].y;
+        if (maxdrift) maxdrift[i] = L[i].z;
+        if (label_id) std::memcpy(&label_id[i], &L[i].w, sizeof(int32_t));
+    }
+    return MPAP_OK;
+}
+
+int mpap_label_path(const mpap_result *rc, int32_t label_id, int32_t *nodes, int32_t capacity,
+                    int32_t *length) {
+    mpap_result *r = const_cast<mpap_result *>(rc);
+    if (!r || !length) return fail(MPAP_ERR_INVAL, "null result or length");
+    const long long L = r->stats.labels_expanded;
+    if (label_id < 0 || label_id >= L) return fail(MPAP_ERR_INVAL, "label id out of range");
+    if (!r->arena_loaded) {
+        r->arena_host.resize(L);
+        HIP_TRY(hipMemcpy(r->arena_host.data(), r->ws->arena, sizeof(int2) * L,
+                          hipMemcpyDeviceToHost));
+        r->arena_loaded = true;
+    }
+    int32_t len = 0;
+    for (long long a = label_id; a >= 0; a = r->arena_host[a].y) {
+        if (++len > L) return fail(MPAP_ERR_HIP, "parent chain does not end");
+    }
+    *length = len;
+    if (capacity < len) return fail(MPAP_ERR_CAPACITY, "capacity below the path length");
+    int32_t i = len - 1;
+    for (long long a = label_id; a >= 0; a = r->arena_host[a].y) nodes[i--] = r->arena_host[a].x;
+    return MPAP_OK;
+}
+
+int mpap_result_stats(const mpap_result *r, mpap_stats *out) {
+    if (!r || !out) return fail(MPAP_ERR_INVAL, "null argument");
+    *out = r->stats;
+    return MPAP_OK;
+}
+
+void mpap_result_free(mpap_result *r) {
+    if (!r) return;
+    if (r->ws && r->g) {
+        std::lock_guard<std::mutex> lk(r->g->mu);
+        r->g->spare.push_back(r->ws);
+    } else if (r->ws) {
+        r->ws->free_all();
+        delete r->ws;
+    }
+    delete r;
+}
+
+}  // extern "C"
+
+static void graph_release(mpap_graph *g) {
+    for (Workspace *w : g->spare) {
+        w->free_all();
+        delete w;
+    }
+    g->spare.clear();
+    if (!g->symmetric_alias) {
+        dfree(g->rptr); dfree(g->rsrc); dfree(g->rcost); dfree(g->rdrift);
+    }
+    dfree(g->optr); dfree(g->ocol); dfree(g->ocost); dfree(g->odrift);
+    dfree(g->nflag); dfree(g->goal_list);
+    delete g;
+}

@@ -1,0 +1,539 @@
+// Wavefront multiobjective label search (Sec. 3, Alg. 3 Explore) for gfx950.
+//
+// One cooperative persistent launch runs every Explore iteration.  Each
+// iteration is three grid phases separated by grid barriers:
+//
+//   P1 count  : per node, the open labels whose cost is within the group
+//               threshold (the group G of Alg. 3), plus open totals and the
+//               least open cost (to skip empty thresholds).
+//   P2 select : a device-wide scan of the group counts gives every group label
+//               a frontier slot and an arena id (ids are dense and follow node
+//               order, so runs are deterministic); the label is closed
+//               (P_open <- P_open \ G), its (node, parent) goes to the arena and
+//               the out-neighbours of its node are queued as merge targets.
+//   P3 merge  : one workgroup per target node x pulls every group label at an
+//               in-neighbour along its in-edge (cost, drift, bound, relocal-
+//               isation: the child line and cutoff of Alg. 3), and merges the
+//               children into P(x) with weak-Pareto RemoveDominated, staged in
+//               LDS.  Each node has exactly one writer per iteration, so the
+//               merge needs no atomics.
+//
+// Labels live in per-node buckets carved out of one pool (grown by doubling
+// into a fresh region when a front outgrows its capacity).  The loop ends when
+// no label is open.
+#include "device_common.h"
+#include "search_kernels.h"
+
+namespace {
+
+constexpr unsigned long long kSpinLimit = 1ull << 22;
+
+__device__ __forceinline__ unsigned wave_par(int w) { return (unsigned)w & 1u; }
+
+// ------------------------------------------------------------------ P1
+__device__ void phase_count(const SearchArgs &a, float T, int par, int lo, int hi,
+                            long long *red_ll, float *red_f) {
+    const int l = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    long long grp = 0, open_nodes = 0;
+    float mn = MPAP_INF;
+    for (int base = lo + w * 64; base < hi; base += nw * 64) {
+        const int v = base + l;
+        float mo = MPAP_INF;
+        bool need = false;
+        if (v < hi) {
+            mo = a.minopen[v];
+            need = mo <= T;
+            if (!need) a.gcnt[v] = 0;
+            if (mo < MPAP_INF) open_nodes += 1;
+        }
+        mn = fminf(mn, mo);
+        uint64_t m = ballot64(need);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int vv = base + src;
+            const int4 nbv = a.nb[vv];
+            int cnt = 0;
+            for (int k = l; k < nbv.z; k += 64) {
+                const float4 L = a.pool[(size_t)(unsigned)nbv.x + k];
+                cnt += (lab_open(L) && L.x <= T) ? 1 : 0;
+            }
+            cnt = wave_sum(cnt);
+            if (l == 0) a.gcnt[vv] = cnt;
+            if (l == src) grp += cnt;
+        }
+    }
+    long long g = block_sum_ll(grp, red_ll);
+    long long o = block_sum_ll(open_nodes, red_ll);
+    float bm = block_min(mn, red_f);
+    if (threadIdx.x == 0) {
+        a.part_cnt[par * a.nblocks + blockIdx.x] = g;
+        a.part_open[par * a.nblocks + blockIdx.x] = o;
+        a.part_min[par * a.nblocks + blockIdx.x] = bm;
+    }
+}
+
+// ------------------------------------------------------------------ P2
+__device__ void phase_select(const SearchArgs &a, float T, int wave, long long abase,
+                             long long myoff, int lo, int hi, int *s_scan, int *s_goff) {
+    const int l = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const unsigned wp = wave_par(wave);
+    long long carry = myoff;
+    for (int tb = lo; tb < hi; tb += blockDim.x) {
+        const int v = tb + threadIdx.x;
+        const int g = (v < hi) ? a.gcnt[v] : 0;
+        int tot;
+        const int ex = block_excl_scan(g, s_scan, &tot);
+        s_goff[threadIdx.x] = (int)(carry + ex);  // frontier offsets fit in int32
+        __syncthreads();
+        // each wave handles the flagged nodes of its own 64-node slice
+        const int vs = tb + w * 64 + l;
+        const bool flag = (vs < hi) && g > 0;
+        uint64_t m = ballot64(flag);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int vv = tb + w * 64 + src;
+            const int goff = s_goff[w * 64 + src];
+            const int4 nbv = a.nb[vv];
+            int run = 0;
+            float rmin = MPAP_INF;
+            for (int k0 = 0; k0 < nbv.z; k0 += 64) {
+                const int k = k0 + l;
+                bool in = false;
+                float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
+                const size_t slot = (size_t)(unsigned)nbv.x + k;
+                if (k < nbv.z) {
+                    L = a.pool[slot];
+                    const bool op = lab_open(L);
+                    in = op && L.x <= T;
+                    if (op && !in) rmin = fminf(rmin, L.x);
+                }
+                const uint64_t bm = ballot64(in);
+                if (in) {
+                    const int pos = goff + run + lanes_below(bm);
+                    const long long id = abase + pos;
+                    a.F[pos] = make_float4(L.x, L.y, L.z, __int_as_float((int)id));
+                    a.arena[id] = make_int2(vv, lab_parent(L));
+                    reinterpret_cast<int *>(&a.pool[slot])[3] = (int)id;
+                }
+                run += (int)__popcll(bm);
+            }
+            rmin = wave_min(rmin);
+            if (l == 0) {
+                a.minopen[vv] = rmin;
+                a.fo[vv] = make_int4(goff, run, wave, 0);
+            }
+            // queue out-neighbours as merge targets of this wave
+            for (int e = a.optr[vv] + l; e < a.optr[vv + 1]; e += 64) {
+                const int x = a.ocol[e];
+                if (atomicExch(&a.mark[x], wave) != wave) {
+                    const int s = atomicAdd(&a.acnt[wp], 1);
+                    a.alist[s] = x;
+                }
+            }
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    (void)nw;
+}
+
+// ------------------------------------------------------------------ P3
+struct MergeLds {
+    float4 *B;      // [capB] bucket being built
+    float4 *C;      // [capC] candidate chunk
+    uint8_t *bdead; // [capB]
+    uint8_t *cdead; // [capC]
+    int *e_off;     // [blockDim] frontier offset of the in-neighbour
+    int *e_pre;     // [blockDim] inclusive prefix of candidate counts
+    float *e_c;     // [blockDim] edge cost
+    float *e_d;     // [blockDim] edge drift
+    int *scan;      // [blockDim/64 + 1]
+    int *misc;      // [8]
+};
+
+// compact the flagged-alive entries of arr[0..n) to the front, stable.
+// Returns the new count.  Entries only move to lower indices and each tile is
+// read before it is written.
+__device__ int compact_alive(float4 *arr, const uint8_t *dead, int n, int *scan) {
+    int out = 0;
+    for (int t0 = 0; t0 < n; t0 += blockDim.x) {
+        const int i = t0 + threadIdx.x;
+        const bool alive = i < n && !dead[i];
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (alive) v = arr[i];
+        int tot;
+        const int ex = block_excl_scan(alive ? 1 : 0, scan, &tot);
+        if (alive) arr[out + ex] = v;
+        out += tot;
+        __syncthreads();
+    }
+    return out;
+}
+
+__device__ void merge_chunk(const MergeLds &s, int &nB, int nC, int capB, int *err) {
+    // (a) candidates: dead if a bucket label or another candidate is <= it
+    //     (equal candidates: the first one is kept)
+    for (int i = threadIdx.x; i < nC; i += blockDim.x) {
+        const float4 ci = s.C[i];
+        bool dead = false;
+        for (int j = 0; j < nB && !dead; ++j) dead = lab_le(s.B[j], ci);
+        for (int k = 0; k < nC && !dead; ++k) {
+            if (k == i) continue;
+            const float4 ck = s.C[k];
+            dead = lab_le(ck, ci) && (k < i || !lab_eq(ck, ci));
+        }
+        s.cdead[i] = dead ? 1 : 0;
+    }
+    __syncthreads();
+    // (b) bucket labels strictly dominated by a surviving candidate leave
+    for (int j = threadIdx.x; j < nB; j += blockDim.x) {
+        const float4 bj = s.B[j];
+        bool dead = false;
+        for (int i = 0; i < nC && !dead; ++i) dead = !s.cdead[i] && lab_le(s.C[i], bj);
+        s.bdead[j] = dead ? 1 : 0;
+    }
+    __syncthreads();
+    const int nBs = compact_alive(s.B, s.bdead, nB, s.scan);
+    const int nCs = compact_alive(s.C, s.cdead, nC, s.scan);
+    if (nBs + nCs > capB) {
+        if (threadIdx.x == 0) atomicOr(err, kErrBucket);
+        nB = nBs;  // drop the chunk; the search reports overflow
+        __syncthreads();
+        return;
+    }
+    for (int i = threadIdx.x; i < nCs; i += blockDim.x) s.B[nBs + i] = s.C[i];
+    nB = nBs + nCs;
+    __syncthreads();
+}
+
+__device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds &s,
+                           long long &st_cand) {
+    const int4 nbx = a.nb[x];
+    int nB = nbx.z;
+    if (nB > a.capB) {
+        if (threadIdx.x == 0) atomicOr(a.err, kErrBucket);
+        return;
+    }
+    for (int i = threadIdx.x; i < nB; i += blockDim.x)
+        s.B[i] = a.pool[(size_t)(unsigned)nbx.x + i];
+    __syncthreads();
+    const bool rst = (a.nflag[x] & 1u) != 0u;
+    const int e0 = a.rptr[x], e1 = a.rptr[x + 1];
+    const int per = a.capC / blockDim.x;  // candidates per thread per chunk
+    for (int t0 = e0; t0 < e1; t0 += blockDim.x) {
+        // in-edge tile: frontier label counts of each in-neighbour
+        const int e = t0 + threadIdx.x;
+        int cnt = 0, off = 0;
+        float ce = 0.f, de = 0.f;
+        if (e < e1) {
+            const int u = a.rsrc[e];
+            const int4 fu = a.fo[u];
+            if (fu.z == wave) {
+                cnt = fu.y;
+                off = fu.x;
+                ce = a.rcost[e];
+                de = a.rdrift[e];
+            }
+        }
+        int tot;
+        const int ex = block_excl_scan(cnt, s.scan, &tot);
+        s.e_off[threadIdx.x] = off;
+        s.e_pre[threadIdx.x] = ex + cnt;
+        s.e_c[threadIdx.x] = ce;
+        s.e_d[threadIdx.x] = de;
+        __syncthreads();
+        const int ntile = min((int)blockDim.x, e1 - t0);
+        for (int j0 = 0; j0 < tot; j0 += a.capC) {
+            // generate up to capC children of this tile, keep those within the bound
+            int nC = 0;
+            for (int r = 0; r < per; ++r) {
+                const int j = j0 + r * (int)blockDim.x + threadIdx.x;
+                bool ok = false;
+                float4 ch = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (j < tot && j < j0 + a.capC) {
+                    // edge t: first with inclusive prefix > j
+                    int lo2 = 0, hi2 = ntile - 1;
+                    while (lo2 < hi2) {
+                        const int mid = (lo2 + hi2) >> 1;
+                        if (s.e_pre[mid] > j) hi2 = mid; else lo2 = mid + 1;
+                    }
+                    const int t = lo2;
+                    const int k = j - (t > 0 ? s.e_pre[t - 1] : 0);
+                    const float4 P = a.F[s.e_off[t] + k];
+                    const float c2 = P.x + s.e_c[t];
+                    const float dpre = P.y + s.e_d[t];
+                    ok = dpre <= a.beta;
+                    const float d2 = rst ? 0.0f : dpre;
+                    const float m2 = (a.nobj >= 3) ? fmaxf(P.z, dpre) : 0.0f;
+                    const unsigned meta = MPAP_OPEN_BIT | (unsigned)(__float_as_int(P.w) + 1);
+                    ch = make_float4(c2, d2, m2, __uint_as_float(meta));
+                }
+                int t2;
+                const int ex2 = block_excl_scan(ok ? 1 : 0, s.scan, &t2);
+                if (ok) s.C[nC + ex2] = ch;
+                nC += t2;
+            }
+            __syncthreads();
+            st_cand += nC;
+            if (nC > 0) merge_chunk(s, nB, nC, a.capB, a.err);
+        }
+        __syncthreads();
+    }
+    // write the merged front back (fresh region if it outgrew the old one)
+    int off = nbx.x, cap = nbx.y;
+    if (nB > cap) {
+        if (threadIdx.x == 0) {
+            int nc = 16;
+            while (nc < nB) nc <<= 1;
+            const unsigned o = atomicAdd(a.pool_top, (unsigned)nc);
+            if ((unsigned long long)o + (unsigned)nc > a.pool_cap) {
+                atomicOr(a.err, kErrPool);
+                s.misc[0] = -1;
+            } else {
+                s.misc[0] = (int)o;
+                s.misc[1] = nc;
+            }
+        }
+        __syncthreads();
+        off = s.misc[0];
+        cap = s.misc[1];
+        __syncthreads();
+        if (off < 0) return;
+    }
+    float mn = MPAP_INF;
+    for (int i = threadIdx.x; i < nB; i += blockDim.x) {
+        const float4 L = s.B[i];
+        a.pool[(size_t)(unsigned)off + i] = L;
+        if (lab_open(L)) mn = fminf(mn, L.x);
+    }
+    mn = block_min(mn, reinterpret_cast<float *>(s.scan));
+    if (threadIdx.x == 0) {
+        a.nb[x] = make_int4(off, cap, nB, 0);
+        a.minopen[x] = mn;
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_search_init(SearchArgs a) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < a.n) {
+        if (v == a.root) {
+            a.nb[v] = make_int4(0, 16, 1, 0);
+            a.minopen[v] = 0.0f;
+            a.pool[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(MPAP_OPEN_BIT));
+        } else {
+            a.nb[v] = make_int4(0, 0, 0, 0);
+            a.minopen[v] = MPAP_INF;
+        }
+        a.gcnt[v] = 0;
+        a.fo[v] = make_int4(0, 0, -1, 0);
+        a.mark[v] = -1;
+    }
+    if (v == 0) {
+        *a.pool_top = 16u;
+        a.acnt[0] = 0;
+        a.acnt[1] = 0;
+        *a.bar = 0u;
+        *a.err = 0;
+        for (int i = 0; i < kOutWords; ++i) a.out[i] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_search(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    // LDS carve-up
+    MergeLds s;
+    unsigned char *p = lds;
+    s.B = reinterpret_cast<float4 *>(p);
+    p += sizeof(float4) * a.capB;
+    s.C = reinterpret_cast<float4 *>(p);
+    p += sizeof(float4) * a.capC;
+    s.e_off = reinterpret_cast<int *>(p);
+    p += sizeof(int) * blockDim.x;
+    s.e_pre = reinterpret_cast<int *>(p);
+    p += sizeof(int) * blockDim.x;
+    s.e_c = reinterpret_cast<float *>(p);
+    p += sizeof(float) * blockDim.x;
+    s.e_d = reinterpret_cast<float *>(p);
+    p += sizeof(float) * blockDim.x;
+    s.scan = reinterpret_cast<int *>(p);
+    p += sizeof(long long) * 16;
+    s.misc = reinterpret_cast<int *>(p);
+    p += sizeof(int) * 8;
+    s.bdead = p;
+    p += a.capB;
+    s.cdead = p;
+
+    __shared__ long long red_ll[16];
+    __shared__ float red_f[16];
+
+    const int G = (int)gridDim.x;
+    const int b = (int)blockIdx.x;
+    const int lo = (int)((long long)b * a.n / G);
+    const int hi = (int)((long long)(b + 1) * a.n / G);
+
+    unsigned epoch = 0;
+    float T = 0.0f;        // group threshold of this iteration
+    long long i_step = 0;  // threshold index: T = i_step * delta (unless jumped)
+    int wave = 0;          // number of groups expanded so far
+    long long abase = 0;   // arena ids handed out so far
+    int it = 0;            // loop trips (parity of the partial sums)
+    long long st_merges = 0, st_cand = 0;
+    int status = kStatusOk;
+
+    for (;;) {
+        const int par = it & 1;
+        if (threadIdx.x == 0 && b == 0) a.acnt[wave_par(wave)] = 0;
+        phase_count(a, T, par, lo, hi, red_ll, red_f);
+        grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+
+        // every block derives the same decisions from the same partial sums
+        long long total = 0, before = 0, open_nodes = 0;
+        float mn = MPAP_INF;
+        for (int q = 0; q < G; ++q) {
+            const long long c = a.part_cnt[par * G + q];
+            if (q < b) before += c;
+            total += c;
+            open_nodes += a.part_open[par * G + q];
+            mn = fminf(mn, a.part_min[par * G + q]);
+        }
+        const int errv = __hip_atomic_load(a.err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (errv != 0) {
+            status = kStatusError;
+            break;
+        }
+        if (open_nodes == 0) break;  // P_open is empty
+        ++it;
+        if (it > 2 * a.max_waves + 64 || (total == 0 && !(mn < MPAP_INF))) {
+            status = kStatusNoConverge;
+            break;
+        }
+        if (total == 0) {
+            // empty group: move the threshold up to the cheapest open label
+            T = mn;
+            i_step = (long long)floorf(mn / a.delta);
+            continue;
+        }
+        if (wave >= a.max_waves) {
+            status = kStatusNoConverge;
+            break;
+        }
+        if (abase + total > a.arena_cap || total > a.F_cap) {
+            status = kStatusArena;
+            break;
+        }
+        phase_select(a, T, wave, abase, before, lo, hi, s.scan, s.e_off);
+        grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+
+        const int na = __hip_atomic_load(&a.acnt[wave_par(wave)], __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = b; k < na; k += G) {
+            const int x = a.alist[k];
+            merge_node(a, x, wave, s, st_cand);
+            ++st_merges;
+        }
+        grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+
+        abase += total;
+        ++wave;
+        ++i_step;
+        T = (float)i_step * a.delta;
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&a.out[kOutMerges], (unsigned long long)st_merges);
+        atomicAdd((unsigned long long *)&a.out[kOutCandidates], (unsigned long long)st_cand);
+        if (b == 0) {
+            a.out[kOutWaves] = wave;
+            a.out[kOutLabels] = abase;
+            a.out[kOutStatus] = status;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
+    __shared__ long long red[16];
+    long long s = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x)
+        s += a.nb[v].z;
+    s = block_sum_ll(s, red);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.out[kOutFront], (unsigned long long)s);
+}
+
+// ----------------------------------------------------------- goal front (a7)
+// Gather the labels of every goal node (goal nodes ascending, bucket order),
+// drop weakly dominated ones (first of equal vectors kept), and emit the
+// survivors in lexicographic (c, d, m) order with their witness.
+__global__ void __launch_bounds__(1024) k_goal_gather(GoalArgs g) {
+    __shared__ int scan[32];
+    int carry = 0;
+    for (int t0 = 0; t0 < g.n_goal; t0 += blockDim.x) {
+        const int i = t0 + threadIdx.x;
+        int c = 0;
+        int4 nbv = make_int4(0, 0, 0, 0);
+        int node = -1;
+        if (i < g.n_goal) {
+            node = g.goal_list[i];
+            nbv = g.nb[node];
+            c = nbv.z;
+        }
+        int tot;
+        const int ex = block_excl_scan(c, scan, &tot);
+        const int base = carry + ex;
+        for (int k = 0; k < c; ++k) {
+            if (base + k < g.cap) {
+                g.lab[base + k] = g.pool[(size_t)(unsigned)nbv.x + k];
+                g.lab_node[base + k] = node;
+            }
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *g.n_lab = carry;
+}
+
+__global__ void __launch_bounds__(256) k_goal_dominance(GoalArgs g) {
+    const int n = min(*g.n_lab, g.cap);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float4 li = g.lab[i];
+        bool dead = false;
+        for (int j = 0; j < n && !dead; ++j) {
+            if (j == i) continue;
+            const float4 lj = g.lab[j];
+            dead = lab_le(lj, li) && (j < i || !lab_eq(lj, li));
+        }
+        g.dead[i] = dead ? 1 : 0;
+    }
+}
+
+__device__ __forceinline__ bool lex_less(const float4 &a, const float4 &b) {
+    if (a.x != b.x) return a.x < b.x;
+    if (a.y != b.y) return a.y < b.y;
+    return a.z < b.z;
+}
+
+__global__ void __launch_bounds__(256) k_goal_emit(GoalArgs g) {
+    const int n = min(*g.n_lab, g.cap);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (g.dead[i]) continue;
+        const float4 li = g.lab[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j)
+            if (!g.dead[j] && lex_less(g.lab[j], li)) ++rank;
+        g.out_lab[rank] = li;
+        g.out_node[rank] = g.lab_node[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // survivors count (same for every block); computed serially once
+        int c = 0;
+        for (int j = 0; j < n; ++j) c += g.dead[j] ? 0 : 1;
+        *g.out_count = c;
+    }
+}

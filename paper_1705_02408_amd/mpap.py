@@ -1,0 +1,315 @@
+"""Thin ctypes binding of libmpap (include/mpap.h), same names as the C ABI.
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels.  If the library is not built, or no gfx950 device is present, calls
+fail loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpap.so")
+
+MPAP_OK = 0
+MPAP_ERR_INVAL = 1
+MPAP_ERR_NOGOAL = 2
+MPAP_ERR_NOMEM = 3
+MPAP_ERR_HIP = 4
+MPAP_ERR_OVERFLOW = 5
+MPAP_ERR_NOCONVERGE = 6
+MPAP_ERR_CAPACITY = 7
+MPAP_ERR_DEVICE = 8
+
+
+class MpapError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"mpap status {status}: {message}")
+        self.status = status
+
+
+class mpap_env(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+                ("pos", ctypes.c_void_p), ("n_boxes", ctypes.c_int32),
+                ("box_lo", ctypes.c_void_p), ("box_hi", ctypes.c_void_p),
+                ("n_blobs", ctypes.c_int32), ("blob_mu", ctypes.c_void_p),
+                ("blob_sigma", ctypes.c_void_p), ("blob_amp", ctypes.c_void_p),
+                ("goal", ctypes.c_float * 3), ("goal_radius", ctypes.c_float)]
+
+
+class mpap_graph_params(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_float), ("check_step", ctypes.c_float),
+                ("reset_q", ctypes.c_float)]
+
+
+class mpap_search_params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_float), ("lambda_", ctypes.c_float),
+                ("radius", ctypes.c_float), ("n_obj", ctypes.c_int32),
+                ("init_node", ctypes.c_int32), ("max_waves", ctypes.c_int32)]
+
+
+class mpap_stats(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("retries", ctypes.c_int32),
+                ("labels_expanded", ctypes.c_int64), ("front_labels", ctypes.c_int64),
+                ("merges", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("gpu_ms", ctypes.c_float)]
+
+
+SYMBOLS = [
+    "mpap_build_graph", "mpap_graph_from_csr", "mpap_graph_info", "mpap_graph_export",
+    "mpap_graph_free", "mpap_search", "mpap_goal_front", "mpap_node_front",
+    "mpap_label_path", "mpap_result_stats", "mpap_result_free", "mpap_status_string",
+    "mpap_last_error",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmpap.so.  torch (if installed) is imported first so that the
+    library binds to the same HIP runtime as torch in this process."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built (run __graft_entry__.build())")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.mpap_build_graph.argtypes = [ctypes.POINTER(mpap_env), ctypes.POINTER(mpap_graph_params),
+                                     P, ctypes.POINTER(P)]
+    lib.mpap_graph_from_csr.argtypes = [I32, P, P, P, P, P, P, P, ctypes.POINTER(P)]
+    lib.mpap_graph_info.argtypes = [P, P, P, P]
+    lib.mpap_graph_export.argtypes = [P, P, P, P, P, P, P]
+    lib.mpap_graph_free.argtypes = [P]
+    lib.mpap_graph_free.restype = None
+    lib.mpap_search.argtypes = [P, ctypes.POINTER(mpap_search_params), P, ctypes.POINTER(P)]
+    lib.mpap_goal_front.argtypes = [P, P, P, P, P, P, I32, P]
+    lib.mpap_node_front.argtypes = [P, I32, P, P, P, P, I32, P]
+    lib.mpap_label_path.argtypes = [P, I32, P, I32, P]
+    lib.mpap_result_stats.argtypes = [P, ctypes.POINTER(mpap_stats)]
+    lib.mpap_result_free.argtypes = [P]
+    lib.mpap_result_free.restype = None
+    lib.mpap_status_string.argtypes = [ctypes.c_int]
+    lib.mpap_status_string.restype = ctypes.c_char_p
+    lib.mpap_last_error.argtypes = []
+    lib.mpap_last_error.restype = ctypes.c_char_p
+    for name in ("mpap_build_graph", "mpap_graph_from_csr", "mpap_graph_info",
+                 "mpap_graph_export", "mpap_search", "mpap_goal_front", "mpap_node_front",
+                 "mpap_label_path", "mpap_result_stats"):
+        getattr(lib, name).restype = ctypes.c_int
+    _ = I64
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != MPAP_OK:
+        msg = _lib.mpap_last_error().decode(errors="replace")
+        raise MpapError(status, msg)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(int(stream.cuda_stream))  # torch.cuda.Stream
+
+
+class Graph:
+    """Owner of an mpap_graph handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def info(self):
+        n = ctypes.c_int32()
+        e = ctypes.c_int64()
+        g = ctypes.c_int32()
+        _check(load().mpap_graph_info(self.handle, ctypes.byref(n), ctypes.byref(e),
+                                      ctypes.byref(g)))
+        return dict(n=n.value, e=e.value, n_goal=g.value)
+
+    def export(self) -> dict:
+        inf = self.info()
+        n, e = inf["n"], inf["e"]
+        out = dict(row_ptr=np.empty(n + 1, np.int32), col=np.empty(e, np.int32),
+                   cost=np.empty(e, np.float32), drift=np.empty(e, np.float32),
+                   reset=np.empty(n, np.uint8), goal=np.empty(n, np.uint8))
+        _check(load().mpap_graph_export(self.handle, _p(out["row_ptr"]), _p(out["col"]),
+                                        _p(out["cost"]), _p(out["drift"]), _p(out["reset"]),
+                                        _p(out["goal"])))
+        return out
+
+    def close(self):
+        if self.handle:
+            load().mpap_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpap_graph_from_csr(row_ptr, col, cost, drift, reset, goal, stream=None) -> Graph:
+    lib = load()
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    cl = np.ascontiguousarray(col, np.int32)
+    co = np.ascontiguousarray(cost, np.float32)
+    dr = np.ascontiguousarray(drift, np.float32)
+    rs = np.ascontiguousarray(reset, np.uint8)
+    go = np.ascontiguousarray(goal, np.uint8)
+    h = ctypes.c_void_p()
+    _check(lib.mpap_graph_from_csr(rp.shape[0] - 1, _p(rp), _p(cl), _p(co), _p(dr), _p(rs),
+                                   _p(go), _stream(stream), ctypes.byref(h)))
+    return Graph(h)
+
+
+def mpap_build_graph(env, radius=None, check_step=None, reset_q=None, stream=None) -> Graph:
+    """Build the roadmap of an environment (synth.Env or alike) on the GPU."""
+    lib = load()
+    pos = np.ascontiguousarray(env.pos, np.float32)
+    lo = np.ascontiguousarray(env.box_lo, np.float32)
+    hi = np.ascontiguousarray(env.box_hi, np.float32)
+    mu = np.ascontiguousarray(env.blob_mu, np.float32)
+    sg = np.ascontiguousarray(env.blob_sigma, np.float32)
+    am = np.ascontiguousarray(env.blob_amp, np.float32)
+    e = mpap_env()
+    e.dim = env.dim
+    e.n_nodes = pos.shape[0]
+    e.pos = _p(pos).value
+    e.n_boxes = lo.shape[0]
+    e.box_lo = _p(lo).value
+    e.box_hi = _p(hi).value
+    e.n_blobs = mu.shape[0]
+    e.blob_mu = _p(mu).value
+    e.blob_sigma = _p(sg).value
+    e.blob_amp = _p(am).value
+    gl = np.zeros(3, np.float32)
+    gl[: env.dim] = env.goal
+    for k in range(3):
+        e.goal[k] = float(gl[k])
+    e.goal_radius = float(env.goal_radius)
+    gp = mpap_graph_params(float(env.radius if radius is None else radius),
+                           float(env.check_step if check_step is None else check_step),
+                           float(env.reset_q if reset_q is None else reset_q))
+    h = ctypes.c_void_p()
+    _check(lib.mpap_build_graph(ctypes.byref(e), ctypes.byref(gp), _stream(stream),
+                                ctypes.byref(h)))
+    return Graph(h)
+
+
+@dataclasses.dataclass
+class Front:
+    vecs: np.ndarray      # float32 [k, 3] (cost, drift, max drift)
+    goal_node: np.ndarray  # int32 [k]
+    label: np.ndarray      # int32 [k]
+
+
+class Result:
+    """Owner of an mpap_result handle.  Free results before their graph."""
+
+    def __init__(self, handle, graph: Graph):
+        self.handle = handle
+        self.graph = graph
+
+    def goal_front(self) -> Front:
+        return mpap_goal_front(self)
+
+    def node_front(self, node: int, with_ids: bool = False):
+        return mpap_node_front(self, node, with_ids)
+
+    def path(self, label: int) -> list[int]:
+        return mpap_label_path(self, label)
+
+    def stats(self) -> dict:
+        return mpap_result_stats(self)
+
+    def close(self):
+        if self.handle:
+            load().mpap_result_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float = 0.5,
+                init_node: int = 0, max_waves: int = 0, stream=None) -> Result:
+    lib = load()
+    sp = mpap_search_params(float(beta), float(lam), float(radius), int(n_obj), int(init_node),
+                            int(max_waves))
+    h = ctypes.c_void_p()
+    _check(lib.mpap_search(graph.handle, ctypes.byref(sp), _stream(stream), ctypes.byref(h)))
+    return Result(h, graph)
+
+
+def mpap_goal_front(res: Result) -> Front:
+    lib = load()
+    cnt = ctypes.c_int32()
+    st = lib.mpap_goal_front(res.handle, None, None, None, None, None, 0, ctypes.byref(cnt))
+    if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
+        _check(st)
+    k = cnt.value
+    c = np.empty(k, np.float32)
+    d = np.empty(k, np.float32)
+    m = np.empty(k, np.float32)
+    gn = np.empty(k, np.int32)
+    lb = np.empty(k, np.int32)
+    _check(lib.mpap_goal_front(res.handle, _p(c), _p(d), _p(m), _p(gn), _p(lb), k,
+                               ctypes.byref(cnt)))
+    return Front(np.stack([c, d, m], axis=1).reshape(k, 3), gn, lb)
+
+
+def mpap_node_front(res: Result, node: int, with_ids: bool = False):
+    """Labels of P(node) in storage order: float32 [k, 3] (and int32 ids)."""
+    lib = load()
+    cnt = ctypes.c_int32()
+    st = lib.mpap_node_front(res.handle, int(node), None, None, None, None, 0,
+                             ctypes.byref(cnt))
+    if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
+        _check(st)
+    k = cnt.value
+    c = np.empty(k, np.float32)
+    d = np.empty(k, np.float32)
+    m = np.empty(k, np.float32)
+    ids = np.empty(k, np.int32)
+    _check(lib.mpap_node_front(res.handle, int(node), _p(c), _p(d), _p(m), _p(ids), k,
+                               ctypes.byref(cnt)))
+    v = np.stack([c, d, m], axis=1).reshape(k, 3)
+    return (v, ids) if with_ids else v
+
+
+def mpap_label_path(res: Result, label: int) -> list[int]:
+    lib = load()
+    ln = ctypes.c_int32()
+    st = lib.mpap_label_path(res.handle, int(label), None, 0, ctypes.byref(ln))
+    if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
+        _check(st)
+    buf = np.empty(ln.value, np.int32)
+    _check(lib.mpap_label_path(res.handle, int(label), _p(buf), ln.value, ctypes.byref(ln)))
+    return buf.tolist()
+
+
+def mpap_result_stats(res: Result) -> dict:
+    lib = load()
+    s = mpap_stats()
+    _check(lib.mpap_result_stats(res.handle, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in mpap_stats._fields_}
