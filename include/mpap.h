@@ -176,10 +176,24 @@ typedef struct {
     int64_t front_labels;     /* sum over nodes of the final front sizes */
     int64_t merges;           /* per-node dominance merges */
     int64_t candidates;       /* children generated that passed the bound */
-    float gpu_ms;             /* device time of the search launch(es) */
+    int64_t relaxations;      /* sum over nodes of |P(v)| * out-degree(v) */
+    float gpu_ms;             /* device time of the search launch (hipEvents on the stream) */
+    int32_t lds_front_cap;    /* largest per-node front the LDS merge stages */
+    int32_t blocks;           /* workgroups of the persistent launch */
 } mpap_stats;
 
 int mpap_result_stats(const mpap_result *r, mpap_stats *out);
+
+/*
+ * mpap_wave_trace - per-iteration trace of the last search (a profiling aid).
+ * For each of the first min(waves, 4096) Explore iterations, 8 int64 words:
+ * device clock (100 MHz) at the start of the count phase, after the count,
+ * select and merge barriers; group size; merge targets; the longest and the
+ * summed per-workgroup merge-phase duration (ticks).  out holds
+ * capacity * 8 words; *waves receives the traced count (MPAP_ERR_CAPACITY if
+ * it exceeds capacity, nothing written).
+ */
+int mpap_wave_trace(const mpap_result *r, int64_t *out, int32_t capacity, int32_t *waves);
 void mpap_result_free(mpap_result *r);
 
 /* ----------------------------------------------------------------- misc */

@@ -73,6 +73,8 @@ class OracleResult:
     pops: int
     R: int = 0        # sum over front labels of the head's out-degree
     seconds: float = 0.0
+    complete: bool = True
+    cut: float = float("inf")  # fronts are exact for costs below this
 
     def node_front(self, v: int) -> np.ndarray:
         """float32 [k, 3] vectors (c, d, m) at node v, lexicographic order."""
@@ -97,8 +99,14 @@ def sort_lex(v: np.ndarray) -> np.ndarray:
 
 
 def search(g: dict, beta: float, n_obj: int, root: int = 0,
-           max_labels: int = 0) -> OracleResult:
-    """Exact per-node fronts for graph ``g`` (CSR dict), bound beta."""
+           max_labels: int = 0, allow_partial: bool = False) -> OracleResult:
+    """Exact per-node fronts for graph ``g`` (CSR dict), bound beta.
+
+    With ``max_labels`` > 0 and ``allow_partial`` the run stops once that many
+    labels are permanent.  Labels become permanent in lexicographic order, so
+    the partial fronts are then exactly the final fronts restricted to costs
+    below ``cut`` (the cost of the last permanent label): ``complete`` tells
+    which case holds."""
     import time
     lib = _load()
     rp = np.ascontiguousarray(g["row_ptr"], dtype=np.int32)
@@ -116,7 +124,7 @@ def search(g: dict, beta: float, n_obj: int, root: int = 0,
     if not h:
         raise RuntimeError(f"oracle failed, status {st.value}")
     try:
-        if st.value != 0:
+        if st.value != 0 and not (st.value == 1 and allow_partial):
             raise RuntimeError(f"oracle stopped, status {st.value}")
         L = lib.mo_num_labels(h)
         c = np.empty(L, np.float32)
@@ -135,10 +143,12 @@ def search(g: dict, beta: float, n_obj: int, root: int = 0,
     outdeg = np.diff(rp).astype(np.int64)
     sizes = np.diff(off)
     R = int((sizes * outdeg).sum())
+    complete = st.value == 0
+    cut = float("inf") if complete else float(c[-1])
     return OracleResult(n_obj=n_obj, beta=float(np.float32(beta)), c=c, d=d, m=m, node=node,
                         parent=parent, front_off=off, front_lab=lab, X=int(cnt[0]),
                         violations=int(cnt[2]), pushes=int(cnt[3]), pops=int(cnt[4]), R=R,
-                        seconds=secs)
+                        seconds=secs, complete=complete, cut=cut)
 
 
 def pareto_min(vecs: np.ndarray, n_obj: int) -> np.ndarray:
@@ -208,3 +218,29 @@ def rewalk(g: dict, nodes: list[int], beta: float, n_obj: int):
         if n_obj >= 3:
             m = max(m, dpre)
     return c, d, m, ok
+
+
+def timed_sample(g: dict, beta: float, n_obj: int, max_labels: int, root: int = 0):
+    """Run the oracle until it has made ``max_labels`` labels permanent (or
+    finished) and time it.  Returns (labels made permanent, seconds, finished).
+    Used only to quote a CPU rate on a bounded piece of a large search."""
+    import time
+    lib = _load()
+    rp = np.ascontiguousarray(g["row_ptr"], dtype=np.int32)
+    col = np.ascontiguousarray(g["col"], dtype=np.int32)
+    cost = np.ascontiguousarray(g["cost"], dtype=np.float32)
+    drift = np.ascontiguousarray(g["drift"], dtype=np.float32)
+    reset = np.ascontiguousarray(g["reset"], dtype=np.uint8)
+    st = ctypes.c_int32(0)
+    t0 = time.perf_counter()
+    h = lib.mo_run(rp.shape[0] - 1, _ptr(rp), _ptr(col), _ptr(cost), _ptr(drift), _ptr(reset),
+                   ctypes.c_float(np.float32(beta)), n_obj, root, int(max_labels),
+                   ctypes.byref(st))
+    secs = time.perf_counter() - t0
+    if not h:
+        raise RuntimeError(f"oracle failed, status {st.value}")
+    try:
+        labels = int(lib.mo_num_labels(h))
+    finally:
+        lib.mo_free(h)
+    return labels, secs, st.value == 0

@@ -77,6 +77,8 @@ void dfree(T *&p) {
 
 int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+constexpr int kTraceCap = 4096;  // waves recorded in the per-wave trace
+
 // exclusive scan of n int32 (device); tmp holds >= div_up(n, kScanTile) ints
 int scan_i32(const int *in, int *out, long long n, int *tmp, hipStream_t s) {
     if (n <= 0) return MPAP_OK;
@@ -136,6 +138,7 @@ struct Workspace {
     unsigned *bar = nullptr;
     int *err = nullptr;
     long long *out = nullptr;
+    long long *wstat = nullptr;
     // goal front
     float4 *g_lab = nullptr, *g_out = nullptr;
     int *g_node = nullptr, *g_out_node = nullptr, *g_n = nullptr, *g_count = nullptr;
@@ -145,7 +148,7 @@ struct Workspace {
     void free_all() {
         dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
         dfree(mark); dfree(alist); dfree(acnt); dfree(F); dfree(arena); dfree(part_cnt);
-        dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out);
+        dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out); dfree(wstat);
         dfree(g_lab); dfree(g_out); dfree(g_node); dfree(g_out_node); dfree(g_n);
         dfree(g_count); dfree(g_dead);
         if (ev0) (void)hipEventDestroy(ev0);
@@ -172,6 +175,7 @@ static int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     if ((r = dalloc(&w->bar, 1))) return r;
     if ((r = dalloc(&w->err, 1))) return r;
     if ((r = dalloc(&w->out, kOutWords))) return r;
+    if ((r = dalloc(&w->wstat, (size_t)kTraceCap * kTraceWords))) return r;
     if ((r = dalloc(&w->g_n, 1))) return r;
     if ((r = dalloc(&w->g_count, 1))) return r;
     HIP_TRY(hipEventCreate(&w->ev0));
@@ -546,9 +550,10 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
         return st;
     };
 
-    unsigned long long pool_cap = std::max<unsigned long long>(w->pool_cap, 64ull * g->n + 4096);
-    long long arena_cap = std::max<long long>(w->arena_cap, 16ll * g->n + 4096);
-    long long F_cap = std::max<long long>(w->F_cap, 4ll * g->n + 4096);
+    // first guesses; a workspace keeps what earlier searches needed
+    unsigned long long pool_cap = std::max<unsigned long long>(w->pool_cap, 256ull * g->n + 65536);
+    long long arena_cap = std::max<long long>(w->arena_cap, 128ll * g->n + 65536);
+    long long F_cap = std::max<long long>(w->F_cap, 32ll * g->n + 65536);
     const int max_waves = sp->max_waves > 0 ? sp->max_waves : (1 << 18);
     long long dev_out[kOutWords];
     int dev_err = 0;
@@ -567,6 +572,7 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
         a.arena = w->arena; a.arena_cap = std::min<long long>(w->arena_cap, 0x7ffffff0ll);
         a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_min = w->part_min;
         a.bar = w->bar; a.err = w->err; a.out = w->out;
+        a.wstat = w->wstat; a.wstat_cap = kTraceCap;
 
         k_search_init<<<div_up(g->n, 256), 256, 0, s>>>(a);
         HIP_TRY(hipGetLastError());
@@ -590,13 +596,14 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
         if (dev_err & kErrBucket)
             return bail(fail(MPAP_ERR_OVERFLOW, "a per-node front exceeds the LDS staging capacity (" +
                                                     std::to_string(capB) + " labels)"));
-        if (++retries > 8) return bail(fail(MPAP_ERR_OVERFLOW, "capacity retries exhausted"));
-        if (dev_err & kErrPool) pool_cap *= 2;
+        if (++retries > 12) return bail(fail(MPAP_ERR_OVERFLOW, "capacity retries exhausted"));
+        if (dev_err & kErrPool) pool_cap *= 4;
         if (status == kStatusArena) {
-            arena_cap *= 2;
-            F_cap *= 2;
+            if (dev_out[kOutLabels] + dev_out[kOutNeed] > arena_cap) arena_cap *= 4;
+            if (dev_out[kOutNeed] > F_cap) F_cap *= 4;
         }
-        if (pool_cap > (1ull << 31) - 1)
+        pool_cap = std::min<unsigned long long>(pool_cap, (1ull << 31) - 1);
+        if ((dev_err & kErrPool) && w->pool_cap >= (1ull << 31) - 1)
             return bail(fail(MPAP_ERR_OVERFLOW, "bucket pool beyond 2^31 labels"));
     }
 
@@ -637,6 +644,9 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
     res->stats.front_labels = dev_out[kOutFront];
     res->stats.merges = dev_out[kOutMerges];
     res->stats.candidates = dev_out[kOutCandidates];
+    res->stats.relaxations = dev_out[kOutRelax];
+    res->stats.lds_front_cap = capB;
+    res->stats.blocks = nblocks;
     res->stats.gpu_ms = ms;
     *out = res;
     return MPAP_OK;
@@ -704,6 +714,17 @@ int mpap_label_path(const mpap_result *rc, int32_t label_id, int32_t *nodes, int
     if (capacity < len) return fail(MPAP_ERR_CAPACITY, "capacity below the path length");
     int32_t i = len - 1;
     for (long long a = label_id; a >= 0; a = r->arena_host[a].y) nodes[i--] = r->arena_host[a].x;
+    return MPAP_OK;
+}
+
+int mpap_wave_trace(const mpap_result *r, int64_t *out, int32_t capacity, int32_t *waves) {
+    if (!r || !waves) return fail(MPAP_ERR_INVAL, "null argument");
+    const int32_t w = std::min<int32_t>(r->stats.waves, kTraceCap);
+    *waves = w;
+    if (capacity < w) return fail(MPAP_ERR_CAPACITY, "capacity below the traced wave count");
+    if (w > 0 && out)
+        HIP_TRY(hipMemcpy(out, r->ws->wstat, sizeof(int64_t) * kTraceWords * w,
+                          hipMemcpyDeviceToHost));
     return MPAP_OK;
 }
 

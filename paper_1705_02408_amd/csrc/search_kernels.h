@@ -21,7 +21,20 @@ constexpr int kOutMerges = 2;
 constexpr int kOutCandidates = 3;
 constexpr int kOutStatus = 4;
 constexpr int kOutFront = 5;
+constexpr int kOutRelax = 6;
+constexpr int kOutNeed = 7;  // group size that did not fit (arena / frontier)
 constexpr int kOutWords = 8;
+
+// per-wave trace words (device clock ticks, 100 MHz wall clock)
+constexpr int kTraceWords = 8;
+constexpr int kTrStart = 0;      // start of the count phase
+constexpr int kTrCounted = 1;    // after the count barrier
+constexpr int kTrSelected = 2;   // after the select barrier
+constexpr int kTrMerged = 3;     // after the merge barrier
+constexpr int kTrGroup = 4;      // group size
+constexpr int kTrTargets = 5;    // merge targets
+constexpr int kTrMaxMerge = 6;   // longest per-block merge phase (ticks)
+constexpr int kTrSumMerge = 7;   // sum over blocks of merge-phase ticks
 
 struct SearchArgs {
     // graph (device)
@@ -63,6 +76,8 @@ struct SearchArgs {
     unsigned *bar;
     int *err;
     long long *out;    // [kOutWords]
+    long long *wstat;  // per-wave trace [wstat_cap][kTraceWords] (block-0 clock)
+    int wstat_cap;
 };
 
 struct GoalArgs {

@@ -345,6 +345,9 @@ __global__ void __launch_bounds__(256) k_search_init(SearchArgs a) {
         *a.err = 0;
         for (int i = 0; i < kOutWords; ++i) a.out[i] = 0;
     }
+    for (long long i = v; i < (long long)a.wstat_cap * kTraceWords;
+         i += (long long)gridDim.x * blockDim.x)
+        a.wstat[i] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_search(SearchArgs a) {
@@ -389,11 +392,15 @@ __global__ void __launch_bounds__(256) k_search(SearchArgs a) {
     long long st_merges = 0, st_cand = 0;
     int status = kStatusOk;
 
+    const bool tr0 = (b == 0 && threadIdx.x == 0);
     for (;;) {
         const int par = it & 1;
+        long long* tr = (wave < a.wstat_cap) ? a.wstat + (size_t)wave * kTraceWords : nullptr;
+        if (tr0 && tr) tr[kTrStart] = (long long)wall_clock64();
         if (threadIdx.x == 0 && b == 0) a.acnt[wave_par(wave)] = 0;
         phase_count(a, T, par, lo, hi, red_ll, red_f);
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+        if (tr0 && tr) tr[kTrCounted] = (long long)wall_clock64();
 
         // every block derives the same decisions from the same partial sums
         long long total = 0, before = 0, open_nodes = 0;
@@ -428,19 +435,34 @@ __global__ void __launch_bounds__(256) k_search(SearchArgs a) {
         }
         if (abase + total > a.arena_cap || total > a.F_cap) {
             status = kStatusArena;
+            if (b == 0 && threadIdx.x == 0) a.out[kOutNeed] = total;
             break;
         }
         phase_select(a, T, wave, abase, before, lo, hi, s.scan, s.e_off);
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+        if (tr0 && tr) {
+            tr[kTrSelected] = (long long)wall_clock64();
+            tr[kTrGroup] = total;
+        }
 
         const int na = __hip_atomic_load(&a.acnt[wave_par(wave)], __ATOMIC_ACQUIRE,
                                          __HIP_MEMORY_SCOPE_AGENT);
+        const long long m0 = (long long)wall_clock64();
         for (int k = b; k < na; k += G) {
             const int x = a.alist[k];
             merge_node(a, x, wave, s, st_cand);
             ++st_merges;
         }
+        if (threadIdx.x == 0 && tr) {
+            const long long dm = (long long)wall_clock64() - m0;
+            atomicMax((unsigned long long *)&tr[kTrMaxMerge], (unsigned long long)dm);
+            atomicAdd((unsigned long long *)&tr[kTrSumMerge], (unsigned long long)dm);
+        }
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+        if (tr0 && tr) {
+            tr[kTrMerged] = (long long)wall_clock64();
+            tr[kTrTargets] = na;
+        }
 
         abase += total;
         ++wave;
@@ -459,12 +481,20 @@ __global__ void __launch_bounds__(256) k_search(SearchArgs a) {
 }
 
 __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
+    // front labels X = sum_v |P(v)| and useful relaxations R = sum_v |P(v)| outdeg(v)
     __shared__ long long red[16];
-    long long s = 0;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x)
-        s += a.nb[v].z;
+    long long s = 0, r = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
+        const long long k = a.nb[v].z;
+        s += k;
+        r += k * (a.optr[v + 1] - a.optr[v]);
+    }
     s = block_sum_ll(s, red);
-    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.out[kOutFront], (unsigned long long)s);
+    r = block_sum_ll(r, red);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&a.out[kOutFront], (unsigned long long)s);
+        atomicAdd((unsigned long long *)&a.out[kOutRelax], (unsigned long long)r);
+    }
 }
 
 // ----------------------------------------------------------- goal front (a7)

@@ -56,14 +56,15 @@ class mpap_stats(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("retries", ctypes.c_int32),
                 ("labels_expanded", ctypes.c_int64), ("front_labels", ctypes.c_int64),
                 ("merges", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                ("gpu_ms", ctypes.c_float)]
+                ("relaxations", ctypes.c_int64), ("gpu_ms", ctypes.c_float),
+                ("lds_front_cap", ctypes.c_int32), ("blocks", ctypes.c_int32)]
 
 
 SYMBOLS = [
     "mpap_build_graph", "mpap_graph_from_csr", "mpap_graph_info", "mpap_graph_export",
     "mpap_graph_free", "mpap_search", "mpap_goal_front", "mpap_node_front",
     "mpap_label_path", "mpap_result_stats", "mpap_result_free", "mpap_status_string",
-    "mpap_last_error",
+    "mpap_last_error", "mpap_wave_trace",
 ]
 
 _lib = None
@@ -95,6 +96,7 @@ def load(path: str = LIB_PATH):
     lib.mpap_node_front.argtypes = [P, I32, P, P, P, P, I32, P]
     lib.mpap_label_path.argtypes = [P, I32, P, I32, P]
     lib.mpap_result_stats.argtypes = [P, ctypes.POINTER(mpap_stats)]
+    lib.mpap_wave_trace.argtypes = [P, P, I32, P]
     lib.mpap_result_free.argtypes = [P]
     lib.mpap_result_free.restype = None
     lib.mpap_status_string.argtypes = [ctypes.c_int]
@@ -103,7 +105,7 @@ def load(path: str = LIB_PATH):
     lib.mpap_last_error.restype = ctypes.c_char_p
     for name in ("mpap_build_graph", "mpap_graph_from_csr", "mpap_graph_info",
                  "mpap_graph_export", "mpap_search", "mpap_goal_front", "mpap_node_front",
-                 "mpap_label_path", "mpap_result_stats"):
+                 "mpap_label_path", "mpap_result_stats", "mpap_wave_trace"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -239,6 +241,9 @@ class Result:
     def stats(self) -> dict:
         return mpap_result_stats(self)
 
+    def wave_trace(self) -> np.ndarray:
+        return mpap_wave_trace(self)
+
     def close(self):
         if self.handle:
             load().mpap_result_free(self.handle)
@@ -313,3 +318,15 @@ def mpap_result_stats(res: Result) -> dict:
     s = mpap_stats()
     _check(lib.mpap_result_stats(res.handle, ctypes.byref(s)))
     return {k: getattr(s, k) for k, _ in mpap_stats._fields_}
+
+
+def mpap_wave_trace(res: Result) -> np.ndarray:
+    """int64 [waves, 8] per-iteration trace (see include/mpap.h)."""
+    lib = load()
+    w = ctypes.c_int32()
+    st = lib.mpap_wave_trace(res.handle, None, 0, ctypes.byref(w))
+    if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
+        _check(st)
+    out = np.zeros((w.value, 8), np.int64)
+    _check(lib.mpap_wave_trace(res.handle, _p(out), w.value, ctypes.byref(w)))
+    return out

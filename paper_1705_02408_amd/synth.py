@@ -184,16 +184,17 @@ def make_env(seed: int, dim: int, n: int, n_boxes: int, n_blobs: int,
 
 def plain2d(seed: int = 0, n: int = 2000) -> Env:
     """Unit square, n uniform free samples, ~20 neighbours, 20 rectangles,
-    30 feature blobs, start (0.1, 0.1), goal ball r=0.05 at (0.9, 0.9),
-    drift bound 0.3, two objectives (cost, drift)."""
+    30 feature blobs of amplitude 0.3, start (0.1, 0.1), goal ball r=0.05 at
+    (0.9, 0.9), drift bound 0.3, two objectives (cost, drift)."""
     return make_env(seed, 2, n, 20, 30, 20.0, 0.3, 2, name=f"plain2d_n{n}_s{seed}")
 
 
 def plain3d(seed: int = 0, n: int = 20000) -> Env:
-    """Unit cube, n uniform free samples, ~40 neighbours, 100 boxes, 80 blobs,
-    start (0.1,0.1,0.1), goal ball r=0.05 at (0.9,0.9,0.9), drift bound 0.25,
-    three objectives (cost, drift, max drift so far)."""
-    return make_env(seed, 3, n, 100, 80, 40.0, 0.25, 3, name=f"plain3d_n{n}_s{seed}")
+    """Unit cube, n uniform free samples, ~40 neighbours, 100 boxes, 80 blobs
+    of amplitude 0.4, start (0.1,0.1,0.1), goal ball r=0.05 at (0.9,0.9,0.9),
+    drift bound 0.25, three objectives (cost, drift, max drift so far)."""
+    return make_env(seed, 3, n, 100, 80, 40.0, 0.25, 3, blob_amp=0.4,
+                    name=f"plain3d_n{n}_s{seed}")
 
 
 def tiny_random_graph(seed: int, n: int = 30, p_reset: float = 0.2,

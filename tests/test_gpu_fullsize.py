@@ -1,0 +1,142 @@
+"""Full-size checks of the HIP search on the 3D workload the benchmark times
+(20,000 samples, three objectives), in the same launch configuration.
+
+The whole oracle run is too long here, so three checks that hold at any size
+replace the element-by-element comparison:
+* the cheap end of every front: the oracle makes labels permanent in
+  lexicographic order, so a bounded oracle run gives the exact final fronts
+  below its last popped cost; every GPU front restricted to that cost must
+  match it bit for bit, at every node;
+* the fixpoint of Alg. 3 at sampled nodes: P(v) equals the Pareto minimum of
+  the extensions of P(u) over the in-edges u -> v (plus the root label);
+* soundness: sampled labels re-walk, along their parent chain, to their own
+  bits within the bound; the goal front is the Pareto minimum over P(goal).
+"""
+import numpy as np
+import pytest
+
+from oracle import graph as ograph, search as osearch
+from paper_1705_02408_amd import synth
+
+pytestmark = pytest.mark.gpu
+mpap = pytest.importorskip("paper_1705_02408_amd.mpap")
+
+F32 = np.float32
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def sort_lex(v):
+    v = np.asarray(v, dtype=np.float32).reshape(-1, 3)
+    return v[np.lexsort((v[:, 2], v[:, 1], v[:, 0]))] if v.shape[0] else v
+
+
+def is_pareto_min_of(P, C):
+    """True iff P equals Min(C): P is a set of distinct members of C, no member
+    of C is strictly below a member of P, and every member of C is weakly
+    dominated by a member of P.  Vectorised O(|P| |C|)."""
+    P = np.asarray(P, np.float32).reshape(-1, 3)
+    C = np.asarray(C, np.float32).reshape(-1, 3)
+    if P.shape[0] == 0 or C.shape[0] == 0:
+        return P.shape[0] == 0 and C.shape[0] == 0
+    pb = {tuple(r) for r in bits(P).tolist()}
+    cb = {tuple(r) for r in bits(C).tolist()}
+    if len(pb) != P.shape[0] or not pb <= cb:
+        return False
+    for i0 in range(0, C.shape[0], 4096):
+        blk = C[i0:i0 + 4096]
+        le = np.all(P[None, :, :] <= blk[:, None, :], axis=2)   # p <= c
+        if not le.any(axis=1).all():
+            return False
+        below = np.all(blk[:, None, :] <= P[None, :, :], axis=2) & \
+            ~np.all(blk[:, None, :] == P[None, :, :], axis=2)     # c < p strictly
+        if below.any():
+            return False
+    return True
+
+
+@pytest.fixture(scope="module")
+def full3d():
+    env = synth.plain3d(0)
+    g = ograph.build_graph(env)
+    dg = mpap.mpap_graph_from_csr(g["row_ptr"], g["col"], g["cost"], g["drift"], g["reset"],
+                                  g["goal"])
+    res = mpap.mpap_search(dg, env.beta, 3, env.radius, env.lam)
+    print("full3d search stats:", res.stats(), flush=True)
+    fronts = [res.node_front(v) for v in range(g["goal"].shape[0])]
+    yield env, g, dg, res, fronts
+    res.close()
+    dg.close()
+
+
+def test_cheap_end_of_every_front_matches_oracle(full3d):
+    env, g, dg, res, fronts = full3d
+    ref = osearch.search(g, env.beta, 3, max_labels=300000, allow_partial=True)
+    assert ref.violations == 0
+    cut = ref.cut
+    n_cmp = 0
+    for v in range(len(fronts)):
+        a = sort_lex(fronts[v])
+        a = a[a[:, 0] < cut]
+        b = ref.node_front(v)
+        b = b[b[:, 0] < cut]
+        assert a.shape == b.shape, (v, a.shape, b.shape)
+        assert np.array_equal(bits(a), bits(b)), v
+        n_cmp += a.shape[0]
+    assert n_cmp > 100000
+
+
+def test_fixpoint_at_sampled_nodes(full3d):
+    env, g, dg, res, fronts = full3d
+    rp, col = g["row_ptr"], g["col"]
+    n = rp.shape[0] - 1
+    # in-edges
+    src = np.repeat(np.arange(n), np.diff(rp))
+    order = np.argsort(col, kind="stable")
+    in_src, in_e = src[order], order
+    in_ptr = np.concatenate([[0], np.cumsum(np.bincount(col, minlength=n))])
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([rng.choice(n, 250, replace=False),
+                                       np.nonzero(g["goal"])[0], [0]]))
+    beta = F32(env.beta)
+    for i, v in enumerate(sample):
+        if i % 50 == 0:
+            print(f"fixpoint check {i}/{len(sample)}", flush=True)
+        cand = [np.zeros((1, 3), np.float32)] if v == 0 else []
+        for k in range(in_ptr[v], in_ptr[v + 1]):
+            u, e = in_src[k], in_e[k]
+            P = fronts[u]
+            if P.shape[0] == 0:
+                continue
+            c2 = (P[:, 0] + g["cost"][e]).astype(F32)
+            dp = (P[:, 1] + g["drift"][e]).astype(F32)
+            ok = dp <= beta
+            d2 = np.zeros_like(dp) if g["reset"][v] else dp
+            m2 = np.maximum(P[:, 2], dp)
+            cand.append(np.stack([c2, d2, m2], axis=1)[ok])
+        C = np.concatenate(cand) if cand else np.zeros((0, 3), np.float32)
+        assert is_pareto_min_of(fronts[v], C), v
+
+
+def test_soundness_and_goal_front(full3d):
+    env, g, dg, res, fronts = full3d
+    rng = np.random.default_rng(1)
+    n = len(fronts)
+    checked = 0
+    for v in rng.choice(n, 120, replace=False):
+        vecs, ids = res.node_front(int(v), with_ids=True)
+        for k in range(min(3, vecs.shape[0])):
+            path = res.path(int(ids[k]))
+            assert path[0] == 0 and path[-1] == v
+            c, d, m, ok = osearch.rewalk(g, path, env.beta, 3)
+            assert ok and bits([c, d, m]).tolist() == bits(vecs[k]).tolist()
+            checked += 1
+    assert checked > 50
+    gidx = np.nonzero(g["goal"])[0]
+    fr = res.goal_front()
+    assert np.array_equal(bits(fr.vecs), bits(sort_lex(fr.vecs)))
+    assert is_pareto_min_of(fr.vecs, np.concatenate([fronts[v] for v in gidx]))
+    st = res.stats()
+    assert st["front_labels"] == sum(f.shape[0] for f in fronts)
