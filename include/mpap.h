@@ -180,6 +180,7 @@ typedef struct {
     float gpu_ms;             /* device time of the search launch (hipEvents on the stream) */
     int32_t lds_front_cap;    /* largest per-node front the LDS merge stages */
     int32_t blocks;           /* workgroups of the persistent launch */
+    int32_t max_front;        /* largest final per-node front */
 } mpap_stats;
 
 int mpap_result_stats(const mpap_result *r, mpap_stats *out);

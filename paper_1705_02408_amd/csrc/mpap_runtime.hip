@@ -131,6 +131,7 @@ struct Workspace {
     int *mark = nullptr;
     int *alist = nullptr;
     int *acnt = nullptr;
+    int *mcur = nullptr;
     float4 *F = nullptr;
     int2 *arena = nullptr;
     long long *part_cnt = nullptr, *part_open = nullptr;
@@ -147,7 +148,7 @@ struct Workspace {
 
     void free_all() {
         dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
-        dfree(mark); dfree(alist); dfree(acnt); dfree(F); dfree(arena); dfree(part_cnt);
+        dfree(mark); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
         dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out); dfree(wstat);
         dfree(g_lab); dfree(g_out); dfree(g_node); dfree(g_out_node); dfree(g_n);
         dfree(g_count); dfree(g_dead);
@@ -169,6 +170,7 @@ static int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     if ((r = dalloc(&w->mark, n))) return r;
     if ((r = dalloc(&w->alist, n))) return r;
     if ((r = dalloc(&w->acnt, 2))) return r;
+    if ((r = dalloc(&w->mcur, 2))) return r;
     if ((r = dalloc(&w->part_cnt, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->part_open, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->part_min, 2 * (size_t)nblocks))) return r;
@@ -505,13 +507,14 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     // launch shape: 256-thread blocks, LDS staging sized from the device limit
-    const int threads = 256;
-    const int capC = 1024;
-    const size_t fixed = 16 * (size_t)capC + 16 * (size_t)threads + 128 + 32 + capC;
+    const int threads = 1024;
+    const int capC = 1024;  // a power of two, a multiple of the block size
+    const size_t fixed = 16 * (size_t)capC + 16 * (size_t)threads + 8 * (size_t)capC + 128 +
+                         32 + capC;
     // leave 1 KiB for the kernel's static LDS
     size_t lds_budget = std::min<size_t>(di.max_lds, 160 * 1024) - 1024;
     int capB = (int)((lds_budget - fixed) / 17);
-    capB = std::min(capB, 1 << 16);
+    capB = std::min(capB, 8 * threads);
     capB -= capB % 64;
     if (capB < 256) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
     const size_t lds = fixed + 17 * (size_t)capB;
@@ -568,7 +571,7 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
         a.max_waves = max_waves; a.capB = capB; a.capC = capC; a.nblocks = nblocks;
         a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
         a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
-        a.alist = w->alist; a.acnt = w->acnt; a.F = w->F; a.F_cap = w->F_cap;
+        a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
         a.arena = w->arena; a.arena_cap = std::min<long long>(w->arena_cap, 0x7ffffff0ll);
         a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_min = w->part_min;
         a.bar = w->bar; a.err = w->err; a.out = w->out;
@@ -646,6 +649,7 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
     res->stats.candidates = dev_out[kOutCandidates];
     res->stats.relaxations = dev_out[kOutRelax];
     res->stats.lds_front_cap = capB;
+    res->stats.max_front = (int32_t)dev_out[kOutMaxFront];
     res->stats.blocks = nblocks;
     res->stats.gpu_ms = ms;
     *out = res;

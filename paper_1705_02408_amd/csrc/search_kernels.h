@@ -23,7 +23,8 @@ constexpr int kOutStatus = 4;
 constexpr int kOutFront = 5;
 constexpr int kOutRelax = 6;
 constexpr int kOutNeed = 7;  // group size that did not fit (arena / frontier)
-constexpr int kOutWords = 8;
+constexpr int kOutMaxFront = 8;
+constexpr int kOutWords = 10;
 
 // per-wave trace words (device clock ticks, 100 MHz wall clock)
 constexpr int kTraceWords = 8;
@@ -66,6 +67,7 @@ struct SearchArgs {
     int *mark;         // per node last wave it was queued as merge target
     int *alist;        // merge targets of the current wave [n]
     int *acnt;         // [2] target counts by wave parity
+    int *mcur;         // [2] next target to merge, by wave parity
     float4 *F;         // frontier labels of the current wave
     long long F_cap;
     int2 *arena;       // per expanded label {node, parent id}

@@ -144,22 +144,42 @@ __device__ void phase_select(const SearchArgs &a, float T, int wave, long long a
 }
 
 // ------------------------------------------------------------------ P3
+// Buckets are kept in lexicographic order of (c, d, m) (then the meta bits,
+// which makes the order total and the run deterministic).  With that order a
+// label b can weakly dominate a candidate q only if b.c <= q.c, i.e. b lies in
+// the prefix of the bucket below q's cost, and the dominator of a dominated
+// candidate is nearly always among the last few labels of that prefix (the
+// labels of similar cost), so the merge tests those first.
+__device__ __forceinline__ bool lex_lt(const float4 &a, const float4 &b) {
+    if (a.x != b.x) return a.x < b.x;
+    if (a.y != b.y) return a.y < b.y;
+    if (a.z != b.z) return a.z < b.z;
+    return __float_as_uint(a.w) < __float_as_uint(b.w);
+}
+// drift and max-drift part of weak dominance (the cost part is known)
+__device__ __forceinline__ bool dm_le(const float4 &b, const float4 &q) {
+    return b.y <= q.y && b.z <= q.z;
+}
+
 struct MergeLds {
-    float4 *B;      // [capB] bucket being built
-    float4 *C;      // [capC] candidate chunk
+    float4 *B;      // [capB] front of the target, lexicographic order
+    float4 *C;      // [capC] candidates of the current chunk
     uint8_t *bdead; // [capB]
     uint8_t *cdead; // [capC]
     int *e_off;     // [blockDim] frontier offset of the in-neighbour
     int *e_pre;     // [blockDim] inclusive prefix of candidate counts
     float *e_c;     // [blockDim] edge cost
     float *e_d;     // [blockDim] edge drift
-    int *scan;      // [blockDim/64 + 1]
+    int *u_idx;     // [capC] candidates still undecided after the near scan
+    int *u_end;     // [capC] per candidate: end of the bucket prefix left to scan
+    int *scan;      // [32]
     int *misc;      // [8]
 };
 
-// compact the flagged-alive entries of arr[0..n) to the front, stable.
-// Returns the new count.  Entries only move to lower indices and each tile is
-// read before it is written.
+constexpr int kNearScan = 16;   // labels tested per candidate before the full scan
+constexpr int kMaxBPerThread = 8;  // capB <= kMaxBPerThread * blockDim
+
+// compact the alive entries of arr[0..n) to the front, stable.
 __device__ int compact_alive(float4 *arr, const uint8_t *dead, int n, int *scan) {
     int out = 0;
     for (int t0 = 0; t0 < n; t0 += blockDim.x) {
@@ -176,39 +196,152 @@ __device__ int compact_alive(float4 *arr, const uint8_t *dead, int n, int *scan)
     return out;
 }
 
-__device__ void merge_chunk(const MergeLds &s, int &nB, int nC, int capB, int *err) {
-    // (a) candidates: dead if a bucket label or another candidate is <= it
-    //     (equal candidates: the first one is kept)
-    for (int i = threadIdx.x; i < nC; i += blockDim.x) {
-        const float4 ci = s.C[i];
-        bool dead = false;
-        for (int j = 0; j < nB && !dead; ++j) dead = lab_le(s.B[j], ci);
-        for (int k = 0; k < nC && !dead; ++k) {
-            if (k == i) continue;
-            const float4 ck = s.C[k];
-            dead = lab_le(ck, ci) && (k < i || !lab_eq(ck, ci));
+// first index j of the sorted arr[0..n) with arr[j].c > c
+__device__ __forceinline__ int upper_c(const float4 *arr, int n, float c) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (arr[mid].x <= c) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+// number of entries of the sorted arr[0..n) lexicographically below v
+__device__ __forceinline__ int lex_rank(const float4 *arr, int n, const float4 &v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lex_lt(arr[mid], v)) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// block-wide bitonic sort of v[0..n), n a power of two
+__device__ void bitonic_sort(float4 *v, int n) {
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const float4 p = v[i], q = v[ixj];
+                    const bool up = (i & k) == 0;
+                    if (lex_lt(q, p) == up) {
+                        v[i] = q;
+                        v[ixj] = p;
+                    }
+                }
+            }
+            __syncthreads();
         }
+    }
+}
+
+// P(x) <- Min(P(x) U C): B[0..nB) sorted, C[0..nC) unsorted; result sorted in B.
+__device__ void merge_chunk(const MergeLds &s, int &nB, int nC, int capB, int *err) {
+    const int bd = blockDim.x;
+    // 1. near scan: the labels just below the candidate's cost
+    for (int i = threadIdx.x; i < nC; i += bd) {
+        const float4 q = s.C[i];
+        const int k = upper_c(s.B, nB, q.x);
+        const int stop = max(0, k - kNearScan);
+        bool dead = false;
+        for (int j = k - 1; j >= stop && !dead; --j) dead = dm_le(s.B[j], q);
+        s.cdead[i] = dead ? 1 : 0;
+        s.u_end[i] = dead ? 0 : stop;
+    }
+    __syncthreads();
+    // 2. list the undecided candidates (bucket prefix left to scan)
+    int nU = 0;
+    for (int t0 = 0; t0 < nC; t0 += bd) {
+        const int i = t0 + threadIdx.x;
+        const bool und = i < nC && !s.cdead[i] && s.u_end[i] > 0;
+        int tot;
+        const int ex = block_excl_scan(und ? 1 : 0, s.scan, &tot);
+        if (und) s.u_idx[nU + ex] = i;
+        nU += tot;
+    }
+    __syncthreads();
+    // 3. full scan of the rest of the prefix, gs threads per candidate
+    if (nU > 0) {
+        int gs = 1;
+        while (gs < 64 && gs * 2 * nU <= bd) gs <<= 1;
+        const int per_round = bd / gs;
+        for (int base = 0; base < nU; base += per_round) {
+            const int u = base + (int)threadIdx.x / gs;
+            const int sub = (int)threadIdx.x % gs;
+            if (u < nU) {
+                const int i = s.u_idx[u];
+                const float4 q = s.C[i];
+                int n_it = 0;
+                for (int j = s.u_end[i] - 1 - sub; j >= 0; j -= gs) {
+                    if (dm_le(s.B[j], q)) {
+                        s.cdead[i] = 1;
+                        break;
+                    }
+                    if ((++n_it & 15) == 0 && *(volatile uint8_t *)&s.cdead[i]) break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // 4. survivors of the bucket test, sorted
+    const int nS = compact_alive(s.C, s.cdead, nC, s.scan);
+    if (nS == 0) return;
+    int P = 1;
+    while (P < nS) P <<= 1;
+    for (int i = nS + threadIdx.x; i < P; i += bd)
+        s.C[i] = make_float4(MPAP_INF, MPAP_INF, MPAP_INF, __uint_as_float(0xffffffffu));
+    __syncthreads();
+    bitonic_sort(s.C, P);
+    // 5. candidates among themselves: an earlier (cheaper) one may dominate
+    for (int i = threadIdx.x; i < nS; i += bd) {
+        const float4 q = s.C[i];
+        bool dead = false;
+        for (int j = 0; j < i && !dead; ++j) dead = dm_le(s.C[j], q);
         s.cdead[i] = dead ? 1 : 0;
     }
     __syncthreads();
-    // (b) bucket labels strictly dominated by a surviving candidate leave
-    for (int j = threadIdx.x; j < nB; j += blockDim.x) {
-        const float4 bj = s.B[j];
+    const int nS2 = compact_alive(s.C, s.cdead, nS, s.scan);
+    // 6. bucket labels a surviving candidate dominates leave
+    for (int j = threadIdx.x; j < nB; j += bd) {
+        const float4 b = s.B[j];
+        const int kk = upper_c(s.C, nS2, b.x);
         bool dead = false;
-        for (int i = 0; i < nC && !dead; ++i) dead = !s.cdead[i] && lab_le(s.C[i], bj);
+        for (int i = 0; i < kk && !dead; ++i) dead = dm_le(s.C[i], b);
         s.bdead[j] = dead ? 1 : 0;
     }
     __syncthreads();
     const int nBs = compact_alive(s.B, s.bdead, nB, s.scan);
-    const int nCs = compact_alive(s.C, s.cdead, nC, s.scan);
-    if (nBs + nCs > capB) {
+    const int total = nBs + nS2;
+    if (total > capB) {
         if (threadIdx.x == 0) atomicOr(err, kErrBucket);
-        nB = nBs;  // drop the chunk; the search reports overflow
+        nB = nBs;
         __syncthreads();
         return;
     }
-    for (int i = threadIdx.x; i < nCs; i += blockDim.x) s.B[nBs + i] = s.C[i];
-    nB = nBs + nCs;
+    // 7. merge the two sorted runs in place (positions by rank; read, then write)
+    float4 rb[kMaxBPerThread];
+    int pb[kMaxBPerThread];
+#pragma unroll
+    for (int r = 0; r < kMaxBPerThread; ++r) {
+        const int k = (int)threadIdx.x + r * bd;
+        pb[r] = -1;
+        if (k < nBs) {
+            rb[r] = s.B[k];
+            pb[r] = k + lex_rank(s.C, nS2, rb[r]);
+        }
+    }
+    float4 rc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int pc = -1;
+    if ((int)threadIdx.x < nS2) {
+        rc = s.C[threadIdx.x];
+        pc = (int)threadIdx.x + lex_rank(s.B, nBs, rc);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kMaxBPerThread; ++r)
+        if (pb[r] >= 0) s.B[pb[r]] = rb[r];
+    if (pc >= 0) s.B[pc] = rc;
+    nB = total;
     __syncthreads();
 }
 
@@ -225,7 +358,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds 
     __syncthreads();
     const bool rst = (a.nflag[x] & 1u) != 0u;
     const int e0 = a.rptr[x], e1 = a.rptr[x + 1];
-    const int per = a.capC / blockDim.x;  // candidates per thread per chunk
+    bool changed = false;
     for (int t0 = e0; t0 < e1; t0 += blockDim.x) {
         // in-edge tile: frontier label counts of each in-neighbour
         const int e = t0 + threadIdx.x;
@@ -250,14 +383,14 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds 
         __syncthreads();
         const int ntile = min((int)blockDim.x, e1 - t0);
         for (int j0 = 0; j0 < tot; j0 += a.capC) {
-            // generate up to capC children of this tile, keep those within the bound
+            // children j0 .. j0+capC-1 of this tile, those within the bound
             int nC = 0;
-            for (int r = 0; r < per; ++r) {
-                const int j = j0 + r * (int)blockDim.x + threadIdx.x;
+            for (int jr = j0; jr < min(tot, j0 + a.capC); jr += blockDim.x) {
+                const int j = jr + threadIdx.x;
                 bool ok = false;
                 float4 ch = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (j < tot && j < j0 + a.capC) {
-                    // edge t: first with inclusive prefix > j
+                if (j < min(tot, j0 + a.capC)) {
+                    // in-edge t: first with inclusive prefix > j
                     int lo2 = 0, hi2 = ntile - 1;
                     while (lo2 < hi2) {
                         const int mid = (lo2 + hi2) >> 1;
@@ -281,10 +414,16 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds 
             }
             __syncthreads();
             st_cand += nC;
-            if (nC > 0) merge_chunk(s, nB, nC, a.capB, a.err);
+            if (nC > 0) {
+                const int before = nB;
+                merge_chunk(s, nB, nC, a.capB, a.err);
+                changed = true;
+                (void)before;
+            }
         }
         __syncthreads();
     }
+    if (!changed) return;
     // write the merged front back (fresh region if it outgrew the old one)
     int off = nbx.x, cap = nbx.y;
     if (nB > cap) {
@@ -350,7 +489,7 @@ __global__ void __launch_bounds__(256) k_search_init(SearchArgs a) {
         a.wstat[i] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_search(SearchArgs a) {
+__global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     // LDS carve-up
     MergeLds s;
@@ -367,6 +506,10 @@ __global__ void __launch_bounds__(256) k_search(SearchArgs a) {
     p += sizeof(float) * blockDim.x;
     s.e_d = reinterpret_cast<float *>(p);
     p += sizeof(float) * blockDim.x;
+    s.u_idx = reinterpret_cast<int *>(p);
+    p += sizeof(int) * a.capC;
+    s.u_end = reinterpret_cast<int *>(p);
+    p += sizeof(int) * a.capC;
     s.scan = reinterpret_cast<int *>(p);
     p += sizeof(long long) * 16;
     s.misc = reinterpret_cast<int *>(p);
@@ -397,7 +540,10 @@ __global__ void __launch_bounds__(256) k_search(SearchArgs a) {
         const int par = it & 1;
         long long* tr = (wave < a.wstat_cap) ? a.wstat + (size_t)wave * kTraceWords : nullptr;
         if (tr0 && tr) tr[kTrStart] = (long long)wall_clock64();
-        if (threadIdx.x == 0 && b == 0) a.acnt[wave_par(wave)] = 0;
+        if (threadIdx.x == 0 && b == 0) {
+            a.acnt[wave_par(wave)] = 0;
+            a.mcur[wave_par(wave)] = 0;
+        }
         phase_count(a, T, par, lo, hi, red_ll, red_f);
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) tr[kTrCounted] = (long long)wall_clock64();
@@ -448,9 +594,14 @@ __global__ void __launch_bounds__(256) k_search(SearchArgs a) {
         const int na = __hip_atomic_load(&a.acnt[wave_par(wave)], __ATOMIC_ACQUIRE,
                                          __HIP_MEMORY_SCOPE_AGENT);
         const long long m0 = (long long)wall_clock64();
-        for (int k = b; k < na; k += G) {
-            const int x = a.alist[k];
-            merge_node(a, x, wave, s, st_cand);
+        for (;;) {
+            // targets are taken dynamically: merges differ widely in cost
+            if (threadIdx.x == 0) s.misc[2] = atomicAdd(&a.mcur[wave_par(wave)], 1);
+            __syncthreads();
+            const int k = s.misc[2];
+            __syncthreads();
+            if (k >= na) break;
+            merge_node(a, a.alist[k], wave, s, st_cand);
             ++st_merges;
         }
         if (threadIdx.x == 0 && tr) {
@@ -484,17 +635,22 @@ __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
     // front labels X = sum_v |P(v)| and useful relaxations R = sum_v |P(v)| outdeg(v)
     __shared__ long long red[16];
     long long s = 0, r = 0;
+    int mx = 0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
         const long long k = a.nb[v].z;
         s += k;
         r += k * (a.optr[v + 1] - a.optr[v]);
+        mx = max(mx, (int)k);
     }
     s = block_sum_ll(s, red);
     r = block_sum_ll(r, red);
+    mx = wave_max_i(mx);
     if (threadIdx.x == 0) {
         atomicAdd((unsigned long long *)&a.out[kOutFront], (unsigned long long)s);
         atomicAdd((unsigned long long *)&a.out[kOutRelax], (unsigned long long)r);
     }
+    if (lane_id() == 0)
+        atomicMax((unsigned long long *)&a.out[kOutMaxFront], (unsigned long long)mx);
 }
 
 // ----------------------------------------------------------- goal front (a7)

@@ -57,7 +57,8 @@ class mpap_stats(ctypes.Structure):
                 ("labels_expanded", ctypes.c_int64), ("front_labels", ctypes.c_int64),
                 ("merges", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("relaxations", ctypes.c_int64), ("gpu_ms", ctypes.c_float),
-                ("lds_front_cap", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+                ("lds_front_cap", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("max_front", ctypes.c_int32)]
 
 
 SYMBOLS = [
