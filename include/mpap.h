@@ -123,6 +123,11 @@ typedef struct {
     int32_t n_obj;     /* 2: (cost, drift); 3: (cost, drift, max drift so far) */
     int32_t init_node; /* root of every plan (x_init), usually 0 */
     int32_t max_waves; /* cap on Explore iterations; 0 = 1 << 18 */
+    int32_t near_scan; /* tuning: front labels each child is tested against before the
+                          full prefix scan; 0 = 16.  Never changes the result. */
+    int32_t stage_cap; /* tuning: largest front merged in LDS (larger ones spill to
+                          per-workgroup device memory); 0 = what the LDS holds.
+                          Never changes the result. */
 } mpap_search_params;
 
 /*
@@ -157,6 +162,45 @@ int mpap_search(const mpap_graph *g, const mpap_search_params *sp, void *stream,
 int mpap_goal_front(const mpap_result *r, float *cost, float *drift, float *maxdrift,
                     int32_t *goal_node, int32_t *label_id, int32_t capacity, int32_t *count);
 
+/*
+ * Batches.  A graph may hold several independent planning queries: the
+ * disjoint union of their roadmaps, query q owning nodes
+ * [node_offset[q], node_offset[q+1]).  One search then runs all of them in a
+ * single persistent launch; node ids in mpap_node_front / mpap_label_path are
+ * ids of the union, goal nodes reported per query are ids within the query.
+ */
+
+/* mpap_graph_concat - a new graph holding the queries of every part, in order
+ * (parts are copied; they stay owned by the caller).  Errors: MPAP_ERR_INVAL
+ * (null, n_parts < 1, more than 2^31 nodes or edges), MPAP_ERR_NOMEM,
+ * MPAP_ERR_HIP. */
+int mpap_graph_concat(const mpap_graph *const *parts, int32_t n_parts, void *stream,
+                      mpap_graph **out);
+
+/* mpap_graph_queries - number of queries; node_offset (nullable) receives
+ * nq + 1 entries. */
+int mpap_graph_queries(const mpap_graph *g, int32_t *nq, int32_t *node_offset);
+
+/* mpap_search_batch - mpap_search over every query of g in one launch.  sp
+ * holds one parameter set per query (n_params == nq) or one for all
+ * (n_params == 1); init_node is relative to the query.  The group threshold
+ * advances by the least lambda * radius of the set (the fronts do not depend
+ * on it).  Errors as mpap_search. */
+int mpap_search_batch(const mpap_graph *g, const mpap_search_params *sp, int32_t n_params,
+                      void *stream, mpap_result **out);
+
+/* mpap_query_goal_front - goal front of one query; same rules as
+ * mpap_goal_front (which is query 0). */
+int mpap_query_goal_front(const mpap_result *r, int32_t query, float *cost, float *drift,
+                          float *maxdrift, int32_t *goal_node, int32_t *label_id,
+                          int32_t capacity, int32_t *count);
+
+/* mpap_query_info - completion of one query inside the launch: the last
+ * Explore iteration that expanded one of its labels, and the device time from
+ * the start of the launch to the end of that iteration (ms).  Either output
+ * may be NULL. */
+int mpap_query_info(const mpap_result *r, int32_t query, float *latency_ms, int32_t *last_wave);
+
 /* mpap_node_front - the final label set P(node) of one node (Alg. 3), in
  * storage order (not sorted), with each label's id.  Any output array may be
  * NULL.  Same capacity rule as mpap_goal_front. */
@@ -187,12 +231,13 @@ int mpap_result_stats(const mpap_result *r, mpap_stats *out);
 
 /*
  * mpap_wave_trace - per-iteration trace of the last search (a profiling aid).
- * For each of the first min(waves, 4096) Explore iterations, 8 int64 words:
+ * For each of the first min(waves, 4096) Explore iterations, 10 int64 words:
  * device clock (100 MHz) at the start of the count phase, after the count,
  * select and merge barriers; group size; merge targets; the longest and the
- * summed per-workgroup merge-phase duration (ticks).  out holds
- * capacity * 8 words; *waves receives the traced count (MPAP_ERR_CAPACITY if
- * it exceeds capacity, nothing written).
+ * summed per-workgroup merge-phase duration (ticks); the clock when workgroup
+ * 0 finished its count work and its select work (before the barriers).  out
+ * holds capacity * 10 words; *waves receives the traced count
+ * (MPAP_ERR_CAPACITY if it exceeds capacity, nothing written).
  */
 int mpap_wave_trace(const mpap_result *r, int64_t *out, int32_t capacity, int32_t *waves);
 void mpap_result_free(mpap_result *r);

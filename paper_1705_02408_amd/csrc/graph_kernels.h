@@ -40,3 +40,5 @@ __global__ void k_flag_list(int n, const uint8_t *flag, unsigned bit, int *list,
 __global__ void k_scan_block_sums(const int *in, long long n, int *bsum);
 __global__ void k_scan_sums(int *bsum, int nb);
 __global__ void k_scan_apply(const int *in, long long n, const int *bsum, int *out);
+__global__ void k_add_i32(int *p, long long n, int add);
+__global__ void k_zero_i32(int *p, long long n);

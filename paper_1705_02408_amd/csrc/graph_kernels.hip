@@ -276,3 +276,16 @@ __global__ void __launch_bounds__(256) k_scan_apply(const int *in, long long n,
         run += v[k];
     }
 }
+
+// p[i] += add for i < n (id shifts when roadmaps are concatenated)
+__global__ void __launch_bounds__(256) k_add_i32(int *p, long long n, int add) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] += add;
+}
+
+// p[i] = 0 for i < n (used instead of memset so the sequence can be captured)
+__global__ void __launch_bounds__(256) k_zero_i32(int *p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}

@@ -109,9 +109,25 @@ struct mpap_graph {
     float *rcost = nullptr, *rdrift = nullptr;
     uint8_t *nflag = nullptr;
     int32_t *goal_list = nullptr;
+    // query partition: query q owns nodes [qoff[q], qoff[q+1]) and goal list
+    // entries [qgoff[q], qgoff[q+1]); a plain roadmap is one query
+    int32_t nq = 1;
+    std::vector<int32_t> qoff_h, qgoff_h;
+    int32_t *qoff = nullptr, *qgoff = nullptr;
     std::vector<Workspace *> spare;
     std::mutex mu;
 };
+
+static int graph_set_single_query(mpap_graph *g) {
+    g->nq = 1;
+    g->qoff_h = {0, g->n};
+    g->qgoff_h = {0, g->n_goal};
+    int r;
+    if ((r = dalloc(&g->qoff, 2)) || (r = dalloc(&g->qgoff, 2))) return r;
+    HIP_TRY(hipMemcpy(g->qoff, g->qoff_h.data(), 2 * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->qgoff, g->qgoff_h.data(), 2 * sizeof(int32_t), hipMemcpyHostToDevice));
+    return MPAP_OK;
+}
 
 static void graph_release(mpap_graph *g);
 
@@ -121,7 +137,7 @@ struct Workspace {
     unsigned long long pool_cap = 0;
     long long arena_cap = 0, F_cap = 0;
     int nblocks = 0;
-    int goal_cap = 0;
+    long long goal_cap = 0;
     float4 *pool = nullptr;
     unsigned *pool_top = nullptr;
     int4 *nb = nullptr;
@@ -140,18 +156,29 @@ struct Workspace {
     int *err = nullptr;
     long long *out = nullptr;
     long long *wstat = nullptr;
+    float4 *spill = nullptr;
+    uint8_t *spill_flags = nullptr;
+    long long spill_cap = 0;  // capG the spill space was sized for
+    // per query
+    int nq_cap = 0;
+    float *qbeta = nullptr;
+    int *qnobj = nullptr, *qroot = nullptr, *qlast = nullptr;
+    long long *g_laboff = nullptr;
+    int *g_labcap = nullptr;
+    int *g_overflow = nullptr;
     // goal front
-    float4 *g_lab = nullptr, *g_out = nullptr;
-    int *g_node = nullptr, *g_out_node = nullptr, *g_n = nullptr, *g_count = nullptr;
-    uint8_t *g_dead = nullptr;
+    float4 *g_out = nullptr;
+    int *g_out_node = nullptr, *g_n = nullptr, *g_count = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     void free_all() {
         dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
         dfree(mark); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
         dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out); dfree(wstat);
-        dfree(g_lab); dfree(g_out); dfree(g_node); dfree(g_out_node); dfree(g_n);
-        dfree(g_count); dfree(g_dead);
+        dfree(spill); dfree(spill_flags);
+        dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count);
+        dfree(qbeta); dfree(qnobj); dfree(qroot); dfree(qlast); dfree(g_laboff);
+        dfree(g_labcap); dfree(g_overflow);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         ev0 = ev1 = nullptr;
@@ -178,15 +205,41 @@ static int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     if ((r = dalloc(&w->err, 1))) return r;
     if ((r = dalloc(&w->out, kOutWords))) return r;
     if ((r = dalloc(&w->wstat, (size_t)kTraceCap * kTraceWords))) return r;
-    if ((r = dalloc(&w->g_n, 1))) return r;
-    if ((r = dalloc(&w->g_count, 1))) return r;
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
     return MPAP_OK;
 }
 
+static int ws_queries(Workspace *w, int nq) {
+    if (nq <= w->nq_cap) return MPAP_OK;
+    int r;
+    dfree(w->qbeta); dfree(w->qnobj); dfree(w->qroot); dfree(w->qlast); dfree(w->g_laboff);
+    dfree(w->g_labcap); dfree(w->g_n); dfree(w->g_count);
+    if ((r = dalloc(&w->qbeta, nq)) || (r = dalloc(&w->qnobj, nq)) ||
+        (r = dalloc(&w->qroot, nq)) || (r = dalloc(&w->qlast, nq)) ||
+        (r = dalloc(&w->g_laboff, nq)) || (r = dalloc(&w->g_labcap, nq)) ||
+        (r = dalloc(&w->g_n, nq)) || (r = dalloc(&w->g_count, nq)))
+        return r;
+    if (!w->g_overflow && (r = dalloc(&w->g_overflow, 1))) return r;
+    w->nq_cap = nq;
+    return MPAP_OK;
+}
+
+static int ws_spill(Workspace *w, long long capG) {
+    if (capG <= w->spill_cap) return MPAP_OK;
+    int r;
+    dfree(w->spill);
+    dfree(w->spill_flags);
+    w->spill_cap = 0;
+    if ((r = dalloc(&w->spill, (size_t)w->nblocks * 2 * capG)) ||
+        (r = dalloc(&w->spill_flags, (size_t)w->nblocks * capG)))
+        return r;
+    w->spill_cap = capG;
+    return MPAP_OK;
+}
+
 static int ws_grow(Workspace *w, unsigned long long pool_cap, long long arena_cap,
-                   long long F_cap, int goal_cap) {
+                   long long F_cap, long long goal_cap) {
     int r;
     if (pool_cap > w->pool_cap) {
         dfree(w->pool);
@@ -204,13 +257,9 @@ static int ws_grow(Workspace *w, unsigned long long pool_cap, long long arena_ca
         w->F_cap = F_cap;
     }
     if (goal_cap > w->goal_cap) {
-        dfree(w->g_lab); dfree(w->g_out); dfree(w->g_node); dfree(w->g_out_node);
-        dfree(w->g_dead);
-        if ((r = dalloc(&w->g_lab, goal_cap))) return r;
+        dfree(w->g_out); dfree(w->g_out_node);
         if ((r = dalloc(&w->g_out, goal_cap))) return r;
-        if ((r = dalloc(&w->g_node, goal_cap))) return r;
         if ((r = dalloc(&w->g_out_node, goal_cap))) return r;
-        if ((r = dalloc(&w->g_dead, goal_cap))) return r;
         w->goal_cap = goal_cap;
     }
     return MPAP_OK;
@@ -221,8 +270,13 @@ struct mpap_result {
     mpap_graph *g = nullptr;
     Workspace *ws = nullptr;
     int n_obj = 2;
+    // goal fronts of all queries, query q at [front_off[q], front_off[q+1])
     std::vector<float4> front;
     std::vector<int32_t> front_node;
+    std::vector<int64_t> front_off;
+    std::vector<int32_t> qlast;      // last wave that expanded a label of the query
+    std::vector<float> qlatency_ms;  // device time from launch start to that wave's end
+    std::vector<int64_t> trace;
     mpap_stats stats{};
     std::vector<int2> arena_host;  // filled on first mpap_label_path
     bool arena_loaded = false;
@@ -325,6 +379,7 @@ int mpap_graph_from_csr(int32_t n, const int32_t *row_ptr, const int32_t *col,
         graph_release(g);
         return fail(MPAP_ERR_HIP, std::string("graph upload: ") + hipGetErrorString(he));
     }
+    if ((r = graph_set_single_query(g))) return bail(r);
     *out = g;
     return MPAP_OK;
 }
@@ -452,6 +507,10 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
         graph_release(g);
         return fail(MPAP_ERR_NOGOAL, "no roadmap node lies in the goal ball");
     }
+    if ((r = graph_set_single_query(g))) {
+        graph_release(g);
+        return r;
+    }
     *out = g;
     return MPAP_OK;
 }
@@ -461,6 +520,100 @@ int mpap_graph_info(const mpap_graph *g, int32_t *n, int64_t *e, int32_t *n_goal
     if (n) *n = g->n;
     if (e) *e = g->e;
     if (n_goal) *n_goal = g->n_goal;
+    return MPAP_OK;
+}
+
+int mpap_graph_queries(const mpap_graph *g, int32_t *nq, int32_t *node_offset) {
+    if (!g || !nq) return fail(MPAP_ERR_INVAL, "null argument");
+    *nq = g->nq;
+    if (node_offset)
+        for (int q = 0; q <= g->nq; ++q) node_offset[q] = g->qoff_h[q];
+    return MPAP_OK;
+}
+
+int mpap_graph_concat(const mpap_graph *const *parts, int32_t n_parts, void *stream,
+                      mpap_graph **out) {
+    if (!out) return fail(MPAP_ERR_INVAL, "out is null");
+    *out = nullptr;
+    if (!parts || n_parts < 1) return fail(MPAP_ERR_INVAL, "need at least one part");
+    long long n = 0, e = 0, ng = 0;
+    bool alias = true;
+    for (int i = 0; i < n_parts; ++i) {
+        if (!parts[i]) return fail(MPAP_ERR_INVAL, "null part");
+        n += parts[i]->n;
+        e += parts[i]->e;
+        ng += parts[i]->n_goal;
+        alias = alias && parts[i]->symmetric_alias;
+    }
+    if (n > 0x7fffffffll || e > 0x7fffffffll)
+        return fail(MPAP_ERR_INVAL, "concatenated roadmap exceeds int32 ids");
+    DeviceInfo di;
+    int r = device_info(&di);
+    if (r) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    mpap_graph *g = new mpap_graph();
+    g->dev = di.dev;
+    g->n = (int32_t)n;
+    g->e = e;
+    g->n_goal = (int32_t)ng;
+    g->symmetric_alias = alias;
+    auto bail = [&](int st) { graph_release(g); return st; };
+    if ((r = dalloc(&g->optr, n + 1)) || (r = dalloc(&g->ocol, e)) ||
+        (r = dalloc(&g->ocost, e)) || (r = dalloc(&g->odrift, e)) ||
+        (r = dalloc(&g->nflag, n)) || (r = dalloc(&g->goal_list, ng)))
+        return bail(r);
+    if (alias) {
+        g->rptr = g->optr; g->rsrc = g->ocol; g->rcost = g->ocost; g->rdrift = g->odrift;
+    } else if ((r = dalloc(&g->rptr, n + 1)) || (r = dalloc(&g->rsrc, e)) ||
+               (r = dalloc(&g->rcost, e)) || (r = dalloc(&g->rdrift, e))) {
+        return bail(r);
+    }
+    g->qoff_h.assign(1, 0);
+    g->qgoff_h.assign(1, 0);
+    long long no = 0, eo = 0, go = 0;
+    for (int i = 0; i < n_parts; ++i) {
+        const mpap_graph *p = parts[i];
+        auto cpy = [&](void *d, const void *src, size_t bytes) -> int {
+            if (bytes) HIP_TRY(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToDevice, s));
+            return MPAP_OK;
+        };
+        if ((r = cpy(g->optr + no, p->optr, sizeof(int32_t) * (p->n + 1))) ||
+            (r = cpy(g->ocol + eo, p->ocol, sizeof(int32_t) * p->e)) ||
+            (r = cpy(g->ocost + eo, p->ocost, sizeof(float) * p->e)) ||
+            (r = cpy(g->odrift + eo, p->odrift, sizeof(float) * p->e)) ||
+            (r = cpy(g->nflag + no, p->nflag, p->n)) ||
+            (r = cpy(g->goal_list + go, p->goal_list, sizeof(int32_t) * p->n_goal)))
+            return bail(r);
+        k_add_i32<<<std::max(1, div_up(p->n + 1, 256)), 256, 0, s>>>(g->optr + no, p->n + 1, (int)eo);
+        if (p->e > 0) k_add_i32<<<div_up(p->e, 256), 256, 0, s>>>(g->ocol + eo, p->e, (int)no);
+        if (p->n_goal > 0)
+            k_add_i32<<<div_up(p->n_goal, 256), 256, 0, s>>>(g->goal_list + go, p->n_goal, (int)no);
+        if (!alias) {
+            if ((r = cpy(g->rptr + no, p->rptr, sizeof(int32_t) * (p->n + 1))) ||
+                (r = cpy(g->rsrc + eo, p->rsrc, sizeof(int32_t) * p->e)) ||
+                (r = cpy(g->rcost + eo, p->rcost, sizeof(float) * p->e)) ||
+                (r = cpy(g->rdrift + eo, p->rdrift, sizeof(float) * p->e)))
+                return bail(r);
+            k_add_i32<<<std::max(1, div_up(p->n + 1, 256)), 256, 0, s>>>(g->rptr + no, p->n + 1, (int)eo);
+            if (p->e > 0) k_add_i32<<<div_up(p->e, 256), 256, 0, s>>>(g->rsrc + eo, p->e, (int)no);
+        }
+        HIP_TRY(hipGetLastError());
+        // the part's own query partition, shifted
+        for (int q = 0; q < p->nq; ++q) {
+            g->qoff_h.push_back((int32_t)(no + p->qoff_h[q + 1]));
+            g->qgoff_h.push_back((int32_t)(go + p->qgoff_h[q + 1]));
+        }
+        // each part's last row pointer must be written after the next part's first
+        HIP_TRY(hipStreamSynchronize(s));
+        no += p->n;
+        eo += p->e;
+        go += p->n_goal;
+    }
+    g->nq = (int32_t)g->qoff_h.size() - 1;
+    if ((r = dalloc(&g->qoff, g->nq + 1)) || (r = dalloc(&g->qgoff, g->nq + 1))) return bail(r);
+    HIP_TRY(hipMemcpy(g->qoff, g->qoff_h.data(), sizeof(int32_t) * (g->nq + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->qgoff, g->qgoff_h.data(), sizeof(int32_t) * (g->nq + 1), hipMemcpyHostToDevice));
+    *out = g;
     return MPAP_OK;
 }
 
@@ -488,25 +641,44 @@ void mpap_graph_free(mpap_graph *g) {
 }
 
 // ----------------------------------------------------------------- search
-int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream,
-                mpap_result **out) {
+int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_t nsp,
+                      void *stream, mpap_result **out) {
     if (!out) return fail(MPAP_ERR_INVAL, "out is null");
     *out = nullptr;
     if (!gc || !sp) return fail(MPAP_ERR_INVAL, "null graph or params");
     mpap_graph *g = const_cast<mpap_graph *>(gc);
-    if (sp->n_obj != 2 && sp->n_obj != 3) return fail(MPAP_ERR_INVAL, "n_obj must be 2 or 3");
-    if (sp->init_node < 0 || sp->init_node >= g->n) return fail(MPAP_ERR_INVAL, "init_node out of range");
-    if (!(sp->lambda > 0.0f) || !(sp->radius > 0.0f) || std::isnan(sp->beta))
-        return fail(MPAP_ERR_INVAL, "lambda and radius must be > 0, beta not NaN");
-    const float delta = sp->lambda * sp->radius;
-    if (!(delta > 0.0f) || !std::isfinite(delta))
-        return fail(MPAP_ERR_INVAL, "lambda * radius must be finite and > 0");
+    const int nq = g->nq;
+    if (nsp != nq && nsp != 1)
+        return fail(MPAP_ERR_INVAL, "need one parameter set per query (or one for all)");
+    float delta = __builtin_inff();
+    int max_waves = 0, near_scan = 16, stage_cap = 0;
+    for (int q = 0; q < nsp; ++q) {
+        const mpap_search_params &p = sp[q];
+        const int qn = g->qoff_h[(nsp == 1 ? 0 : q) + 1] - g->qoff_h[nsp == 1 ? 0 : q];
+        if (p.n_obj != 2 && p.n_obj != 3) return fail(MPAP_ERR_INVAL, "n_obj must be 2 or 3");
+        if (p.init_node < 0 || p.init_node >= qn) return fail(MPAP_ERR_INVAL, "init_node out of range");
+        if (!(p.lambda > 0.0f) || !(p.radius > 0.0f) || std::isnan(p.beta))
+            return fail(MPAP_ERR_INVAL, "lambda and radius must be > 0, beta not NaN");
+        const float dq = p.lambda * p.radius;
+        if (!(dq > 0.0f) || !std::isfinite(dq))
+            return fail(MPAP_ERR_INVAL, "lambda * radius must be finite and > 0");
+        delta = std::min(delta, dq);
+        max_waves = std::max(max_waves, p.max_waves);
+        if (p.near_scan > 0) near_scan = p.near_scan;
+        if (p.stage_cap > 0) stage_cap = p.stage_cap;
+    }
+    if (max_waves <= 0) max_waves = 1 << 18;
+    if (nsp == 1 && nq > 1) {
+        for (int q = 1; q < nq; ++q)
+            if (sp[0].init_node >= g->qoff_h[q + 1] - g->qoff_h[q])
+                return fail(MPAP_ERR_INVAL, "init_node out of range for a query");
+    }
     DeviceInfo di;
     int r = device_info(&di);
     if (r) return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
-    // launch shape: 256-thread blocks, LDS staging sized from the device limit
+    // launch shape: 1024-thread blocks, LDS staging sized from the device limit
     const int threads = 1024;
     const int capC = 1024;  // a power of two, a multiple of the block size
     const size_t fixed = 16 * (size_t)capC + 16 * (size_t)threads + 8 * (size_t)capC + 128 +
@@ -518,6 +690,7 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
     capB -= capB % 64;
     if (capB < 256) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
     const size_t lds = fixed + 17 * (size_t)capB;
+    if (stage_cap > 0) capB = std::min(capB, std::max(stage_cap, 1));
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search, threads, lds));
     if (per_cu < 1) return fail(MPAP_ERR_DEVICE, "search kernel does not fit on a CU");
@@ -547,28 +720,48 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
     mpap_result *res = new mpap_result();
     res->g = g;
     res->ws = w;
-    res->n_obj = sp->n_obj;
+    res->n_obj = sp[0].n_obj;
     auto bail = [&](int st) {
         mpap_result_free(res);
         return st;
     };
+    if ((r = ws_queries(w, nq))) return bail(r);
+    {
+        std::vector<float> hb(nq);
+        std::vector<int> hn(nq), hr(nq);
+        for (int q = 0; q < nq; ++q) {
+            const mpap_search_params &p = sp[nsp == 1 ? 0 : q];
+            hb[q] = p.beta;
+            hn[q] = p.n_obj;
+            hr[q] = g->qoff_h[q] + p.init_node;
+        }
+        HIP_TRY(hipMemcpyAsync(w->qbeta, hb.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(w->qnobj, hn.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(w->qroot, hr.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
 
     // first guesses; a workspace keeps what earlier searches needed
     unsigned long long pool_cap = std::max<unsigned long long>(w->pool_cap, 256ull * g->n + 65536);
     long long arena_cap = std::max<long long>(w->arena_cap, 128ll * g->n + 65536);
     long long F_cap = std::max<long long>(w->F_cap, 32ll * g->n + 65536);
-    const int max_waves = sp->max_waves > 0 ? sp->max_waves : (1 << 18);
+    pool_cap = std::min<unsigned long long>(pool_cap, (1ull << 31) - 1);
+    long long capG = std::max<long long>(w->spill_cap, std::max(4 * capB, 32768));
     long long dev_out[kOutWords];
     int dev_err = 0;
     int retries = 0;
     float ms = 0.f;
+    SearchArgs a{};
     for (;;) {
         if ((r = ws_grow(w, pool_cap, arena_cap, F_cap, 0))) return bail(r);
-        SearchArgs a{};
+        if ((r = ws_spill(w, capG))) return bail(r);
+        a = SearchArgs{};
         a.n = g->n; a.rptr = g->rptr; a.rsrc = g->rsrc; a.rcost = g->rcost;
         a.rdrift = g->rdrift; a.optr = g->optr; a.ocol = g->ocol; a.nflag = g->nflag;
-        a.beta = sp->beta; a.delta = delta; a.nobj = sp->n_obj; a.root = sp->init_node;
-        a.max_waves = max_waves; a.capB = capB; a.capC = capC; a.nblocks = nblocks;
+        a.nq = nq; a.qoff = g->qoff; a.qbeta = w->qbeta; a.qnobj = w->qnobj;
+        a.qroot = w->qroot; a.qlast = w->qlast;
+        a.delta = delta; a.max_waves = max_waves; a.near_scan = near_scan;
+        a.capB = capB; a.capC = capC; a.nblocks = nblocks;
         a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
         a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
         a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
@@ -576,8 +769,10 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
         a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_min = w->part_min;
         a.bar = w->bar; a.err = w->err; a.out = w->out;
         a.wstat = w->wstat; a.wstat_cap = kTraceCap;
+        a.spill = w->spill; a.spill_flags = w->spill_flags; a.capG = (int)capG;
 
         k_search_init<<<div_up(g->n, 256), 256, 0, s>>>(a);
+        k_search_roots<<<div_up(nq, 256), 256, 0, s>>>(a);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(w->ev0, s));
         void *kargs[] = {&a};
@@ -596,50 +791,79 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
             return bail(fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)"));
         if (status == kStatusNoConverge)
             return bail(fail(MPAP_ERR_NOCONVERGE, "max_waves reached with open plans"));
-        if (dev_err & kErrBucket)
-            return bail(fail(MPAP_ERR_OVERFLOW, "a per-node front exceeds the LDS staging capacity (" +
-                                                    std::to_string(capB) + " labels)"));
         if (++retries > 12) return bail(fail(MPAP_ERR_OVERFLOW, "capacity retries exhausted"));
-        if (dev_err & kErrPool) pool_cap *= 4;
+        if (dev_err & kErrBucket) {
+            if (capG >= (1ll << 22))
+                return bail(fail(MPAP_ERR_OVERFLOW, "a per-node front exceeds 2^22 labels"));
+            capG *= 4;
+        }
+        if (dev_err & kErrPool) {
+            if (w->pool_cap >= (1ull << 31) - 1)
+                return bail(fail(MPAP_ERR_OVERFLOW, "bucket pool beyond 2^31 labels"));
+            pool_cap = std::min<unsigned long long>(pool_cap * 4, (1ull << 31) - 1);
+        }
         if (status == kStatusArena) {
             if (dev_out[kOutLabels] + dev_out[kOutNeed] > arena_cap) arena_cap *= 4;
             if (dev_out[kOutNeed] > F_cap) F_cap *= 4;
         }
-        pool_cap = std::min<unsigned long long>(pool_cap, (1ull << 31) - 1);
-        if ((dev_err & kErrPool) && w->pool_cap >= (1ull << 31) - 1)
-            return bail(fail(MPAP_ERR_OVERFLOW, "bucket pool beyond 2^31 labels"));
     }
 
-    // goal front (a7)
+    // goal fronts (a7): query q writes its front to [lab_off[q], + lab_cap[q])
     {
-        // every goal front holds at most capB labels
-        const long long gl = (long long)g->n_goal * capB;
-        int goal_cap = (int)std::max<long long>(gl, 1);
-        if ((r = ws_grow(w, 0, 0, 0, goal_cap))) return bail(r);
-        int count = 0;
-        if (gl > 0) {
-            GoalArgs ga{};
-            ga.n_goal = g->n_goal; ga.goal_list = g->goal_list; ga.nb = w->nb; ga.pool = w->pool;
-            ga.lab = w->g_lab; ga.lab_node = w->g_node; ga.dead = w->g_dead; ga.cap = goal_cap;
-            ga.n_lab = w->g_n; ga.out_lab = w->g_out; ga.out_node = w->g_out_node;
-            ga.out_count = w->g_count;
-            k_goal_gather<<<1, 1024, 0, s>>>(ga);
-            const int gb = std::max(1, std::min(div_up(dev_out[kOutFront], 256), 1024));
-            k_goal_dominance<<<gb, 256, 0, s>>>(ga);
-            k_goal_emit<<<gb, 256, 0, s>>>(ga);
-            HIP_TRY(hipGetLastError());
-            HIP_TRY(hipMemcpyAsync(&count, w->g_count, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            res->front.resize(count);
-            res->front_node.resize(count);
-            if (count > 0) {
-                HIP_TRY(hipMemcpyAsync(res->front.data(), w->g_out, sizeof(float4) * count,
-                                       hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipMemcpyAsync(res->front_node.data(), w->g_out_node,
-                                       sizeof(int32_t) * count, hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-            }
+        const long long mf = std::max<long long>(dev_out[kOutMaxFront], 1);
+        std::vector<long long> laboff(nq);
+        std::vector<int> labcap(nq);
+        long long tot = 0;
+        for (int q = 0; q < nq; ++q) {
+            const long long c = (long long)(g->qgoff_h[q + 1] - g->qgoff_h[q]) * mf;
+            laboff[q] = tot;
+            labcap[q] = (int)std::min<long long>(c, 0x7fffffff);
+            tot += labcap[q];
         }
+        if ((r = ws_grow(w, 0, 0, 0, std::max<long long>(tot, 1)))) return bail(r);
+        HIP_TRY(hipMemcpyAsync(w->g_laboff, laboff.data(), sizeof(long long) * nq,
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(w->g_labcap, labcap.data(), sizeof(int) * nq,
+                               hipMemcpyHostToDevice, s));
+        std::vector<int> counts(nq, 0);
+        int ovf = 0, gerr = 0;
+        if (tot > 0) {
+            GoalArgs ga{};
+            ga.nq = nq; ga.qgoff = g->qgoff; ga.goal_list = g->goal_list;
+            ga.lab_off = w->g_laboff; ga.lab_cap = w->g_labcap;
+            ga.out_lab = w->g_out; ga.out_node = w->g_out_node; ga.out_count = w->g_count;
+            ga.overflow = w->g_overflow;
+            k_zero_i32<<<div_up(nq, 256), 256, 0, s>>>(w->g_count, nq);
+            k_zero_i32<<<1, 32, 0, s>>>(w->g_overflow, 1);
+            k_goal_front<<<std::min(nq, nblocks), threads, lds, s>>>(a, ga);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(counts.data(), w->g_count, sizeof(int) * nq,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&gerr, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (ovf || gerr) return bail(fail(MPAP_ERR_OVERFLOW, "goal front overflow"));
+        }
+        res->front_off.assign(nq + 1, 0);
+        for (int q = 0; q < nq; ++q) res->front_off[q + 1] = res->front_off[q] + counts[q];
+        res->front.resize(res->front_off[nq]);
+        res->front_node.resize(res->front_off[nq]);
+        for (int q = 0; q < nq; ++q) {
+            if (counts[q] == 0) continue;
+            HIP_TRY(hipMemcpyAsync(res->front.data() + res->front_off[q], w->g_out + laboff[q],
+                                   sizeof(float4) * counts[q], hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(res->front_node.data() + res->front_off[q],
+                                   w->g_out_node + laboff[q], sizeof(int32_t) * counts[q],
+                                   hipMemcpyDeviceToHost, s));
+        }
+        // global goal node ids -> ids within the query
+        res->qlast.resize(nq);
+        HIP_TRY(hipMemcpyAsync(res->qlast.data(), w->qlast, sizeof(int) * nq,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int q = 0; q < nq; ++q)
+            for (long long i = res->front_off[q]; i < res->front_off[q + 1]; ++i)
+                res->front_node[i] -= g->qoff_h[q];
     }
     res->stats.waves = (int32_t)dev_out[kOutWaves];
     res->stats.retries = retries;
@@ -652,28 +876,69 @@ int mpap_search(const mpap_graph *gc, const mpap_search_params *sp, void *stream
     res->stats.max_front = (int32_t)dev_out[kOutMaxFront];
     res->stats.blocks = nblocks;
     res->stats.gpu_ms = ms;
+    // per-query latency from the per-wave device clock
+    {
+        const int tw = std::min<int>(res->stats.waves, kTraceCap);
+        res->trace.resize((size_t)tw * kTraceWords);
+        if (tw > 0)
+            HIP_TRY(hipMemcpy(res->trace.data(), w->wstat, sizeof(int64_t) * tw * kTraceWords,
+                              hipMemcpyDeviceToHost));
+        res->qlatency_ms.assign(nq, ms);
+        if (tw > 0) {
+            const int64_t t0 = res->trace[kTrStart];
+            for (int q = 0; q < nq; ++q) {
+                const int lw = res->qlast[q];
+                if (lw >= 0 && lw < tw && res->trace[(size_t)lw * kTraceWords + kTrMerged] > 0)
+                    res->qlatency_ms[q] =
+                        (float)((res->trace[(size_t)lw * kTraceWords + kTrMerged] - t0) * 1e-5);
+            }
+        }
+    }
     *out = res;
     return MPAP_OK;
 }
 
-int mpap_goal_front(const mpap_result *r, float *cost, float *drift, float *maxdrift,
-                    int32_t *goal_node, int32_t *label_id, int32_t capacity, int32_t *count) {
+int mpap_search(const mpap_graph *g, const mpap_search_params *sp, void *stream,
+                mpap_result **out) {
+    return mpap_search_batch(g, sp, 1, stream, out);
+}
+
+int mpap_query_goal_front(const mpap_result *r, int32_t query, float *cost, float *drift,
+                          float *maxdrift, int32_t *goal_node, int32_t *label_id,
+                          int32_t capacity, int32_t *count) {
     if (!r || !count) return fail(MPAP_ERR_INVAL, "null result or count");
-    const int32_t k = (int32_t)r->front.size();
+    if (query < 0 || query >= r->g->nq) return fail(MPAP_ERR_INVAL, "query out of range");
+    const int64_t o = r->front_off[query];
+    const int32_t k = (int32_t)(r->front_off[query + 1] - o);
     *count = k;
     if (capacity < k) return fail(MPAP_ERR_CAPACITY, "capacity below the front size");
     for (int32_t i = 0; i < k; ++i) {
-        const float4 L = r->front[i];
+        const float4 L = r->front[o + i];
         if (cost) cost[i] = L.x;
         if (drift) drift[i] = L.y;
         if (maxdrift) maxdrift[i] = L.z;
-        if (goal_node) goal_node[i] = r->front_node[i];
+        if (goal_node) goal_node[i] = r->front_node[o + i];
         if (label_id) {
             int id;
             std::memcpy(&id, &L.w, sizeof(int));
             label_id[i] = id;
         }
     }
+    return MPAP_OK;
+}
+
+int mpap_goal_front(const mpap_result *r, float *cost, float *drift, float *maxdrift,
+                    int32_t *goal_node, int32_t *label_id, int32_t capacity, int32_t *count) {
+    return mpap_query_goal_front(r, 0, cost, drift, maxdrift, goal_node, label_id, capacity,
+                                 count);
+}
+
+int mpap_query_info(const mpap_result *r, int32_t query, float *latency_ms,
+                    int32_t *last_wave) {
+    if (!r) return fail(MPAP_ERR_INVAL, "null result");
+    if (query < 0 || query >= r->g->nq) return fail(MPAP_ERR_INVAL, "query out of range");
+    if (latency_ms) *latency_ms = r->qlatency_ms[query];
+    if (last_wave) *last_wave = r->qlast[query];
     return MPAP_OK;
 }
 
@@ -762,6 +1027,6 @@ static void graph_release(mpap_graph *g) {
         dfree(g->rptr); dfree(g->rsrc); dfree(g->rcost); dfree(g->rdrift);
     }
     dfree(g->optr); dfree(g->ocol); dfree(g->ocost); dfree(g->odrift);
-    dfree(g->nflag); dfree(g->goal_list);
+    dfree(g->nflag); dfree(g->goal_list); dfree(g->qoff); dfree(g->qgoff);
     delete g;
 }

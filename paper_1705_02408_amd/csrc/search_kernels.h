@@ -27,7 +27,7 @@ constexpr int kOutMaxFront = 8;
 constexpr int kOutWords = 10;
 
 // per-wave trace words (device clock ticks, 100 MHz wall clock)
-constexpr int kTraceWords = 8;
+constexpr int kTraceWords = 10;
 constexpr int kTrStart = 0;      // start of the count phase
 constexpr int kTrCounted = 1;    // after the count barrier
 constexpr int kTrSelected = 2;   // after the select barrier
@@ -36,6 +36,8 @@ constexpr int kTrGroup = 4;      // group size
 constexpr int kTrTargets = 5;    // merge targets
 constexpr int kTrMaxMerge = 6;   // longest per-block merge phase (ticks)
 constexpr int kTrSumMerge = 7;   // sum over blocks of merge-phase ticks
+constexpr int kTrCountDone = 8;  // block 0 finished its count work
+constexpr int kTrSelectDone = 9; // block 0 finished its select work
 
 struct SearchArgs {
     // graph (device)
@@ -47,12 +49,18 @@ struct SearchArgs {
     const int *optr;      // out-edge CSR row pointers [n+1]
     const int *ocol;      // out-edge target [E]
     const uint8_t *nflag; // bit 0: relocalise on arrival; bit 1: goal
-    // parameters
-    float beta;
-    float delta;  // lambda * r_n
-    int nobj;
-    int root;
+    // queries: the roadmap is the disjoint union of nq query roadmaps, query q
+    // owning nodes [qoff[q], qoff[q+1]); each has its own bound, objective
+    // count and root, and the same group-threshold step delta
+    int nq;
+    const int *qoff;     // [nq+1]
+    const float *qbeta;  // [nq]
+    const int *qnobj;    // [nq]
+    const int *qroot;    // [nq] global node id of x_init
+    int *qlast;          // [nq] last wave with a group label of the query
+    float delta;         // lambda * r_n
     int max_waves;
+    int near_scan;       // bucket labels tested per candidate before the full scan
     int capB;  // LDS staging capacity of a front (labels)
     int capC;  // candidate chunk (labels), multiple of the block size
     int nblocks;
@@ -78,28 +86,30 @@ struct SearchArgs {
     unsigned *bar;
     int *err;
     long long *out;    // [kOutWords]
+    float4 *spill;        // per-block spill space for fronts beyond capB [nblocks][2][capG]
+    uint8_t *spill_flags; // [nblocks][capG]
+    int capG;
     long long *wstat;  // per-wave trace [wstat_cap][kTraceWords] (block-0 clock)
     int wstat_cap;
 };
 
+// Goal fronts of all queries: query q's goal nodes are
+// goal_list[qgoff[q] .. qgoff[q+1]); its front goes to out_lab[lab_off[q] ..)
+// (room for lab_cap[q] labels) with the goal node of each label.
 struct GoalArgs {
-    int n_goal;
+    int nq;
+    const int *qgoff;      // [nq+1]
     const int *goal_list;
-    const int4 *nb;
-    const float4 *pool;
-    float4 *lab;       // gathered goal labels [cap]
-    int *lab_node;     // [cap]
-    uint8_t *dead;     // [cap]
-    int cap;
-    int *n_lab;
-    float4 *out_lab;   // goal front, lexicographic order [cap]
-    int *out_node;     // [cap]
-    int *out_count;
+    const long long *lab_off;  // [nq]
+    const int *lab_cap;    // [nq]
+    float4 *out_lab;
+    int *out_node;
+    int *out_count;        // [nq]
+    int *overflow;
 };
 
 __global__ void k_search_init(SearchArgs a);
+__global__ void k_search_roots(SearchArgs a);
 __global__ void k_search(SearchArgs a);
 __global__ void k_count_front(SearchArgs a);
-__global__ void k_goal_gather(GoalArgs g);
-__global__ void k_goal_dominance(GoalArgs g);
-__global__ void k_goal_emit(GoalArgs g);
+__global__ void k_goal_front(SearchArgs a, GoalArgs g);

@@ -30,40 +30,58 @@ constexpr unsigned long long kSpinLimit = 1ull << 22;
 
 __device__ __forceinline__ unsigned wave_par(int w) { return (unsigned)w & 1u; }
 
+// query owning global node v: last q with qoff[q] <= v
+__device__ __forceinline__ int query_of(const SearchArgs &a, int v) {
+    int lo = 0, hi = a.nq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.qoff[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------------------ P1
+// Nodes of the block's range are taken a tile (one per thread) at a time; the
+// nodes whose least open cost is within the threshold go to an LDS list and
+// the block's waves count their group labels in parallel, one node per wave.
 __device__ void phase_count(const SearchArgs &a, float T, int par, int lo, int hi,
-                            long long *red_ll, float *red_f) {
+                            int *list, int *scan, long long *red_ll, float *red_f) {
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     long long grp = 0, open_nodes = 0;
     float mn = MPAP_INF;
-    for (int base = lo + w * 64; base < hi; base += nw * 64) {
-        const int v = base + l;
-        float mo = MPAP_INF;
+    for (int tb = lo; tb < hi; tb += blockDim.x) {
+        const int v = tb + threadIdx.x;
         bool need = false;
         if (v < hi) {
-            mo = a.minopen[v];
+            const float mo = a.minopen[v];
             need = mo <= T;
             if (!need) a.gcnt[v] = 0;
             if (mo < MPAP_INF) open_nodes += 1;
+            mn = fminf(mn, mo);
         }
-        mn = fminf(mn, mo);
-        uint64_t m = ballot64(need);
-        while (m) {
-            const int src = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const int vv = base + src;
+        int nflag;
+        const int ex = block_excl_scan(need ? 1 : 0, scan, &nflag);
+        if (need) list[ex] = v;
+        __syncthreads();
+        for (int i = w; i < nflag; i += nw) {
+            const int vv = list[i];
             const int4 nbv = a.nb[vv];
+            // open labels at or below T lie in the prefix of the sorted bucket
             int cnt = 0;
             for (int k = l; k < nbv.z; k += 64) {
                 const float4 L = a.pool[(size_t)(unsigned)nbv.x + k];
-                cnt += (lab_open(L) && L.x <= T) ? 1 : 0;
+                if (L.x > T) break;
+                cnt += lab_open(L) ? 1 : 0;
             }
             cnt = wave_sum(cnt);
-            if (l == 0) a.gcnt[vv] = cnt;
-            if (l == src) grp += cnt;
+            if (l == 0) {
+                a.gcnt[vv] = cnt;
+                grp += cnt;
+            }
         }
+        __syncthreads();
     }
     long long g = block_sum_ll(grp, red_ll);
     long long o = block_sum_ll(open_nodes, red_ll);
@@ -76,8 +94,13 @@ __device__ void phase_count(const SearchArgs &a, float T, int par, int lo, int h
 }
 
 // ------------------------------------------------------------------ P2
+// Group labels get consecutive frontier slots in node order (a block-wide scan
+// of the per-node counts on top of the block's offset); each flagged node is
+// then handled by one wave: its group labels are copied to the frontier,
+// closed and given their arena ids, and its out-neighbours are queued.
 __device__ void phase_select(const SearchArgs &a, float T, int wave, long long abase,
-                             long long myoff, int lo, int hi, int *s_scan, int *s_goff) {
+                             long long myoff, int lo, int hi, int *list, int *list_off,
+                             int *scan) {
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
@@ -87,31 +110,33 @@ __device__ void phase_select(const SearchArgs &a, float T, int wave, long long a
         const int v = tb + threadIdx.x;
         const int g = (v < hi) ? a.gcnt[v] : 0;
         int tot;
-        const int ex = block_excl_scan(g, s_scan, &tot);
-        s_goff[threadIdx.x] = (int)(carry + ex);  // frontier offsets fit in int32
+        const int ex = block_excl_scan(g, scan, &tot);
+        int nflag;
+        const int fx = block_excl_scan(g > 0 ? 1 : 0, scan, &nflag);
+        if (g > 0) {
+            list[fx] = v;
+            list_off[fx] = (int)(carry + ex);  // frontier offsets fit in int32
+        }
         __syncthreads();
-        // each wave handles the flagged nodes of its own 64-node slice
-        const int vs = tb + w * 64 + l;
-        const bool flag = (vs < hi) && g > 0;
-        uint64_t m = ballot64(flag);
-        while (m) {
-            const int src = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            const int vv = tb + w * 64 + src;
-            const int goff = s_goff[w * 64 + src];
+        for (int i = w; i < nflag; i += nw) {
+            const int vv = list[i];
+            const int goff = list_off[i];
             const int4 nbv = a.nb[vv];
             int run = 0;
             float rmin = MPAP_INF;
+            // the bucket is sorted by cost: group labels lie below T; past T
+            // only the first open label (the least remaining open cost) matters
             for (int k0 = 0; k0 < nbv.z; k0 += 64) {
                 const int k = k0 + l;
-                bool in = false;
+                bool in = false, op = false, le = false;
                 float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
                 const size_t slot = (size_t)(unsigned)nbv.x + k;
                 if (k < nbv.z) {
                     L = a.pool[slot];
-                    const bool op = lab_open(L);
-                    in = op && L.x <= T;
-                    if (op && !in) rmin = fminf(rmin, L.x);
+                    op = lab_open(L);
+                    le = L.x <= T;
+                    in = op && le;
+                    if (op && !le) rmin = fminf(rmin, L.x);
                 }
                 const uint64_t bm = ballot64(in);
                 if (in) {
@@ -122,11 +147,16 @@ __device__ void phase_select(const SearchArgs &a, float T, int wave, long long a
                     reinterpret_cast<int *>(&a.pool[slot])[3] = (int)id;
                 }
                 run += (int)__popcll(bm);
+                const bool past = ballot64(k < nbv.z && !le) != 0;
+                if (past && (ballot64(op && !le) != 0 || nbv.w - run == 0)) break;
             }
             rmin = wave_min(rmin);
             if (l == 0) {
+                a.nb[vv].w = nbv.w - run;
                 a.minopen[vv] = rmin;
                 a.fo[vv] = make_int4(goff, run, wave, 0);
+                if (a.nq > 1) atomicMax(&a.qlast[query_of(a, vv)], wave);
+                else if (vv >= 0) a.qlast[0] = wave;
             }
             // queue out-neighbours as merge targets of this wave
             for (int e = a.optr[vv] + l; e < a.optr[vv + 1]; e += 64) {
@@ -140,7 +170,6 @@ __device__ void phase_select(const SearchArgs &a, float T, int wave, long long a
         carry += tot;
         __syncthreads();
     }
-    (void)nw;
 }
 
 // ------------------------------------------------------------------ P3
@@ -162,9 +191,15 @@ __device__ __forceinline__ bool dm_le(const float4 &b, const float4 &q) {
 }
 
 struct MergeLds {
-    float4 *B;      // [capB] front of the target, lexicographic order
+    float4 *B;      // the front being built, lexicographic order (LDS or spill space)
+    uint8_t *bdead; // flags for B
+    bool spilled;   // B lives in the block's global spill space
+    float4 *Bl;     // [capB] LDS staging of the front
+    uint8_t *bdeadl;
+    float4 *Bg0, *Bg1;  // [capG] each: this block's global spill space (double buffer)
+    uint8_t *bdeadg;    // [capG]
+    int capG;
     float4 *C;      // [capC] candidates of the current chunk
-    uint8_t *bdead; // [capB]
     uint8_t *cdead; // [capC]
     int *e_off;     // [blockDim] frontier offset of the in-neighbour
     int *e_pre;     // [blockDim] inclusive prefix of candidate counts
@@ -176,7 +211,6 @@ struct MergeLds {
     int *misc;      // [8]
 };
 
-constexpr int kNearScan = 16;   // labels tested per candidate before the full scan
 constexpr int kMaxBPerThread = 8;  // capB <= kMaxBPerThread * blockDim
 
 // compact the alive entries of arr[0..n) to the front, stable.
@@ -236,13 +270,14 @@ __device__ void bitonic_sort(float4 *v, int n) {
 }
 
 // P(x) <- Min(P(x) U C): B[0..nB) sorted, C[0..nC) unsorted; result sorted in B.
-__device__ void merge_chunk(const MergeLds &s, int &nB, int nC, int capB, int *err) {
+__device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan,
+                            int *err) {
     const int bd = blockDim.x;
     // 1. near scan: the labels just below the candidate's cost
     for (int i = threadIdx.x; i < nC; i += bd) {
         const float4 q = s.C[i];
         const int k = upper_c(s.B, nB, q.x);
-        const int stop = max(0, k - kNearScan);
+        const int stop = max(0, k - near_scan);
         bool dead = false;
         for (int j = k - 1; j >= stop && !dead; --j) dead = dm_le(s.B[j], q);
         s.cdead[i] = dead ? 1 : 0;
@@ -312,13 +347,31 @@ __device__ void merge_chunk(const MergeLds &s, int &nB, int nC, int capB, int *e
     __syncthreads();
     const int nBs = compact_alive(s.B, s.bdead, nB, s.scan);
     const int total = nBs + nS2;
-    if (total > capB) {
+    if (total > (s.spilled ? s.capG : capB) && (s.spilled || total > s.capG)) {
         if (threadIdx.x == 0) atomicOr(err, kErrBucket);
         nB = nBs;
         __syncthreads();
         return;
     }
-    // 7. merge the two sorted runs in place (positions by rank; read, then write)
+    if (s.spilled || total > capB) {
+        // 7a. merge out of place into the (other) spill buffer
+        float4 *outb = (s.spilled && s.B == s.Bg0) ? s.Bg1 : s.Bg0;
+        for (int k = threadIdx.x; k < nBs; k += bd) {
+            const float4 v = s.B[k];
+            outb[k + lex_rank(s.C, nS2, v)] = v;
+        }
+        for (int i = threadIdx.x; i < nS2; i += bd) {
+            const float4 v = s.C[i];
+            outb[i + lex_rank(s.B, nBs, v)] = v;
+        }
+        s.B = outb;
+        s.bdead = s.bdeadg;
+        s.spilled = true;
+        nB = total;
+        __syncthreads();
+        return;
+    }
+    // 7b. merge the two sorted runs in place in LDS (positions by rank; read, then write)
     float4 rb[kMaxBPerThread];
     int pb[kMaxBPerThread];
 #pragma unroll
@@ -345,18 +398,30 @@ __device__ void merge_chunk(const MergeLds &s, int &nB, int nC, int capB, int *e
     __syncthreads();
 }
 
-__device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds &s,
+// Stage P(x) (pool region nbv) for merging: LDS if it fits, else spill space.
+__device__ bool stage_front(const SearchArgs &a, MergeLds &s, const int4 &nbv) {
+    s.spilled = nbv.z > a.capB;
+    s.B = s.spilled ? s.Bg0 : s.Bl;
+    s.bdead = s.spilled ? s.bdeadg : s.bdeadl;
+    if (nbv.z > (s.spilled ? s.capG : a.capB)) {
+        if (threadIdx.x == 0) atomicOr(a.err, kErrBucket);
+        return false;
+    }
+    for (int i = threadIdx.x; i < nbv.z; i += blockDim.x)
+        s.B[i] = a.pool[(size_t)(unsigned)nbv.x + i];
+    __syncthreads();
+    return true;
+}
+
+__device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                            long long &st_cand) {
     const int4 nbx = a.nb[x];
     int nB = nbx.z;
-    if (nB > a.capB) {
-        if (threadIdx.x == 0) atomicOr(a.err, kErrBucket);
-        return;
-    }
-    for (int i = threadIdx.x; i < nB; i += blockDim.x)
-        s.B[i] = a.pool[(size_t)(unsigned)nbx.x + i];
-    __syncthreads();
+    if (!stage_front(a, s, nbx)) return;
     const bool rst = (a.nflag[x] & 1u) != 0u;
+    const int q = (a.nq > 1) ? query_of(a, x) : 0;
+    const float beta = a.qbeta[q];
+    const bool three = a.qnobj[q] >= 3;
     const int e0 = a.rptr[x], e1 = a.rptr[x + 1];
     bool changed = false;
     for (int t0 = e0; t0 < e1; t0 += blockDim.x) {
@@ -401,9 +466,9 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds 
                     const float4 P = a.F[s.e_off[t] + k];
                     const float c2 = P.x + s.e_c[t];
                     const float dpre = P.y + s.e_d[t];
-                    ok = dpre <= a.beta;
+                    ok = dpre <= beta;
                     const float d2 = rst ? 0.0f : dpre;
-                    const float m2 = (a.nobj >= 3) ? fmaxf(P.z, dpre) : 0.0f;
+                    const float m2 = three ? fmaxf(P.z, dpre) : 0.0f;
                     const unsigned meta = MPAP_OPEN_BIT | (unsigned)(__float_as_int(P.w) + 1);
                     ch = make_float4(c2, d2, m2, __uint_as_float(meta));
                 }
@@ -416,7 +481,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds 
             st_cand += nC;
             if (nC > 0) {
                 const int before = nB;
-                merge_chunk(s, nB, nC, a.capB, a.err);
+                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.err);
                 changed = true;
                 (void)before;
             }
@@ -446,14 +511,20 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds 
         if (off < 0) return;
     }
     float mn = MPAP_INF;
+    int nopen = 0;
     for (int i = threadIdx.x; i < nB; i += blockDim.x) {
         const float4 L = s.B[i];
         a.pool[(size_t)(unsigned)off + i] = L;
-        if (lab_open(L)) mn = fminf(mn, L.x);
+        if (lab_open(L)) {
+            mn = fminf(mn, L.x);
+            ++nopen;
+        }
     }
     mn = block_min(mn, reinterpret_cast<float *>(s.scan));
+    int tot_open;
+    block_excl_scan(nopen, s.scan, &tot_open);
     if (threadIdx.x == 0) {
-        a.nb[x] = make_int4(off, cap, nB, 0);
+        a.nb[x] = make_int4(off, cap, nB, tot_open);
         a.minopen[x] = mn;
     }
     __syncthreads();
@@ -464,22 +535,18 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, const MergeLds 
 __global__ void __launch_bounds__(256) k_search_init(SearchArgs a) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < a.n) {
-        if (v == a.root) {
-            a.nb[v] = make_int4(0, 16, 1, 0);
-            a.minopen[v] = 0.0f;
-            a.pool[0] = make_float4(0.f, 0.f, 0.f, __uint_as_float(MPAP_OPEN_BIT));
-        } else {
-            a.nb[v] = make_int4(0, 0, 0, 0);
-            a.minopen[v] = MPAP_INF;
-        }
+        a.nb[v] = make_int4(0, 0, 0, 0);
+        a.minopen[v] = MPAP_INF;
         a.gcnt[v] = 0;
         a.fo[v] = make_int4(0, 0, -1, 0);
         a.mark[v] = -1;
     }
     if (v == 0) {
-        *a.pool_top = 16u;
+        *a.pool_top = 16u * (unsigned)a.nq;
         a.acnt[0] = 0;
         a.acnt[1] = 0;
+        a.mcur[0] = 0;
+        a.mcur[1] = 0;
         *a.bar = 0u;
         *a.err = 0;
         for (int i = 0; i < kOutWords; ++i) a.out[i] = 0;
@@ -489,12 +556,21 @@ __global__ void __launch_bounds__(256) k_search_init(SearchArgs a) {
         a.wstat[i] = 0;
 }
 
-__global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    // LDS carve-up
-    MergeLds s;
+// Root label of every query (Alg. 3 first lines): (x_init, 0, 0) open, in its
+// own 16-label region.  Runs after k_search_init.
+__global__ void __launch_bounds__(256) k_search_roots(SearchArgs a) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nq) return;
+    const int r = a.qroot[q];
+    a.nb[r] = make_int4(16 * q, 16, 1, 1);
+    a.minopen[r] = 0.0f;
+    a.pool[(size_t)16 * q] = make_float4(0.f, 0.f, 0.f, __uint_as_float(MPAP_OPEN_BIT));
+    a.qlast[q] = 0;
+}
+
+__device__ void carve_lds(unsigned char *lds, const SearchArgs &a, MergeLds &s) {
     unsigned char *p = lds;
-    s.B = reinterpret_cast<float4 *>(p);
+    s.Bl = reinterpret_cast<float4 *>(p);
     p += sizeof(float4) * a.capB;
     s.C = reinterpret_cast<float4 *>(p);
     p += sizeof(float4) * a.capC;
@@ -514,9 +590,22 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
     p += sizeof(long long) * 16;
     s.misc = reinterpret_cast<int *>(p);
     p += sizeof(int) * 8;
-    s.bdead = p;
+    s.bdeadl = p;
     p += a.capB;
     s.cdead = p;
+    s.capG = a.capG;
+    s.Bg0 = a.spill + (size_t)blockIdx.x * 2 * a.capG;
+    s.Bg1 = s.Bg0 + a.capG;
+    s.bdeadg = a.spill_flags + (size_t)blockIdx.x * a.capG;
+    s.B = s.Bl;
+    s.bdead = s.bdeadl;
+    s.spilled = false;
+}
+
+__global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    MergeLds s;
+    carve_lds(lds, a, s);
 
     __shared__ long long red_ll[16];
     __shared__ float red_f[16];
@@ -544,7 +633,8 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
             a.acnt[wave_par(wave)] = 0;
             a.mcur[wave_par(wave)] = 0;
         }
-        phase_count(a, T, par, lo, hi, red_ll, red_f);
+        phase_count(a, T, par, lo, hi, s.u_idx, s.scan, red_ll, red_f);
+        if (tr0 && tr) tr[kTrCountDone] = (long long)wall_clock64();
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) tr[kTrCounted] = (long long)wall_clock64();
 
@@ -584,7 +674,8 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
             if (b == 0 && threadIdx.x == 0) a.out[kOutNeed] = total;
             break;
         }
-        phase_select(a, T, wave, abase, before, lo, hi, s.scan, s.e_off);
+        phase_select(a, T, wave, abase, before, lo, hi, s.u_idx, s.u_end, s.scan);
+        if (tr0 && tr) tr[kTrSelectDone] = (long long)wall_clock64();
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) {
             tr[kTrSelected] = (long long)wall_clock64();
@@ -654,72 +745,41 @@ __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
 }
 
 // ----------------------------------------------------------- goal front (a7)
-// Gather the labels of every goal node (goal nodes ascending, bucket order),
-// drop weakly dominated ones (first of equal vectors kept), and emit the
-// survivors in lexicographic (c, d, m) order with their witness.
-__global__ void __launch_bounds__(1024) k_goal_gather(GoalArgs g) {
-    __shared__ int scan[32];
-    int carry = 0;
-    for (int t0 = 0; t0 < g.n_goal; t0 += blockDim.x) {
-        const int i = t0 + threadIdx.x;
-        int c = 0;
-        int4 nbv = make_int4(0, 0, 0, 0);
-        int node = -1;
-        if (i < g.n_goal) {
-            node = g.goal_list[i];
-            nbv = g.nb[node];
-            c = nbv.z;
-        }
-        int tot;
-        const int ex = block_excl_scan(c, scan, &tot);
-        const int base = carry + ex;
-        for (int k = 0; k < c; ++k) {
-            if (base + k < g.cap) {
-                g.lab[base + k] = g.pool[(size_t)(unsigned)nbv.x + k];
-                g.lab_node[base + k] = node;
+// P_candidates of Alg. 3 kept whole: per query, the weak-Pareto minimum of the
+// labels of all its goal nodes, in lexicographic (c, d, m) order, built with
+// the same sorted merge as the search (goal nodes in ascending order, so of
+// equal vectors the one at the smallest goal node is kept).  One workgroup per
+// query (looping if there are more queries than workgroups).
+__global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    MergeLds s;
+    carve_lds(lds, a, s);
+    for (int q = blockIdx.x; q < g.nq; q += gridDim.x) {
+        s.B = s.Bl;
+        s.bdead = s.bdeadl;
+        s.spilled = false;
+        int nB = 0;
+        for (int gi = g.qgoff[q]; gi < g.qgoff[q + 1]; ++gi) {
+            const int4 nbv = a.nb[g.goal_list[gi]];
+            for (int c0 = 0; c0 < nbv.z; c0 += a.capC) {
+                const int nC = min(a.capC, nbv.z - c0);
+                for (int i = threadIdx.x; i < nC; i += blockDim.x)
+                    s.C[i] = a.pool[(size_t)(unsigned)nbv.x + c0 + i];
+                __syncthreads();
+                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.err);
             }
         }
-        carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *g.n_lab = carry;
-}
-
-__global__ void __launch_bounds__(256) k_goal_dominance(GoalArgs g) {
-    const int n = min(*g.n_lab, g.cap);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float4 li = g.lab[i];
-        bool dead = false;
-        for (int j = 0; j < n && !dead; ++j) {
-            if (j == i) continue;
-            const float4 lj = g.lab[j];
-            dead = lab_le(lj, li) && (j < i || !lab_eq(lj, li));
+        const long long o = g.lab_off[q];
+        if (nB > g.lab_cap[q]) {
+            if (threadIdx.x == 0) atomicOr(g.overflow, 1);
+            nB = g.lab_cap[q];
         }
-        g.dead[i] = dead ? 1 : 0;
-    }
-}
-
-__device__ __forceinline__ bool lex_less(const float4 &a, const float4 &b) {
-    if (a.x != b.x) return a.x < b.x;
-    if (a.y != b.y) return a.y < b.y;
-    return a.z < b.z;
-}
-
-__global__ void __launch_bounds__(256) k_goal_emit(GoalArgs g) {
-    const int n = min(*g.n_lab, g.cap);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        if (g.dead[i]) continue;
-        const float4 li = g.lab[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j)
-            if (!g.dead[j] && lex_less(g.lab[j], li)) ++rank;
-        g.out_lab[rank] = li;
-        g.out_node[rank] = g.lab_node[i];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // survivors count (same for every block); computed serially once
-        int c = 0;
-        for (int j = 0; j < n; ++j) c += g.dead[j] ? 0 : 1;
-        *g.out_count = c;
+        for (int i = threadIdx.x; i < nB; i += blockDim.x) {
+            const float4 L = s.B[i];
+            g.out_lab[o + i] = L;
+            g.out_node[o + i] = a.arena[__float_as_int(L.w)].x;
+        }
+        if (threadIdx.x == 0) g.out_count[q] = nB;
+        __syncthreads();
     }
 }

@@ -49,7 +49,8 @@ class mpap_graph_params(ctypes.Structure):
 class mpap_search_params(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_float), ("lambda_", ctypes.c_float),
                 ("radius", ctypes.c_float), ("n_obj", ctypes.c_int32),
-                ("init_node", ctypes.c_int32), ("max_waves", ctypes.c_int32)]
+                ("init_node", ctypes.c_int32), ("max_waves", ctypes.c_int32),
+                ("near_scan", ctypes.c_int32), ("stage_cap", ctypes.c_int32)]
 
 
 class mpap_stats(ctypes.Structure):
@@ -65,7 +66,8 @@ SYMBOLS = [
     "mpap_build_graph", "mpap_graph_from_csr", "mpap_graph_info", "mpap_graph_export",
     "mpap_graph_free", "mpap_search", "mpap_goal_front", "mpap_node_front",
     "mpap_label_path", "mpap_result_stats", "mpap_result_free", "mpap_status_string",
-    "mpap_last_error", "mpap_wave_trace",
+    "mpap_last_error", "mpap_wave_trace", "mpap_graph_concat", "mpap_graph_queries",
+    "mpap_search_batch", "mpap_query_goal_front", "mpap_query_info",
 ]
 
 _lib = None
@@ -98,6 +100,11 @@ def load(path: str = LIB_PATH):
     lib.mpap_label_path.argtypes = [P, I32, P, I32, P]
     lib.mpap_result_stats.argtypes = [P, ctypes.POINTER(mpap_stats)]
     lib.mpap_wave_trace.argtypes = [P, P, I32, P]
+    lib.mpap_graph_concat.argtypes = [P, I32, P, ctypes.POINTER(P)]
+    lib.mpap_graph_queries.argtypes = [P, P, P]
+    lib.mpap_search_batch.argtypes = [P, P, I32, P, ctypes.POINTER(P)]
+    lib.mpap_query_goal_front.argtypes = [P, I32, P, P, P, P, P, I32, P]
+    lib.mpap_query_info.argtypes = [P, I32, P, P]
     lib.mpap_result_free.argtypes = [P]
     lib.mpap_result_free.restype = None
     lib.mpap_status_string.argtypes = [ctypes.c_int]
@@ -106,7 +113,9 @@ def load(path: str = LIB_PATH):
     lib.mpap_last_error.restype = ctypes.c_char_p
     for name in ("mpap_build_graph", "mpap_graph_from_csr", "mpap_graph_info",
                  "mpap_graph_export", "mpap_search", "mpap_goal_front", "mpap_node_front",
-                 "mpap_label_path", "mpap_result_stats", "mpap_wave_trace"):
+                 "mpap_label_path", "mpap_result_stats", "mpap_wave_trace",
+                 "mpap_graph_concat", "mpap_graph_queries", "mpap_search_batch",
+                 "mpap_query_goal_front", "mpap_query_info"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -230,8 +239,11 @@ class Result:
         self.handle = handle
         self.graph = graph
 
-    def goal_front(self) -> Front:
-        return mpap_goal_front(self)
+    def goal_front(self, query: int = 0) -> Front:
+        return mpap_query_goal_front(self, query)
+
+    def query_info(self, query: int) -> dict:
+        return mpap_query_info(self, query)
 
     def node_front(self, node: int, with_ids: bool = False):
         return mpap_node_front(self, node, with_ids)
@@ -257,20 +269,60 @@ class Result:
             pass
 
 
+def search_params(beta: float, n_obj: int, radius: float, lam: float = 0.5,
+                  init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
+                  stage_cap: int = 0):
+    return mpap_search_params(float(beta), float(lam), float(radius), int(n_obj),
+                              int(init_node), int(max_waves), int(near_scan), int(stage_cap))
+
+
 def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float = 0.5,
-                init_node: int = 0, max_waves: int = 0, stream=None) -> Result:
+                init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
+                stage_cap: int = 0, stream=None) -> Result:
     lib = load()
-    sp = mpap_search_params(float(beta), float(lam), float(radius), int(n_obj), int(init_node),
-                            int(max_waves))
+    sp = search_params(beta, n_obj, radius, lam, init_node, max_waves, near_scan, stage_cap)
     h = ctypes.c_void_p()
     _check(lib.mpap_search(graph.handle, ctypes.byref(sp), _stream(stream), ctypes.byref(h)))
     return Result(h, graph)
 
 
-def mpap_goal_front(res: Result) -> Front:
+def mpap_graph_concat(parts, stream=None) -> Graph:
+    lib = load()
+    arr = (ctypes.c_void_p * len(parts))(*[p.handle.value if isinstance(p.handle, ctypes.c_void_p)
+                                           else p.handle for p in parts])
+    h = ctypes.c_void_p()
+    _check(lib.mpap_graph_concat(arr, len(parts), _stream(stream), ctypes.byref(h)))
+    return Graph(h)
+
+
+def mpap_graph_queries(graph: Graph) -> np.ndarray:
+    """Node offsets of the queries, int32 [nq + 1]."""
+    lib = load()
+    nq = ctypes.c_int32()
+    _check(lib.mpap_graph_queries(graph.handle, ctypes.byref(nq), None))
+    off = np.empty(nq.value + 1, np.int32)
+    _check(lib.mpap_graph_queries(graph.handle, ctypes.byref(nq), _p(off)))
+    return off
+
+
+def mpap_search_batch(graph: Graph, params, stream=None) -> Result:
+    """params: one mpap_search_params (applied to all queries) or a list, one
+    per query (see search_params)."""
+    lib = load()
+    if isinstance(params, mpap_search_params):
+        params = [params]
+    arr = (mpap_search_params * len(params))(*params)
+    h = ctypes.c_void_p()
+    _check(lib.mpap_search_batch(graph.handle, arr, len(params), _stream(stream),
+                                 ctypes.byref(h)))
+    return Result(h, graph)
+
+
+def mpap_query_goal_front(res: Result, query: int) -> Front:
     lib = load()
     cnt = ctypes.c_int32()
-    st = lib.mpap_goal_front(res.handle, None, None, None, None, None, 0, ctypes.byref(cnt))
+    st = lib.mpap_query_goal_front(res.handle, int(query), None, None, None, None, None, 0,
+                                   ctypes.byref(cnt))
     if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
         _check(st)
     k = cnt.value
@@ -279,9 +331,21 @@ def mpap_goal_front(res: Result) -> Front:
     m = np.empty(k, np.float32)
     gn = np.empty(k, np.int32)
     lb = np.empty(k, np.int32)
-    _check(lib.mpap_goal_front(res.handle, _p(c), _p(d), _p(m), _p(gn), _p(lb), k,
-                               ctypes.byref(cnt)))
+    _check(lib.mpap_query_goal_front(res.handle, int(query), _p(c), _p(d), _p(m), _p(gn),
+                                     _p(lb), k, ctypes.byref(cnt)))
     return Front(np.stack([c, d, m], axis=1).reshape(k, 3), gn, lb)
+
+
+def mpap_goal_front(res: Result) -> Front:
+    return mpap_query_goal_front(res, 0)
+
+
+def mpap_query_info(res: Result, query: int) -> dict:
+    lib = load()
+    ms = ctypes.c_float()
+    lw = ctypes.c_int32()
+    _check(lib.mpap_query_info(res.handle, int(query), ctypes.byref(ms), ctypes.byref(lw)))
+    return dict(latency_ms=ms.value, last_wave=lw.value)
 
 
 def mpap_node_front(res: Result, node: int, with_ids: bool = False):
@@ -322,12 +386,12 @@ def mpap_result_stats(res: Result) -> dict:
 
 
 def mpap_wave_trace(res: Result) -> np.ndarray:
-    """int64 [waves, 8] per-iteration trace (see include/mpap.h)."""
+    """int64 [waves, 10] per-iteration trace (see include/mpap.h)."""
     lib = load()
     w = ctypes.c_int32()
     st = lib.mpap_wave_trace(res.handle, None, 0, ctypes.byref(w))
     if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
         _check(st)
-    out = np.zeros((w.value, 8), np.int64)
+    out = np.zeros((w.value, 10), np.int64)
     _check(lib.mpap_wave_trace(res.handle, _p(out), w.value, ctypes.byref(w)))
     return out

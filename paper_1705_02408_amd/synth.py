@@ -247,3 +247,41 @@ def tiny_random_graph(seed: int, n: int = 30, p_reset: float = 0.2,
     far = np.argsort(-((pts - pts[0]) ** 2).sum(axis=1), kind="stable")[:2]
     goal[far] = 1
     return dict(row_ptr=row_ptr, col=col, cost=cost, drift=drift, reset=reset, goal=goal)
+
+
+def _free_point(s: Stream, dim: int, lo, hi):
+    while True:
+        p = s.uniform(dim).astype(np.float32)
+        if not _point_in_any_box(p[None, :], lo, hi)[0]:
+            return p
+
+
+def batch_query(batch_seed: int, q: int, nmin: int = 2000, nmax: int = 50000,
+                n_obj3: int = 2) -> Env:
+    """Query q of a serving-style batch: dimension 2 or 3 (even odds), sample
+    count log-uniform in [nmin, nmax], per-query seeded boxes, blobs, start and
+    goal centre (uniform, at least 0.5 apart).  Scene densities follow the
+    single-query workloads of that dimension; the goal radius grows for small
+    roadmaps so that about ten samples fall in the goal ball (never below
+    0.05).  ``n_obj3`` sets the objective count of 3D queries."""
+    s = Stream(batch_seed * 1000003 + q, TAG_BATCH)
+    u = s.uniform(2)
+    dim = 2 if u[0] < np.float32(0.5) else 3
+    n = int(round(math.exp(math.log(nmin) + float(u[1]) * (math.log(nmax) - math.log(nmin)))))
+    seed = int(s.u64(1)[0] & np.uint64(0x7FFFFFFF))
+    qs = Stream(seed, TAG_QUERY)
+    while True:
+        init = qs.uniform(dim).astype(np.float32)
+        goal = qs.uniform(dim).astype(np.float32)
+        if float(np.sum((init.astype(np.float64) - goal) ** 2)) >= 0.25:
+            break
+    if dim == 2:
+        gr = max(0.05, math.sqrt(10.0 / (math.pi * n)))
+        env = make_env(seed, 2, n, 20, 30, 20.0, 0.3, 2, init=init, goal=goal,
+                       goal_radius=gr, blob_amp=0.3)
+    else:
+        gr = max(0.05, (10.0 * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0))
+        env = make_env(seed, 3, n, 100, 80, 40.0, 0.25, n_obj3, init=init, goal=goal,
+                       goal_radius=gr, blob_amp=0.4)
+    env.name = f"batch{batch_seed}_q{q}_{dim}d_n{n}"
+    return env

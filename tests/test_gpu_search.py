@@ -263,3 +263,17 @@ def test_search_on_device_built_graph_matches_oracle_on_same_arrays():
     res.close()
     dg.close()
     _ = checks
+
+
+@pytest.mark.parametrize("stage_cap", [64, 256])
+def test_fronts_beyond_the_lds_stage_spill_exactly(road2d, stage_cap):
+    """Fronts larger than the LDS staging capacity are merged in device
+    memory; forcing a tiny capacity must not change any front."""
+    env, g = road2d[0]
+    ref = osearch.search(g, env.beta, 2)
+    dg = upload(g)
+    res = mpap.mpap_search(dg, env.beta, 2, env.radius, env.lam, stage_cap=stage_cap)
+    assert res.stats()["max_front"] > stage_cap
+    check_against_oracle(g, res, ref, env.beta, 2, all_nodes=False, node_stride=2)
+    res.close()
+    dg.close()
