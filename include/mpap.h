@@ -128,6 +128,8 @@ typedef struct {
     int32_t stage_cap; /* tuning: largest front merged in LDS (larger ones spill to
                           per-workgroup device memory); 0 = what the LDS holds.
                           Never changes the result. */
+    int32_t heuristic; /* per-edge drift: 0 = the analytic values of the roadmap,
+                          1 = the learned surrogate's (mpap_surrogate_score) */
 } mpap_search_params;
 
 /*
@@ -241,6 +243,81 @@ int mpap_result_stats(const mpap_result *r, mpap_stats *out);
  */
 int mpap_wave_trace(const mpap_result *r, int64_t *out, int32_t capacity, int32_t *waves);
 void mpap_result_free(mpap_result *r);
+
+/* ------------------------------------------------------------- surrogate */
+/*
+ * Learned per-edge drift surrogate: a 16 -> 64 -> 64 -> 1 ReLU network that
+ * predicts an edge's mean (1 - q) from its endpoints, length and q at 8 points
+ * along it (the learned-heuristic idea of Sec. 5.2, standing in for the
+ * per-edge precompute of Alg. 1 step 2); the drift increment is
+ * length * clamp(output, 0, 1).  Inputs, the two weight matrices, the output
+ * weights and the first hidden activations are bfloat16 (round to nearest
+ * even from float32); products accumulate in float32 on the matrix cores.
+ * Parameters: one float32 block of 5313 values, W1[16][64] b1[64] W2[64][64]
+ * b2[64] w3[64] b3 (row-major, input index first).  Training is Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error against the
+ * analytic values of the roadmap's edges.
+ */
+typedef struct mpap_surrogate mpap_surrogate;
+
+int mpap_surrogate_create(mpap_surrogate **out);
+void mpap_surrogate_free(mpap_surrogate *s);
+/* Replace the parameters (count must be 5313; finite); resets Adam's state. */
+int mpap_surrogate_set_params(mpap_surrogate *s, const float *params, int32_t count);
+int mpap_surrogate_get_params(const mpap_surrogate *s, float *params, int32_t capacity,
+                              int32_t *count);
+/* He-normal weights from a counter-based SplitMix64 stream of `seed`, zero biases. */
+int mpap_surrogate_init(mpap_surrogate *s, uint64_t seed);
+
+/* The network's inputs for every edge of g (forward CSR order), 16 bfloat16
+ * bit patterns per edge, computed on the device from the id-ordered endpoint
+ * pair: x_a (3), x_b (3; z = 0 in 2D), length, q at the points
+ * x_a + (k + 1/2)/8 (x_b - x_a), k = 0..7, and q(x_b).  Needs a roadmap built
+ * by mpap_build_graph (MPAP_ERR_INVAL otherwise).  out (host, nullable) holds
+ * capacity >= 16 * edges values. */
+int mpap_edge_features(const mpap_graph *g, void *stream, uint16_t *out, int64_t capacity);
+
+/* Outputs of the network for n rows of inputs (host memory, 16 bfloat16 bit
+ * patterns per row). */
+int mpap_surrogate_forward(const mpap_surrogate *s, const uint16_t *X, int64_t n, float *y);
+
+/* Gradient of the mean squared error over one batch of n rows (n a power of
+ * two >= 64) with respect to the 5313 float32 parameters, without updating
+ * them; y_out (nullable) receives the n outputs.  For checking the training
+ * kernels. */
+int mpap_surrogate_gradient(mpap_surrogate *s, const uint16_t *X, const float *t, int32_t n,
+                            float *grad, float *y_out);
+
+/* Train on the edges `edges[0..n_train)` of g (host indices into the forward
+ * edge order), targets drift/length of the roadmap's analytic values, in
+ * batches of `batch` consecutive entries (a power of two >= 64; a short tail
+ * is dropped), `epochs` passes, learning rate lr.  epoch_loss (nullable)
+ * receives the mean squared error over the training edges after each epoch. */
+int mpap_surrogate_train(mpap_surrogate *s, const mpap_graph *g, const int64_t *edges,
+                         int64_t n_train, int32_t epochs, int32_t batch, float lr, void *stream,
+                         float *epoch_loss);
+
+/* Predicted drift of every edge of g, kept in the graph for searches with
+ * heuristic = 1 (and carried into mpap_graph_concat when every part has it).
+ * The inputs are recomputed on every call; ms (nullable) receives the device
+ * time of inputs plus inference.  Needs a roadmap built by mpap_build_graph. */
+int mpap_surrogate_score(const mpap_surrogate *s, mpap_graph *g, void *stream, float *ms);
+
+/* Recompute the analytic drift of every edge of g on the device (the same
+ * values mpap_build_graph produced); ms (nullable) receives the kernel time.
+ * The cost the surrogate is measured against. */
+int mpap_analytic_drift(mpap_graph *g, void *stream, float *ms);
+
+/* Copy a drift array of g to the host (forward CSR order): which = 0 the
+ * analytic values, 1 the surrogate's. */
+int mpap_graph_drift(const mpap_graph *g, int32_t which, float *out);
+
+/* Re-walk the plan of every goal-front label of one query with the analytic
+ * drift of the roadmap (the surrogate's judge): cost, drift, max drift and
+ * whether the pre-reset drift stays within the bound at every step.  Same
+ * order and capacity rule as mpap_query_goal_front.  Any output may be NULL. */
+int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *drift,
+                       float *maxdrift, uint8_t *feasible, int32_t capacity, int32_t *count);
 
 /* ----------------------------------------------------------------- misc */
 const char *mpap_status_string(int status);

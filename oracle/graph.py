@@ -179,3 +179,29 @@ def graph_stats(g):
     return dict(n=n, e=e, mean_degree=e / max(n, 1),
                 reset_frac=float(g["reset"].mean()), n_goal=int(g["goal"].sum()),
                 min_cost=float(g["cost"].min()) if e else math.inf)
+
+
+def edge_features(pos, row_ptr, col, cost, mu, sigma, amp):
+    """Inputs of the learned drift surrogate per edge (forward CSR order), from
+    the id-ordered pair (a, b): x_a (3), x_b (3, zero z in 2D), the length, q at
+    x_a + (k + 1/2)/8 (x_b - x_a) for k = 0..7 (float64 q), q(x_b).  float32
+    values before the bfloat16 rounding of the model."""
+    n = row_ptr.shape[0] - 1
+    src = np.repeat(np.arange(n), np.diff(row_ptr))
+    a = np.minimum(src, col)
+    b = np.maximum(src, col)
+    pa = pos[a].astype(np.float32)
+    pb = pos[b].astype(np.float32)
+    e = col.shape[0]
+    f = np.zeros((e, 16), dtype=np.float32)
+    d = pos.shape[1]
+    f[:, 0:d] = pa
+    f[:, 3:3 + d] = pb
+    f[:, 6] = cost
+    diff = (pb - pa).astype(np.float32)
+    for k in range(8):
+        s = np.float32((k + 0.5) / 8.0)
+        pts = (pa + s * diff).astype(np.float32)
+        f[:, 7 + k] = quality(pts, mu, sigma, amp)
+    f[:, 15] = quality(pb, mu, sigma, amp)
+    return f

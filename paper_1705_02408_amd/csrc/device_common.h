@@ -131,3 +131,12 @@ __device__ __forceinline__ void grid_barrier(unsigned *counter, unsigned nblocks
     __syncthreads();
     __threadfence();
 }
+
+// float32 -> bfloat16 bits, round to nearest, ties to even (NaN stays NaN)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }

@@ -42,3 +42,6 @@ __global__ void k_scan_sums(int *bsum, int nb);
 __global__ void k_scan_apply(const int *in, long long n, const int *bsum, int *out);
 __global__ void k_add_i32(int *p, long long n, int add);
 __global__ void k_zero_i32(int *p, long long n);
+__global__ void k_edge_features(BuildArgs g, int n, const int *row_ptr, const int *col,
+                                const float *cost, uint16_t *X);
+__global__ void k_drift_ratio(long long m, const float *drift, const float *cost, float *t);

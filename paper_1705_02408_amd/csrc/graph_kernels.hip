@@ -289,3 +289,55 @@ __global__ void __launch_bounds__(256) k_zero_i32(int *p, long long n) {
          i += (long long)gridDim.x * blockDim.x)
         p[i] = 0;
 }
+
+// Inputs of the learned drift surrogate for edge row u -> col[e], from the
+// id-ordered pair (a, b) so both directions agree: x_a (3), x_b (3, zero z in
+// 2D), the length, q at the 8 segment points (k + 1/2)/8, q(x_b); bfloat16.
+__global__ void __launch_bounds__(64) k_edge_features(BuildArgs g, int n, const int *row_ptr,
+                                                      const int *col, const float *cost,
+                                                      uint16_t *X) {
+    extern __shared__ float blob[];
+    for (int i = threadIdx.x; i < g.nblob * g.dim; i += blockDim.x) blob[i] = g.mu[i];
+    for (int i = threadIdx.x; i < g.nblob; i += blockDim.x) {
+        blob[g.nblob * g.dim + i] = g.sig[i];
+        blob[g.nblob * g.dim + g.nblob + i] = g.amp[i];
+    }
+    __syncthreads();
+    BuildArgs gl = g;
+    gl.mu = blob;
+    gl.sig = blob + g.nblob * g.dim;
+    gl.amp = blob + g.nblob * g.dim + g.nblob;
+    const int u = blockIdx.x;
+    if (u >= n) return;
+    for (int e = row_ptr[u] + threadIdx.x; e < row_ptr[u + 1]; e += blockDim.x) {
+        const int v = col[e];
+        const int a = min(u, v), b = max(u, v);
+        float xa[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < g.dim; ++k) {
+            xa[k] = g.pos[a * g.dim + k];
+            xb[k] = g.pos[b * g.dim + k];
+            df[k] = xb[k] - xa[k];
+        }
+        uint16_t *f = X + (size_t)e * 16;
+        for (int k = 0; k < 3; ++k) {
+            f[k] = f2bf(xa[k]);
+            f[3 + k] = f2bf(xb[k]);
+        }
+        f[6] = f2bf(cost[e]);
+        for (int j = 0; j < 8; ++j) {
+            const float s = ((float)j + 0.5f) / 8.0f;
+            float p[3] = {0.f, 0.f, 0.f};
+            for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + s * df[k];
+            f[7 + j] = f2bf(quality(gl, p));
+        }
+        f[15] = f2bf(quality(gl, xb));
+    }
+}
+
+// t[e] = drift[e] / cost[e]: the analytic per-edge mean of (1 - q), the
+// surrogate's training target
+__global__ void __launch_bounds__(256) k_drift_ratio(long long m, const float *drift,
+                                                     const float *cost, float *t) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) t[e] = drift[e] / cost[e];
+}

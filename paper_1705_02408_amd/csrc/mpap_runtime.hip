@@ -4,283 +4,9 @@
 // launches the kernels, grows capacities and retries when the device reports
 // an overflow, and copies results back.  No part of the search itself runs on
 // the host.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <mutex>
-#include <string>
-#include <vector>
-
-#include "graph_kernels.h"
-#include "mpap.h"
-#include "search_kernels.h"
-
-// ------------------------------------------------------------- error state
-namespace {
+#include "runtime_internal.h"
 
 thread_local std::string g_last_error;
-
-int fail(int status, const std::string &msg) {
-    g_last_error = msg;
-    return status;
-}
-
-#define HIP_TRY(expr)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(e_ == hipErrorOutOfMemory ? MPAP_ERR_NOMEM : MPAP_ERR_HIP,      \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
-    } while (0)
-
-struct DeviceInfo {
-    int dev = -1;
-    int cus = 0;
-    int coop = 0;
-    size_t max_lds = 0;
-};
-
-int device_info(DeviceInfo *out) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(MPAP_ERR_DEVICE, std::string("libmpap is built for gfx950, device is ") +
-                                         prop.gcnArchName);
-    out->dev = dev;
-    out->cus = prop.multiProcessorCount;
-    int coop = 0;
-    HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-    out->coop = coop;
-    out->max_lds = prop.sharedMemPerBlock;
-    if (!coop) return fail(MPAP_ERR_DEVICE, "device does not support cooperative launches");
-    return MPAP_OK;
-}
-
-template <typename T>
-int dalloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    HIP_TRY(hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)));
-    return MPAP_OK;
-}
-
-template <typename T>
-void dfree(T *&p) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
-
-int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
-
-constexpr int kTraceCap = 4096;  // waves recorded in the per-wave trace
-
-// exclusive scan of n int32 (device); tmp holds >= div_up(n, kScanTile) ints
-int scan_i32(const int *in, int *out, long long n, int *tmp, hipStream_t s) {
-    if (n <= 0) return MPAP_OK;
-    const int nb = div_up(n, kScanTile);
-    k_scan_block_sums<<<nb, 256, 0, s>>>(in, n, tmp);
-    k_scan_sums<<<1, 1024, 0, s>>>(tmp, nb);
-    k_scan_apply<<<nb, 256, 0, s>>>(in, n, tmp, out);
-    HIP_TRY(hipGetLastError());
-    return MPAP_OK;
-}
-
-}  // namespace
-
-// ------------------------------------------------------------------ graph
-struct Workspace;
-
-struct mpap_graph {
-    int dev = -1;
-    int32_t n = 0;
-    int64_t e = 0;
-    int32_t n_goal = 0;
-    bool symmetric_alias = false;  // in-edge arrays alias the out-edge ones
-    // forward CSR
-    int32_t *optr = nullptr, *ocol = nullptr;
-    float *ocost = nullptr, *odrift = nullptr;
-    // reverse CSR (in-edges)
-    int32_t *rptr = nullptr, *rsrc = nullptr;
-    float *rcost = nullptr, *rdrift = nullptr;
-    uint8_t *nflag = nullptr;
-    int32_t *goal_list = nullptr;
-    // query partition: query q owns nodes [qoff[q], qoff[q+1]) and goal list
-    // entries [qgoff[q], qgoff[q+1]); a plain roadmap is one query
-    int32_t nq = 1;
-    std::vector<int32_t> qoff_h, qgoff_h;
-    int32_t *qoff = nullptr, *qgoff = nullptr;
-    std::vector<Workspace *> spare;
-    std::mutex mu;
-};
-
-static int graph_set_single_query(mpap_graph *g) {
-    g->nq = 1;
-    g->qoff_h = {0, g->n};
-    g->qgoff_h = {0, g->n_goal};
-    int r;
-    if ((r = dalloc(&g->qoff, 2)) || (r = dalloc(&g->qgoff, 2))) return r;
-    HIP_TRY(hipMemcpy(g->qoff, g->qoff_h.data(), 2 * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(g->qgoff, g->qgoff_h.data(), 2 * sizeof(int32_t), hipMemcpyHostToDevice));
-    return MPAP_OK;
-}
-
-static void graph_release(mpap_graph *g);
-
-// ------------------------------------------------------------- workspace
-struct Workspace {
-    int32_t n = 0;
-    unsigned long long pool_cap = 0;
-    long long arena_cap = 0, F_cap = 0;
-    int nblocks = 0;
-    long long goal_cap = 0;
-    float4 *pool = nullptr;
-    unsigned *pool_top = nullptr;
-    int4 *nb = nullptr;
-    float *minopen = nullptr;
-    int *gcnt = nullptr;
-    int4 *fo = nullptr;
-    int *mark = nullptr;
-    int *alist = nullptr;
-    int *acnt = nullptr;
-    int *mcur = nullptr;
-    float4 *F = nullptr;
-    int2 *arena = nullptr;
-    long long *part_cnt = nullptr, *part_open = nullptr;
-    float *part_min = nullptr;
-    unsigned *bar = nullptr;
-    int *err = nullptr;
-    long long *out = nullptr;
-    long long *wstat = nullptr;
-    float4 *spill = nullptr;
-    uint8_t *spill_flags = nullptr;
-    long long spill_cap = 0;  // capG the spill space was sized for
-    // per query
-    int nq_cap = 0;
-    float *qbeta = nullptr;
-    int *qnobj = nullptr, *qroot = nullptr, *qlast = nullptr;
-    long long *g_laboff = nullptr;
-    int *g_labcap = nullptr;
-    int *g_overflow = nullptr;
-    // goal front
-    float4 *g_out = nullptr;
-    int *g_out_node = nullptr, *g_n = nullptr, *g_count = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-
-    void free_all() {
-        dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
-        dfree(mark); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
-        dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out); dfree(wstat);
-        dfree(spill); dfree(spill_flags);
-        dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count);
-        dfree(qbeta); dfree(qnobj); dfree(qroot); dfree(qlast); dfree(g_laboff);
-        dfree(g_labcap); dfree(g_overflow);
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-        ev0 = ev1 = nullptr;
-    }
-};
-
-static int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
-    int r;
-    w->n = n;
-    w->nblocks = nblocks;
-    if ((r = dalloc(&w->pool_top, 1))) return r;
-    if ((r = dalloc(&w->nb, n))) return r;
-    if ((r = dalloc(&w->minopen, n))) return r;
-    if ((r = dalloc(&w->gcnt, n))) return r;
-    if ((r = dalloc(&w->fo, n))) return r;
-    if ((r = dalloc(&w->mark, n))) return r;
-    if ((r = dalloc(&w->alist, n))) return r;
-    if ((r = dalloc(&w->acnt, 2))) return r;
-    if ((r = dalloc(&w->mcur, 2))) return r;
-    if ((r = dalloc(&w->part_cnt, 2 * (size_t)nblocks))) return r;
-    if ((r = dalloc(&w->part_open, 2 * (size_t)nblocks))) return r;
-    if ((r = dalloc(&w->part_min, 2 * (size_t)nblocks))) return r;
-    if ((r = dalloc(&w->bar, 1))) return r;
-    if ((r = dalloc(&w->err, 1))) return r;
-    if ((r = dalloc(&w->out, kOutWords))) return r;
-    if ((r = dalloc(&w->wstat, (size_t)kTraceCap * kTraceWords))) return r;
-    HIP_TRY(hipEventCreate(&w->ev0));
-    HIP_TRY(hipEventCreate(&w->ev1));
-    return MPAP_OK;
-}
-
-static int ws_queries(Workspace *w, int nq) {
-    if (nq <= w->nq_cap) return MPAP_OK;
-    int r;
-    dfree(w->qbeta); dfree(w->qnobj); dfree(w->qroot); dfree(w->qlast); dfree(w->g_laboff);
-    dfree(w->g_labcap); dfree(w->g_n); dfree(w->g_count);
-    if ((r = dalloc(&w->qbeta, nq)) || (r = dalloc(&w->qnobj, nq)) ||
-        (r = dalloc(&w->qroot, nq)) || (r = dalloc(&w->qlast, nq)) ||
-        (r = dalloc(&w->g_laboff, nq)) || (r = dalloc(&w->g_labcap, nq)) ||
-        (r = dalloc(&w->g_n, nq)) || (r = dalloc(&w->g_count, nq)))
-        return r;
-    if (!w->g_overflow && (r = dalloc(&w->g_overflow, 1))) return r;
-    w->nq_cap = nq;
-    return MPAP_OK;
-}
-
-static int ws_spill(Workspace *w, long long capG) {
-    if (capG <= w->spill_cap) return MPAP_OK;
-    int r;
-    dfree(w->spill);
-    dfree(w->spill_flags);
-    w->spill_cap = 0;
-    if ((r = dalloc(&w->spill, (size_t)w->nblocks * 2 * capG)) ||
-        (r = dalloc(&w->spill_flags, (size_t)w->nblocks * capG)))
-        return r;
-    w->spill_cap = capG;
-    return MPAP_OK;
-}
-
-static int ws_grow(Workspace *w, unsigned long long pool_cap, long long arena_cap,
-                   long long F_cap, long long goal_cap) {
-    int r;
-    if (pool_cap > w->pool_cap) {
-        dfree(w->pool);
-        if ((r = dalloc(&w->pool, pool_cap))) return r;
-        w->pool_cap = pool_cap;
-    }
-    if (arena_cap > w->arena_cap) {
-        dfree(w->arena);
-        if ((r = dalloc(&w->arena, arena_cap))) return r;
-        w->arena_cap = arena_cap;
-    }
-    if (F_cap > w->F_cap) {
-        dfree(w->F);
-        if ((r = dalloc(&w->F, F_cap))) return r;
-        w->F_cap = F_cap;
-    }
-    if (goal_cap > w->goal_cap) {
-        dfree(w->g_out); dfree(w->g_out_node);
-        if ((r = dalloc(&w->g_out, goal_cap))) return r;
-        if ((r = dalloc(&w->g_out_node, goal_cap))) return r;
-        w->goal_cap = goal_cap;
-    }
-    return MPAP_OK;
-}
-
-// ------------------------------------------------------------------ result
-struct mpap_result {
-    mpap_graph *g = nullptr;
-    Workspace *ws = nullptr;
-    int n_obj = 2;
-    // goal fronts of all queries, query q at [front_off[q], front_off[q+1])
-    std::vector<float4> front;
-    std::vector<int32_t> front_node;
-    std::vector<int64_t> front_off;
-    std::vector<int32_t> qlast;      // last wave that expanded a label of the query
-    std::vector<float> qlatency_ms;  // device time from launch start to that wave's end
-    std::vector<int64_t> trace;
-    mpap_stats stats{};
-    std::vector<int2> arena_host;  // filled on first mpap_label_path
-    bool arena_loaded = false;
-};
 
 extern "C" {
 
@@ -502,6 +228,11 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
     // the roadmap is symmetric (same cost, drift and collision result both
     // ways), so the in-edge lists are the out-edge lists
     g->rptr = g->optr; g->rsrc = g->ocol; g->rcost = g->ocost; g->rdrift = g->odrift;
+    // keep the environment for the surrogate's inputs
+    g->dim = dim; g->nbox = env->n_boxes; g->nblob = env->n_blobs;
+    g->check_step = gp->check_step; g->reset_q = gp->reset_q; g->radius = gp->radius;
+    g->pos = d_pos; g->bmu = d_mu; g->bsig = d_sig; g->bamp = d_amp;
+    d_pos = d_mu = d_sig = d_amp = nullptr;
     cleanup();
     if (hg == 0) {
         graph_release(g);
@@ -570,6 +301,9 @@ int mpap_graph_concat(const mpap_graph *const *parts, int32_t n_parts, void *str
     }
     g->qoff_h.assign(1, 0);
     g->qgoff_h.assign(1, 0);
+    bool all_sur = true;
+    for (int i = 0; i < n_parts; ++i) all_sur = all_sur && parts[i]->sdrift != nullptr;
+    if (all_sur && alias && (r = dalloc(&g->sdrift, e))) return bail(r);
     long long no = 0, eo = 0, go = 0;
     for (int i = 0; i < n_parts; ++i) {
         const mpap_graph *p = parts[i];
@@ -582,7 +316,8 @@ int mpap_graph_concat(const mpap_graph *const *parts, int32_t n_parts, void *str
             (r = cpy(g->ocost + eo, p->ocost, sizeof(float) * p->e)) ||
             (r = cpy(g->odrift + eo, p->odrift, sizeof(float) * p->e)) ||
             (r = cpy(g->nflag + no, p->nflag, p->n)) ||
-            (r = cpy(g->goal_list + go, p->goal_list, sizeof(int32_t) * p->n_goal)))
+            (r = cpy(g->goal_list + go, p->goal_list, sizeof(int32_t) * p->n_goal)) ||
+            (g->sdrift && (r = cpy(g->sdrift + eo, p->sdrift, sizeof(float) * p->e))))
             return bail(r);
         k_add_i32<<<std::max(1, div_up(p->n + 1, 256)), 256, 0, s>>>(g->optr + no, p->n + 1, (int)eo);
         if (p->e > 0) k_add_i32<<<div_up(p->e, 256), 256, 0, s>>>(g->ocol + eo, p->e, (int)no);
@@ -665,6 +400,10 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
         delta = std::min(delta, dq);
         max_waves = std::max(max_waves, p.max_waves);
         if (p.near_scan > 0) near_scan = p.near_scan;
+        if (p.heuristic != 0 && p.heuristic != 1)
+            return fail(MPAP_ERR_INVAL, "heuristic must be 0 (analytic) or 1 (surrogate)");
+        if (p.heuristic == 1 && (!g->sdrift || !g->symmetric_alias))
+            return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph (mpap_surrogate_score)");
         if (p.stage_cap > 0) stage_cap = p.stage_cap;
     }
     if (max_waves <= 0) max_waves = 1 << 18;
@@ -728,13 +467,18 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
     if ((r = ws_queries(w, nq))) return bail(r);
     {
         std::vector<float> hb(nq);
-        std::vector<int> hn(nq), hr(nq);
+        std::vector<int> hn(nq), hr(nq), hh(nq);
         for (int q = 0; q < nq; ++q) {
             const mpap_search_params &p = sp[nsp == 1 ? 0 : q];
             hb[q] = p.beta;
             hn[q] = p.n_obj;
             hr[q] = g->qoff_h[q] + p.init_node;
+            hh[q] = p.heuristic;
         }
+        res->qbeta = hb;
+        res->qnobj = hn;
+        res->qheur = hh;
+        HIP_TRY(hipMemcpyAsync(w->qheur, hh.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(w->qbeta, hb.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(w->qnobj, hn.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(w->qroot, hr.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
@@ -758,6 +502,7 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
         a = SearchArgs{};
         a.n = g->n; a.rptr = g->rptr; a.rsrc = g->rsrc; a.rcost = g->rcost;
         a.rdrift = g->rdrift; a.optr = g->optr; a.ocol = g->ocol; a.nflag = g->nflag;
+        a.sdrift = g->sdrift; a.qheur = w->qheur;
         a.nq = nq; a.qoff = g->qoff; a.qbeta = w->qbeta; a.qnobj = w->qnobj;
         a.qroot = w->qroot; a.qlast = w->qlast;
         a.delta = delta; a.max_waves = max_waves; a.near_scan = near_scan;
@@ -1017,7 +762,7 @@ void mpap_result_free(mpap_result *r) {
 
 }  // extern "C"
 
-static void graph_release(mpap_graph *g) {
+void graph_release(mpap_graph *g) {
     for (Workspace *w : g->spare) {
         w->free_all();
         delete w;
@@ -1028,5 +773,6 @@ static void graph_release(mpap_graph *g) {
     }
     dfree(g->optr); dfree(g->ocol); dfree(g->ocost); dfree(g->odrift);
     dfree(g->nflag); dfree(g->goal_list); dfree(g->qoff); dfree(g->qgoff);
+    dfree(g->pos); dfree(g->bmu); dfree(g->bsig); dfree(g->bamp); dfree(g->feat); dfree(g->sdrift);
     delete g;
 }

@@ -1,0 +1,288 @@
+// Internal host-runtime state shared by the C ABI implementation files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "graph_kernels.h"
+#include "mpap.h"
+#include "search_kernels.h"
+
+// ------------------------------------------------------------- error state
+extern thread_local std::string g_last_error;
+
+inline int fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? MPAP_ERR_NOMEM : MPAP_ERR_HIP,      \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+struct DeviceInfo {
+    int dev = -1;
+    int cus = 0;
+    int coop = 0;
+    size_t max_lds = 0;
+};
+
+inline int device_info(DeviceInfo *out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MPAP_ERR_DEVICE, std::string("libmpap is built for gfx950, device is ") +
+                                         prop.gcnArchName);
+    out->dev = dev;
+    out->cus = prop.multiProcessorCount;
+    int coop = 0;
+    HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    out->coop = coop;
+    out->max_lds = prop.sharedMemPerBlock;
+    if (!coop) return fail(MPAP_ERR_DEVICE, "device does not support cooperative launches");
+    return MPAP_OK;
+}
+
+template <typename T>
+inline int dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    HIP_TRY(hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)));
+    return MPAP_OK;
+}
+
+template <typename T>
+inline void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+constexpr int kTraceCap = 4096;  // waves recorded in the per-wave trace
+
+// exclusive scan of n int32 (device); tmp holds >= div_up(n, kScanTile) ints
+inline int scan_i32(const int *in, int *out, long long n, int *tmp, hipStream_t s) {
+    if (n <= 0) return MPAP_OK;
+    const int nb = div_up(n, kScanTile);
+    k_scan_block_sums<<<nb, 256, 0, s>>>(in, n, tmp);
+    k_scan_sums<<<1, 1024, 0, s>>>(tmp, nb);
+    k_scan_apply<<<nb, 256, 0, s>>>(in, n, tmp, out);
+    HIP_TRY(hipGetLastError());
+    return MPAP_OK;
+}
+
+
+// ------------------------------------------------------------------ graph
+struct Workspace;
+
+struct mpap_graph {
+    int dev = -1;
+    int32_t n = 0;
+    int64_t e = 0;
+    int32_t n_goal = 0;
+    bool symmetric_alias = false;  // in-edge arrays alias the out-edge ones
+    // forward CSR
+    int32_t *optr = nullptr, *ocol = nullptr;
+    float *ocost = nullptr, *odrift = nullptr;
+    // reverse CSR (in-edges)
+    int32_t *rptr = nullptr, *rsrc = nullptr;
+    float *rcost = nullptr, *rdrift = nullptr;
+    uint8_t *nflag = nullptr;
+    int32_t *goal_list = nullptr;
+    // query partition: query q owns nodes [qoff[q], qoff[q+1]) and goal list
+    // entries [qgoff[q], qgoff[q+1]); a plain roadmap is one query
+    int32_t nq = 1;
+    std::vector<int32_t> qoff_h, qgoff_h;
+    int32_t *qoff = nullptr, *qgoff = nullptr;
+    // environment of a roadmap built by mpap_build_graph (inputs of the
+    // surrogate's features); absent for imported and concatenated graphs
+    int dim = 0, nbox = 0, nblob = 0;
+    float check_step = 0.f, reset_q = 0.f, radius = 0.f;
+    float *pos = nullptr, *bmu = nullptr, *bsig = nullptr, *bamp = nullptr;
+    uint16_t *feat = nullptr;  // [E][16] bf16 surrogate inputs, computed on demand
+    float *sdrift = nullptr;   // [E] surrogate drift (forward edge order)
+    std::vector<Workspace *> spare;
+    std::mutex mu;
+};
+
+inline int graph_set_single_query(mpap_graph *g) {
+    g->nq = 1;
+    g->qoff_h = {0, g->n};
+    g->qgoff_h = {0, g->n_goal};
+    int r;
+    if ((r = dalloc(&g->qoff, 2)) || (r = dalloc(&g->qgoff, 2))) return r;
+    HIP_TRY(hipMemcpy(g->qoff, g->qoff_h.data(), 2 * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->qgoff, g->qgoff_h.data(), 2 * sizeof(int32_t), hipMemcpyHostToDevice));
+    return MPAP_OK;
+}
+
+void graph_release(mpap_graph *g);
+
+// ------------------------------------------------------------- workspace
+struct Workspace {
+    int32_t n = 0;
+    unsigned long long pool_cap = 0;
+    long long arena_cap = 0, F_cap = 0;
+    int nblocks = 0;
+    long long goal_cap = 0;
+    float4 *pool = nullptr;
+    unsigned *pool_top = nullptr;
+    int4 *nb = nullptr;
+    float *minopen = nullptr;
+    int *gcnt = nullptr;
+    int4 *fo = nullptr;
+    int *mark = nullptr;
+    int *alist = nullptr;
+    int *acnt = nullptr;
+    int *mcur = nullptr;
+    float4 *F = nullptr;
+    int2 *arena = nullptr;
+    long long *part_cnt = nullptr, *part_open = nullptr;
+    float *part_min = nullptr;
+    unsigned *bar = nullptr;
+    int *err = nullptr;
+    long long *out = nullptr;
+    long long *wstat = nullptr;
+    float4 *spill = nullptr;
+    uint8_t *spill_flags = nullptr;
+    long long spill_cap = 0;  // capG the spill space was sized for
+    // per query
+    int nq_cap = 0;
+    float *qbeta = nullptr;
+    int *qnobj = nullptr, *qroot = nullptr, *qlast = nullptr, *qheur = nullptr;
+    long long *g_laboff = nullptr;
+    int *g_labcap = nullptr;
+    int *g_overflow = nullptr;
+    // goal front
+    float4 *g_out = nullptr;
+    int *g_out_node = nullptr, *g_n = nullptr, *g_count = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    void free_all() {
+        dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
+        dfree(mark); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
+        dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out); dfree(wstat);
+        dfree(spill); dfree(spill_flags);
+        dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count);
+        dfree(qbeta); dfree(qnobj); dfree(qroot); dfree(qlast); dfree(qheur); dfree(g_laboff);
+        dfree(g_labcap); dfree(g_overflow);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        ev0 = ev1 = nullptr;
+    }
+};
+
+inline int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
+    int r;
+    w->n = n;
+    w->nblocks = nblocks;
+    if ((r = dalloc(&w->pool_top, 1))) return r;
+    if ((r = dalloc(&w->nb, n))) return r;
+    if ((r = dalloc(&w->minopen, n))) return r;
+    if ((r = dalloc(&w->gcnt, n))) return r;
+    if ((r = dalloc(&w->fo, n))) return r;
+    if ((r = dalloc(&w->mark, n))) return r;
+    if ((r = dalloc(&w->alist, n))) return r;
+    if ((r = dalloc(&w->acnt, 2))) return r;
+    if ((r = dalloc(&w->mcur, 2))) return r;
+    if ((r = dalloc(&w->part_cnt, 2 * (size_t)nblocks))) return r;
+    if ((r = dalloc(&w->part_open, 2 * (size_t)nblocks))) return r;
+    if ((r = dalloc(&w->part_min, 2 * (size_t)nblocks))) return r;
+    if ((r = dalloc(&w->bar, 1))) return r;
+    if ((r = dalloc(&w->err, 1))) return r;
+    if ((r = dalloc(&w->out, kOutWords))) return r;
+    if ((r = dalloc(&w->wstat, (size_t)kTraceCap * kTraceWords))) return r;
+    HIP_TRY(hipEventCreate(&w->ev0));
+    HIP_TRY(hipEventCreate(&w->ev1));
+    return MPAP_OK;
+}
+
+inline int ws_queries(Workspace *w, int nq) {
+    if (nq <= w->nq_cap) return MPAP_OK;
+    int r;
+    dfree(w->qbeta); dfree(w->qnobj); dfree(w->qroot); dfree(w->qlast); dfree(w->g_laboff);
+    dfree(w->g_labcap); dfree(w->g_n); dfree(w->g_count); dfree(w->qheur);
+    if ((r = dalloc(&w->qbeta, nq)) || (r = dalloc(&w->qnobj, nq)) || (r = dalloc(&w->qheur, nq)) ||
+        (r = dalloc(&w->qroot, nq)) || (r = dalloc(&w->qlast, nq)) ||
+        (r = dalloc(&w->g_laboff, nq)) || (r = dalloc(&w->g_labcap, nq)) ||
+        (r = dalloc(&w->g_n, nq)) || (r = dalloc(&w->g_count, nq)))
+        return r;
+    if (!w->g_overflow && (r = dalloc(&w->g_overflow, 1))) return r;
+    w->nq_cap = nq;
+    return MPAP_OK;
+}
+
+inline int ws_spill(Workspace *w, long long capG) {
+    if (capG <= w->spill_cap) return MPAP_OK;
+    int r;
+    dfree(w->spill);
+    dfree(w->spill_flags);
+    w->spill_cap = 0;
+    if ((r = dalloc(&w->spill, (size_t)w->nblocks * 2 * capG)) ||
+        (r = dalloc(&w->spill_flags, (size_t)w->nblocks * capG)))
+        return r;
+    w->spill_cap = capG;
+    return MPAP_OK;
+}
+
+inline int ws_grow(Workspace *w, unsigned long long pool_cap, long long arena_cap,
+                   long long F_cap, long long goal_cap) {
+    int r;
+    if (pool_cap > w->pool_cap) {
+        dfree(w->pool);
+        if ((r = dalloc(&w->pool, pool_cap))) return r;
+        w->pool_cap = pool_cap;
+    }
+    if (arena_cap > w->arena_cap) {
+        dfree(w->arena);
+        if ((r = dalloc(&w->arena, arena_cap))) return r;
+        w->arena_cap = arena_cap;
+    }
+    if (F_cap > w->F_cap) {
+        dfree(w->F);
+        if ((r = dalloc(&w->F, F_cap))) return r;
+        w->F_cap = F_cap;
+    }
+    if (goal_cap > w->goal_cap) {
+        dfree(w->g_out); dfree(w->g_out_node);
+        if ((r = dalloc(&w->g_out, goal_cap))) return r;
+        if ((r = dalloc(&w->g_out_node, goal_cap))) return r;
+        w->goal_cap = goal_cap;
+    }
+    return MPAP_OK;
+}
+
+// ------------------------------------------------------------------ result
+struct mpap_result {
+    mpap_graph *g = nullptr;
+    Workspace *ws = nullptr;
+    int n_obj = 2;
+    std::vector<float> qbeta;   // per-query bound
+    std::vector<int> qnobj;     // per-query objective count
+    std::vector<int> qheur;     // per-query heuristic (0 analytic, 1 surrogate)
+    // goal fronts of all queries, query q at [front_off[q], front_off[q+1])
+    std::vector<float4> front;
+    std::vector<int32_t> front_node;
+    std::vector<int64_t> front_off;
+    std::vector<int32_t> qlast;      // last wave that expanded a label of the query
+    std::vector<float> qlatency_ms;  // device time from launch start to that wave's end
+    std::vector<int64_t> trace;
+    mpap_stats stats{};
+    std::vector<int2> arena_host;  // filled on first mpap_label_path
+    bool arena_loaded = false;
+};
+

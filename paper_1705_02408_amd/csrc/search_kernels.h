@@ -57,6 +57,8 @@ struct SearchArgs {
     const float *qbeta;  // [nq]
     const int *qnobj;    // [nq]
     const int *qroot;    // [nq] global node id of x_init
+    const int *qheur;    // [nq] 1: drift from the learned surrogate (sdrift)
+    const float *sdrift; // surrogate drift, in-edge order (the roadmap is symmetric)
     int *qlast;          // [nq] last wave with a group label of the query
     float delta;         // lambda * r_n
     int max_waves;
@@ -109,6 +111,11 @@ struct GoalArgs {
 };
 
 __global__ void k_search_init(SearchArgs a);
+// analytic re-walk of labels' plans (surrogate check): out = {c, d, m, feasible}
+__global__ void k_rescore(const int2 *arena, const int *optr, const int *ocol,
+                          const float *ocost, const float *odrift, const uint8_t *nflag,
+                          const int *lab, const float *beta, const int *nobj, int n, int *path,
+                          int maxlen, float4 *out, int *err);
 __global__ void k_search_roots(SearchArgs a);
 __global__ void k_search(SearchArgs a);
 __global__ void k_count_front(SearchArgs a);

@@ -422,6 +422,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
     const int q = (a.nq > 1) ? query_of(a, x) : 0;
     const float beta = a.qbeta[q];
     const bool three = a.qnobj[q] >= 3;
+    const float *edrift = a.qheur[q] ? a.sdrift : a.rdrift;
     const int e0 = a.rptr[x], e1 = a.rptr[x + 1];
     bool changed = false;
     for (int t0 = e0; t0 < e1; t0 += blockDim.x) {
@@ -436,7 +437,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                 cnt = fu.y;
                 off = fu.x;
                 ce = a.rcost[e];
-                de = a.rdrift[e];
+                de = edrift[e];
             }
         }
         int tot;
@@ -782,4 +783,52 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
         if (threadIdx.x == 0) g.out_count[q] = nB;
         __syncthreads();
     }
+}
+
+// Re-walk the plan of each label with the analytic per-edge drift (the check
+// of a search run on the learned surrogate's drift): thread i follows the
+// parent chain of label lab[i] back to its root, then folds cost, drift
+// (bound on the pre-reset drift, relocalisation) and max drift forward.
+__global__ void __launch_bounds__(256) k_rescore(const int2 *arena, const int *optr,
+                                                 const int *ocol, const float *ocost,
+                                                 const float *odrift, const uint8_t *nflag,
+                                                 const int *lab, const float *beta,
+                                                 const int *nobj, int n, int *path, int maxlen,
+                                                 float4 *out, int *err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int *pth = path + (size_t)i * maxlen;
+    int len = 0;
+    int id = lab[i];
+    while (id >= 0 && len < maxlen) {
+        const int2 r = arena[id];
+        pth[len++] = r.x;
+        id = r.y;
+    }
+    if (id >= 0) {
+        atomicOr(err, 1);
+        out[i] = make_float4(MPAP_INF, MPAP_INF, MPAP_INF, 0.f);
+        return;
+    }
+    float c = 0.f, d = 0.f, m = 0.f;
+    bool ok = true;
+    for (int k = len - 1; k > 0; --k) {
+        const int u = pth[k], v = pth[k - 1];
+        int lo = optr[u], hi = optr[u + 1];
+        while (lo < hi) {  // targets of a row are sorted
+            const int mid = (lo + hi) >> 1;
+            if (ocol[mid] < v) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= optr[u + 1] || ocol[lo] != v) {
+            atomicOr(err, 2);
+            ok = false;
+            break;
+        }
+        c = c + ocost[lo];
+        const float dpre = d + odrift[lo];
+        ok = ok && (dpre <= beta[i]);
+        d = (nflag[v] & 1u) ? 0.0f : dpre;
+        m = (nobj[i] >= 3) ? fmaxf(m, dpre) : 0.0f;
+    }
+    out[i] = make_float4(c, d, m, ok ? 1.f : 0.f);
 }

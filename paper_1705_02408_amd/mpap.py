@@ -50,7 +50,8 @@ class mpap_search_params(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_float), ("lambda_", ctypes.c_float),
                 ("radius", ctypes.c_float), ("n_obj", ctypes.c_int32),
                 ("init_node", ctypes.c_int32), ("max_waves", ctypes.c_int32),
-                ("near_scan", ctypes.c_int32), ("stage_cap", ctypes.c_int32)]
+                ("near_scan", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
+                ("heuristic", ctypes.c_int32)]
 
 
 class mpap_stats(ctypes.Structure):
@@ -68,6 +69,10 @@ SYMBOLS = [
     "mpap_label_path", "mpap_result_stats", "mpap_result_free", "mpap_status_string",
     "mpap_last_error", "mpap_wave_trace", "mpap_graph_concat", "mpap_graph_queries",
     "mpap_search_batch", "mpap_query_goal_front", "mpap_query_info",
+    "mpap_surrogate_create", "mpap_surrogate_free", "mpap_surrogate_set_params",
+    "mpap_surrogate_get_params", "mpap_surrogate_init", "mpap_edge_features",
+    "mpap_surrogate_forward", "mpap_surrogate_gradient", "mpap_surrogate_train",
+    "mpap_surrogate_score", "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
 ]
 
 _lib = None
@@ -105,6 +110,20 @@ def load(path: str = LIB_PATH):
     lib.mpap_search_batch.argtypes = [P, P, I32, P, ctypes.POINTER(P)]
     lib.mpap_query_goal_front.argtypes = [P, I32, P, P, P, P, P, I32, P]
     lib.mpap_query_info.argtypes = [P, I32, P, P]
+    lib.mpap_surrogate_create.argtypes = [ctypes.POINTER(P)]
+    lib.mpap_surrogate_free.argtypes = [P]
+    lib.mpap_surrogate_free.restype = None
+    lib.mpap_surrogate_set_params.argtypes = [P, P, I32]
+    lib.mpap_surrogate_get_params.argtypes = [P, P, I32, P]
+    lib.mpap_surrogate_init.argtypes = [P, ctypes.c_uint64]
+    lib.mpap_edge_features.argtypes = [P, P, P, I64]
+    lib.mpap_surrogate_forward.argtypes = [P, P, I64, P]
+    lib.mpap_surrogate_gradient.argtypes = [P, P, P, I32, P, P]
+    lib.mpap_surrogate_train.argtypes = [P, P, P, I64, I32, I32, ctypes.c_float, P, P]
+    lib.mpap_surrogate_score.argtypes = [P, P, P, P]
+    lib.mpap_graph_drift.argtypes = [P, I32, P]
+    lib.mpap_analytic_drift.argtypes = [P, P, P]
+    lib.mpap_rescore_front.argtypes = [P, I32, P, P, P, P, I32, P]
     lib.mpap_result_free.argtypes = [P]
     lib.mpap_result_free.restype = None
     lib.mpap_status_string.argtypes = [ctypes.c_int]
@@ -115,7 +134,11 @@ def load(path: str = LIB_PATH):
                  "mpap_graph_export", "mpap_search", "mpap_goal_front", "mpap_node_front",
                  "mpap_label_path", "mpap_result_stats", "mpap_wave_trace",
                  "mpap_graph_concat", "mpap_graph_queries", "mpap_search_batch",
-                 "mpap_query_goal_front", "mpap_query_info"):
+                 "mpap_query_goal_front", "mpap_query_info", "mpap_surrogate_create",
+                 "mpap_surrogate_set_params", "mpap_surrogate_get_params",
+                 "mpap_surrogate_init", "mpap_edge_features", "mpap_surrogate_forward",
+                 "mpap_surrogate_gradient", "mpap_surrogate_train", "mpap_surrogate_score",
+                 "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -271,16 +294,18 @@ class Result:
 
 def search_params(beta: float, n_obj: int, radius: float, lam: float = 0.5,
                   init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
-                  stage_cap: int = 0):
+                  stage_cap: int = 0, heuristic: int = 0):
     return mpap_search_params(float(beta), float(lam), float(radius), int(n_obj),
-                              int(init_node), int(max_waves), int(near_scan), int(stage_cap))
+                              int(init_node), int(max_waves), int(near_scan), int(stage_cap),
+                              int(heuristic))
 
 
 def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float = 0.5,
                 init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
-                stage_cap: int = 0, stream=None) -> Result:
+                stage_cap: int = 0, heuristic: int = 0, stream=None) -> Result:
     lib = load()
-    sp = search_params(beta, n_obj, radius, lam, init_node, max_waves, near_scan, stage_cap)
+    sp = search_params(beta, n_obj, radius, lam, init_node, max_waves, near_scan, stage_cap,
+                       heuristic)
     h = ctypes.c_void_p()
     _check(lib.mpap_search(graph.handle, ctypes.byref(sp), _stream(stream), ctypes.byref(h)))
     return Result(h, graph)
@@ -395,3 +420,123 @@ def mpap_wave_trace(res: Result) -> np.ndarray:
     out = np.zeros((w.value, 10), np.int64)
     _check(lib.mpap_wave_trace(res.handle, _p(out), w.value, ctypes.byref(w)))
     return out
+
+
+N_PARAMS = 5313
+
+
+class Surrogate:
+    """Owner of an mpap_surrogate handle (the learned per-edge drift model)."""
+
+    def __init__(self, seed=None):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.mpap_surrogate_create(ctypes.byref(h)))
+        self.handle = h
+        if seed is not None:
+            _check(lib.mpap_surrogate_init(self.handle, ctypes.c_uint64(int(seed))))
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32).reshape(-1)
+        _check(load().mpap_surrogate_set_params(self.handle, _p(p), p.shape[0]))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(N_PARAMS, np.float32)
+        cnt = ctypes.c_int32()
+        _check(load().mpap_surrogate_get_params(self.handle, _p(out), N_PARAMS, ctypes.byref(cnt)))
+        return out
+
+    def forward(self, X_bits) -> np.ndarray:
+        X = np.ascontiguousarray(X_bits, np.uint16).reshape(-1, 16)
+        y = np.empty(X.shape[0], np.float32)
+        _check(load().mpap_surrogate_forward(self.handle, _p(X), X.shape[0], _p(y)))
+        return y
+
+    def gradient(self, X_bits, t):
+        X = np.ascontiguousarray(X_bits, np.uint16).reshape(-1, 16)
+        tt = np.ascontiguousarray(t, np.float32)
+        g = np.empty(N_PARAMS, np.float32)
+        y = np.empty(X.shape[0], np.float32)
+        _check(load().mpap_surrogate_gradient(self.handle, _p(X), _p(tt), X.shape[0], _p(g), _p(y)))
+        return g, y
+
+    def train(self, graph: Graph, edges, epochs: int, batch: int, lr: float, stream=None):
+        e = np.ascontiguousarray(edges, np.int64)
+        loss = np.zeros(max(epochs, 1), np.float32)
+        _check(load().mpap_surrogate_train(self.handle, graph.handle, _p(e), e.shape[0],
+                                           int(epochs), int(batch), ctypes.c_float(lr),
+                                           _stream(stream), _p(loss)))
+        return loss[:epochs]
+
+    def score(self, graph: Graph, stream=None) -> float:
+        ms = ctypes.c_float()
+        _check(load().mpap_surrogate_score(self.handle, graph.handle, _stream(stream),
+                                           ctypes.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if self.handle:
+            load().mpap_surrogate_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpap_edge_features(graph: Graph) -> np.ndarray:
+    e = graph.info()["e"]
+    out = np.empty((e, 16), np.uint16)
+    _check(load().mpap_edge_features(graph.handle, None, _p(out), out.size))
+    return out
+
+
+def mpap_analytic_drift(graph: Graph, stream=None) -> float:
+    """Recompute the analytic edge drift on the device; returns kernel ms."""
+    ms = ctypes.c_float()
+    _check(load().mpap_analytic_drift(graph.handle, _stream(stream), ctypes.byref(ms)))
+    return ms.value
+
+
+def mpap_graph_drift(graph: Graph, which: int) -> np.ndarray:
+    out = np.empty(graph.info()["e"], np.float32)
+    _check(load().mpap_graph_drift(graph.handle, int(which), _p(out)))
+    return out
+
+
+def mpap_rescore_front(res: Result, query: int = 0) -> dict:
+    lib = load()
+    cnt = ctypes.c_int32()
+    st = lib.mpap_rescore_front(res.handle, int(query), None, None, None, None, 0,
+                                ctypes.byref(cnt))
+    if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
+        _check(st)
+    k = cnt.value
+    c = np.empty(k, np.float32)
+    d = np.empty(k, np.float32)
+    m = np.empty(k, np.float32)
+    f = np.empty(k, np.uint8)
+    _check(lib.mpap_rescore_front(res.handle, int(query), _p(c), _p(d), _p(m), _p(f), k,
+                                  ctypes.byref(cnt)))
+    return dict(cost=c, drift=d, maxdrift=m, feasible=f.astype(bool))
+
+
+def surrogate_front_ok(res: Result, query: int, beta: float, tol: float = 1e-2) -> bool:
+    """Judge a search run on the surrogate's drift: every goal-front plan,
+    re-walked with the analytic drift, stays within the bound and its drift
+    (and max drift) differ from the surrogate's by at most tol relative to
+    max(analytic value, 1e-3 beta)."""
+    fr = mpap_query_goal_front(res, query)
+    rs = mpap_rescore_front(res, query)
+    if fr.vecs.shape[0] == 0:
+        return True
+    if not rs["feasible"].all():
+        return False
+    floor = 1e-3 * beta
+    for k, a in ((1, rs["drift"]), (2, rs["maxdrift"])):
+        err = np.abs(fr.vecs[:, k].astype(np.float64) - a) / np.maximum(a, floor)
+        if (err > tol).any():
+            return False
+    return True
