@@ -48,6 +48,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", choices=["plain3d", "plain2d", "batch"], default="plain3d")
     ap.add_argument("--queries", type=int, default=256, help="batch workload: query count")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed batches")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched serving measurement of the default run")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cpu-labels", type=int, default=150000,
                     help="labels the oracle makes permanent in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -190,15 +194,52 @@ def main():
         "cpu_baseline": cpu,
     }
     dg.close()
+    if not args.no_batch:
+        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+        out["batched_serving"] = measure_batch(args, log, with_surrogate=not args.no_surrogate)
     print(json.dumps(out), flush=True)
 
 
-def run_batch(args):
+def train_surrogates(seed: int, log):
+    """One surrogate per dimension, trained on roadmaps that are not part of
+    the measured batch (the largest query sizes, other seeds)."""
+    import numpy as np
+    from paper_1705_02408_amd import mpap, synth
+    models = {}
+    for dim, env in ((2, synth.make_env(10_000 + seed, 2, 50000, 20, 30, 20.0, 0.3, 2,
+                                        blob_amp=0.3)),
+                     (3, synth.make_env(20_000 + seed, 3, 30000, 100, 80, 40.0, 0.25, 2,
+                                        blob_amp=0.4))):
+        g = mpap.mpap_build_graph(env)
+        e = g.info()["e"]
+        n_train = min(1 << 20, (e // 4096) * 4096)
+        edges = np.random.default_rng(seed + dim).permutation(e)[:n_train]
+        s = mpap.Surrogate(seed=seed * 10 + dim)
+        t0 = time.perf_counter()
+        loss = s.train(g, edges, epochs=8, batch=4096, lr=2e-3)
+        dt = time.perf_counter() - t0
+        s.score(g)
+        ana = mpap.mpap_graph_drift(g, 0)
+        sur = mpap.mpap_graph_drift(g, 1)
+        held = np.setdiff1d(np.arange(e), edges)
+        rel = np.abs(sur[held] - ana[held]) / np.maximum(ana[held], 1e-3)
+        log(f"# surrogate {dim}D: {n_train} edges, {dt:.2f}s, loss {loss[0]:.4g} -> "
+            f"{loss[-1]:.4g}, held-out median rel err {np.median(rel):.4f} (n={held.size})")
+        models[dim] = dict(model=s, train_s=dt, loss_first=float(loss[0]),
+                           loss_last=float(loss[-1]), heldout_median_rel=float(np.median(rel)),
+                           n_train=int(n_train))
+        g.close()
+    return models
+
+
+def measure_batch(args, log, with_surrogate: bool = True):
     """Serving-style load: args.queries independent queries of uneven size in
-    one persistent launch; compared with the same queries searched one by one."""
+    one persistent launch, on the learned drift (judged by the analytic
+    re-walk, failing queries searched again on the analytic drift), against
+    the same queries searched one launch each on the analytic drift."""
     import numpy as np
     import torch
-    from paper_1705_02408_amd import mpap, synth
+    from paper_1705_02408_amd import autotune, mpap, synth
 
     t0 = time.perf_counter()
     envs, parts = [], []
@@ -212,78 +253,141 @@ def run_batch(args):
         except mpap.MpapError as ex:  # no sample in the goal ball: draw the next query
             if ex.status != mpap.MPAP_ERR_NOGOAL:
                 raise
-    union = mpap.mpap_graph_concat(parts)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    nq = len(envs)
+    # analytic precompute time (the drift the plain path uses)
+    ana_ms = sum(mpap.mpap_analytic_drift(p) for p in parts)
+    out = {"queries": nq, "build_s": build_s, "analytic_drift_ms": ana_ms}
+    models = None
+    sur_ms = 0.0
+    if with_surrogate:
+        models = train_surrogates(args.seed, log)
+        sur_ms = sum(models[e.dim]["model"].score(p) for e, p in zip(envs, parts))
+        out["surrogate"] = {f"{d}d": {k: v for k, v in m.items() if k != "model"}
+                            for d, m in models.items()}
+        out["surrogate_score_ms"] = sur_ms
+    union = mpap.mpap_graph_concat(parts)
     info = union.info()
-    print(f"# {len(parts)} roadmaps built on GPU in {build_s:.2f}s: {info}", file=sys.stderr,
-          flush=True)
-    params = [mpap.search_params(e.beta, e.n_obj, e.radius, e.lam) for e in envs]
+    log(f"# {nq} roadmaps ({info}) built in {build_s:.2f}s; analytic drift {ana_ms:.1f} ms, "
+        f"surrogate scoring {sur_ms:.1f} ms")
+    heur = 1 if with_surrogate else 0
+    params = [mpap.search_params(e.beta, e.n_obj, e.radius, e.lam, heuristic=heur) for e in envs]
+    # tune on the first 32 queries (the choice never changes a result)
+    sub = mpap.mpap_graph_concat(parts[:32])
+    t0 = time.perf_counter()
+    choice = autotune.tune(sub, params[:32], sorted({e.dim for e in envs}), 2, repeats=1,
+                           lambdas=(0.5, 1.0, 2.0), near_scans=(8, 16, 32), log=log)
+    sub.close()
+    log(f"# autotune {time.perf_counter() - t0:.1f}s")
+    params = autotune.apply(params, choice)
+    log(f"# autotuned: lambda {choice.lam}, near_scan {choice.near_scan} ({choice.tried})")
 
-    def step():
-        res = mpap.mpap_search_batch(union, params)
-        st = res.stats()
-        lat = [res.query_info(k)["latency_ms"] for k in range(len(envs))]
-        fronts = [res.goal_front(k).vecs.shape[0] for k in range(len(envs))]
-        res.close()
-        return st, lat, fronts
+    # the batch recorded once as a HIP graph: scoring of every roadmap by its
+    # surrogate, the persistent search, the goal fronts
+    t0 = time.perf_counter()
+    plan = mpap.Plan(union, params, parts=parts if with_surrogate else None,
+                     models=[models[e.dim]["model"] for e in envs] if with_surrogate else None)
+    log(f"# plan recorded in {time.perf_counter() - t0:.2f}s")
 
-    for i in range(args.warmup):
-        st, lat, fr = step()
-        print(f"# warmup {i}: {st}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    times, stats, lats = [], [], []
-    ts0 = time.perf_counter()
-    for i in range(args.steps):
+    def one_batch():
         ts = time.perf_counter()
-        st, lat, fr = step()
-        times.append(time.perf_counter() - ts)
+        res = plan.run()
+        st = res.stats()
+        ok = [True] * nq
+        if with_surrogate:
+            ok = mpap.surrogate_judge(res, [e.beta for e in envs])
+        lat = [res.query_info(k)["latency_ms"] for k in range(nq)]
+        res.close()
+        log(f"# batch: {time.perf_counter() - ts:.2f}s, kernel {st['gpu_ms']:.1f} ms, "
+            f"judge passed {sum(ok)}/{nq}")
+        fb_ms = 0.0
+        if not all(ok):
+            # the judge rejected some fronts: search those queries again on the
+            # analytic drift (same launch for all, surrogate kept for the rest)
+            p2 = [mpap.search_params(envs[k].beta, envs[k].n_obj, envs[k].radius, choice.lam,
+                                     near_scan=choice.near_scan,
+                                     heuristic=(heur if ok[k] else 0)) for k in range(nq)]
+            r2 = mpap.mpap_search_batch(union, p2)
+            fb_ms = r2.stats()["gpu_ms"]
+            r2.close()
+        return time.perf_counter() - ts, st, lat, ok, fb_ms
+
+    for i in range(min(args.warmup, 1)):
+        one_batch()
+    torch.cuda.synchronize()
+    walls, stats, lats, oks, fbs = [], [], [], [], []
+    for i in range(args.batch_steps):
+        w, st, lat, ok, fb = one_batch()
+        walls.append(w)
         stats.append(st)
         lats.append(lat)
+        oks.append(ok)
+        fbs.append(fb)
     torch.cuda.synchronize()
-    total = time.perf_counter() - ts0
-    nq = len(envs)
+    wall = statistics.mean(walls)
     X = stats[-1]["front_labels"]
     lat = np.array(lats[-1])
-    # the plain alternative: the same queries, one launch each
-    seq = []
-    for p, e in zip(parts, envs):
+    # plain: one launch per query, analytic drift
+    log("# plain: one launch per query")
+    seq = 0.0
+    Xp = 0
+    for k, (p, e) in enumerate(zip(parts, envs)):
         ts = time.perf_counter()
         r1 = mpap.mpap_search(p, e.beta, e.n_obj, e.radius, e.lam)
         r1.goal_front()
+        Xp += r1.stats()["front_labels"]
         r1.close()
-        seq.append(time.perf_counter() - ts)
-    seq_total = sum(seq)
+        seq += time.perf_counter() - ts
+        if (k + 1) % 64 == 0:
+            log(f"# plain: {k + 1}/{nq} queries, {seq:.1f}s")
     k_ms = statistics.mean(s_["gpu_ms"] for s_ in stats)
-    R = stats[-1]["relaxations"]
-    B = alg_bytes(X, R, 2)
-    out = {
-        "metric": "queries/s (batched, oracle-exact fronts)",
-        "value": nq * args.steps / total,
-        "unit": "queries/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1000.0 * total / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded generator), roadmaps built on the GPU",
-        "config": {"workload": f"batch of {nq} queries, 2D/3D even odds, sizes log-uniform "
-                               f"2000-50000 samples ({info['n']} nodes, {info['e']} edges), "
-                               f"two objectives", "queries_per_step": nq,
-                   "parallelism": "single GPU, one persistent launch"},
-        "label_expansions_per_s": X * args.steps / total,
+    B = alg_bytes(X, stats[-1]["relaxations"], 2)
+    out.update({
+        "queries_per_s": nq / wall,
+        "label_expansions_per_s": X / wall,
+        "step_wall_s": wall,
+        "judge_pass_fraction": float(np.mean(oks[-1])),
+        "fallback_ms": fbs[-1],
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
-        "plain_one_launch_per_query": {"queries_per_s": nq / seq_total,
-                                       "label_expansions_per_s": X / seq_total},
-        "search": {"X_front_labels": X, "R_relaxations": R, "waves": stats[-1]["waves"],
-                   "kernel_ms_mean": k_ms, "max_front": stats[-1]["max_front"]},
+        "plain_one_launch_per_query": {"queries_per_s": nq / seq,
+                                       "label_expansions_per_s": Xp / seq,
+                                       "wall_s": seq},
+        "speedup_vs_plain": (nq / wall) / (nq / seq),
+        "search": {"X_front_labels": X, "R_relaxations": stats[-1]["relaxations"],
+                   "waves": stats[-1]["waves"], "kernel_ms_mean": k_ms,
+                   "max_front": stats[-1]["max_front"], "nodes": info["n"], "edges": info["e"]},
         "roofline": {"bound": "hbm", "achieved": B / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": B / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "kernel": "k_search", "alg_bytes_per_launch": B},
-        "cpu_baseline": None,
-    }
+                     "unit": "GB/s", "frac": B / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "autotune": {"lambda": choice.lam, "near_scan": choice.near_scan},
+        "plan": plan.info(),
+    })
+    plan.close()
     union.close()
     for p in parts:
         p.close()
+    if models:
+        for m in models.values():
+            m["model"].close()
+    return out
+
+
+def run_batch(args):
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    b = measure_batch(args, log, with_surrogate=not args.no_surrogate)
+    out = {
+        "metric": "queries/s (batched, oracle-exact fronts)",
+        "value": b["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+        "steps": args.batch_steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * b["step_wall_s"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded generator)",
+        "config": {"workload": f"batch of {b['queries']} queries, 2D/3D even odds, sizes "
+                               f"log-uniform 2000-50000 samples, two objectives",
+                   "queries_per_step": b["queries"], "parallelism": "single GPU"},
+        "batched_serving": b, "roofline": dict(b["roofline"], traffic=None, kernel="k_search"),
+        "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -312,16 +312,58 @@ int mpap_analytic_drift(mpap_graph *g, void *stream, float *ms);
  * analytic values, 1 the surrogate's. */
 int mpap_graph_drift(const mpap_graph *g, int32_t which, float *out);
 
-/* Re-walk the plan of every goal-front label of one query with the analytic
- * drift of the roadmap (the surrogate's judge): cost, drift, max drift and
- * whether the pre-reset drift stays within the bound at every step.  Same
- * order and capacity rule as mpap_query_goal_front.  Any output may be NULL. */
+/* Re-walk the plan of every goal-front label of one query (query = -1: of
+ * all queries, concatenated in query order) with the analytic drift of the
+ * roadmap (the surrogate's judge): cost, drift, max drift and whether the
+ * pre-reset drift stays within the bound at every step.  Same order and
+ * capacity rule as mpap_query_goal_front; plans longer than 4096 steps are an
+ * error (MPAP_ERR_HIP).  Any output may be NULL. */
 int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *drift,
                        float *maxdrift, uint8_t *feasible, int32_t capacity, int32_t *count);
 
 /* ----------------------------------------------------------------- misc */
 const char *mpap_status_string(int status);
 const char *mpap_last_error(void);
+
+/*
+ * Plans: a fixed batch of queries (a graph from mpap_graph_concat, or one
+ * roadmap) recorded once as a HIP graph -- the surrogate scoring of each
+ * part, the persistent search of all queries and the goal-front extraction --
+ * and then launched with one call per batch (the serving loop of many
+ * independent queries; the search itself is Alg. 3 as in mpap_search).
+ */
+typedef struct mpap_plan mpap_plan;
+
+/* mpap_plan_create - validate as mpap_search_batch, run one eager search to
+ * size every capacity, and record the graph.  parts/models (nparts == 0, or
+ * nparts == the graph's query count): parts[q] is the roadmap query q was
+ * concatenated from and models[q] (nullable) the surrogate that scores it
+ * before each search, writing the part's slice of g's surrogate drift (used by
+ * queries with heuristic = 1).  g, the parts and the models must outlive the
+ * plan; the plan owns its own search workspace.  Errors: as
+ * mpap_search_batch, MPAP_ERR_INVAL (part sizes that do not match the
+ * queries, a scored part without an environment), MPAP_ERR_HIP (recording). */
+int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t n_params,
+                     mpap_graph *const *parts, const mpap_surrogate *const *models,
+                     int32_t nparts, void *stream, mpap_plan **out);
+
+/* mpap_plan_run - launch the recorded graph on `stream` and wait.  The result
+ * holds the goal fronts, statistics and latencies like mpap_search_batch's;
+ * its per-node fronts and plans (mpap_node_front, mpap_label_path,
+ * mpap_rescore_front) read the plan's workspace and stay valid until the next
+ * mpap_plan_run or mpap_plan_free of the same plan.  If the device reports a
+ * capacity overflow the batch is searched again eagerly (growing the
+ * workspace) and the graph recorded again; the result is the same.  Free the
+ * result with mpap_result_free.  A plan is not safe to run from two threads at
+ * once.  Errors: MPAP_ERR_HIP (also a grid-barrier timeout),
+ * MPAP_ERR_NOCONVERGE, MPAP_ERR_OVERFLOW. */
+int mpap_plan_run(mpap_plan *p, void *stream, mpap_result **out);
+
+/* mpap_plan_info - launches so far, graph recordings (1 + re-recordings after
+ * overflows) and eager fallbacks.  Outputs are nullable. */
+int mpap_plan_info(const mpap_plan *p, int32_t *launches, int32_t *records, int32_t *fallbacks);
+
+void mpap_plan_free(mpap_plan *p);
 
 #ifdef __cplusplus
 }

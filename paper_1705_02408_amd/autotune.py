@@ -56,10 +56,12 @@ def _time(graph, params, repeats: int) -> float:
 
 
 def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_CACHE,
-         repeats: int = 2, lambdas=LAMBDAS, near_scans=NEAR_SCANS, use_cache: bool = True) -> Choice:
+         repeats: int = 2, lambdas=LAMBDAS, near_scans=NEAR_SCANS, use_cache: bool = True,
+         log=None) -> Choice:
     """Pick (lambda, near_scan) for ``graph`` searched with ``base_params`` (one
     mpap_search_params, or one per query; their lambda/near_scan fields are
-    overridden).  Returns the choice; the cache is updated."""
+    overridden).  Returns the choice; the cache is updated.  ``log`` (optional)
+    receives one line per timed setting."""
     nodes = graph.info()["n"]
     key = workload_key(_device_name(), dims, n_obj, nodes)
     cache = {}
@@ -87,12 +89,16 @@ def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_
     for lam in lambdas:
         ms = _time(graph, with_(lam, 16), repeats)
         tried.append(dict(lam=lam, near_scan=16, kernel_ms=ms))
+        if log:
+            log(f"# autotune lambda {lam} near_scan 16: {ms:.1f} ms")
     best_lam = min(tried, key=lambda r: r["kernel_ms"])["lam"]
     for ns in near_scans:
         if ns == 16:
             continue
         ms = _time(graph, with_(best_lam, ns), repeats)
         tried.append(dict(lam=best_lam, near_scan=ns, kernel_ms=ms))
+        if log:
+            log(f"# autotune lambda {best_lam} near_scan {ns}: {ms:.1f} ms")
     best = min(tried, key=lambda r: r["kernel_ms"])
     choice = Choice(best["lam"], best["near_scan"], best["kernel_ms"], tried)
     if cache_path:

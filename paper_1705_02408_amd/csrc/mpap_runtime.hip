@@ -376,153 +376,193 @@ void mpap_graph_free(mpap_graph *g) {
 }
 
 // ----------------------------------------------------------------- search
-int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_t nsp,
-                      void *stream, mpap_result **out) {
-    if (!out) return fail(MPAP_ERR_INVAL, "out is null");
-    *out = nullptr;
-    if (!gc || !sp) return fail(MPAP_ERR_INVAL, "null graph or params");
-    mpap_graph *g = const_cast<mpap_graph *>(gc);
+}  // extern "C"
+
+int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, SearchPrep &p) {
     const int nq = g->nq;
     if (nsp != nq && nsp != 1)
         return fail(MPAP_ERR_INVAL, "need one parameter set per query (or one for all)");
-    float delta = __builtin_inff();
-    int max_waves = 0, near_scan = 16, stage_cap = 0;
+    p = SearchPrep{};
+    p.nq = nq;
+    p.delta = __builtin_inff();
     for (int q = 0; q < nsp; ++q) {
-        const mpap_search_params &p = sp[q];
+        const mpap_search_params &x = sp[q];
         const int qn = g->qoff_h[(nsp == 1 ? 0 : q) + 1] - g->qoff_h[nsp == 1 ? 0 : q];
-        if (p.n_obj != 2 && p.n_obj != 3) return fail(MPAP_ERR_INVAL, "n_obj must be 2 or 3");
-        if (p.init_node < 0 || p.init_node >= qn) return fail(MPAP_ERR_INVAL, "init_node out of range");
-        if (!(p.lambda > 0.0f) || !(p.radius > 0.0f) || std::isnan(p.beta))
+        if (x.n_obj != 2 && x.n_obj != 3) return fail(MPAP_ERR_INVAL, "n_obj must be 2 or 3");
+        if (x.init_node < 0 || x.init_node >= qn) return fail(MPAP_ERR_INVAL, "init_node out of range");
+        if (!(x.lambda > 0.0f) || !(x.radius > 0.0f) || std::isnan(x.beta))
             return fail(MPAP_ERR_INVAL, "lambda and radius must be > 0, beta not NaN");
-        const float dq = p.lambda * p.radius;
+        const float dq = x.lambda * x.radius;
         if (!(dq > 0.0f) || !std::isfinite(dq))
             return fail(MPAP_ERR_INVAL, "lambda * radius must be finite and > 0");
-        delta = std::min(delta, dq);
-        max_waves = std::max(max_waves, p.max_waves);
-        if (p.near_scan > 0) near_scan = p.near_scan;
-        if (p.heuristic != 0 && p.heuristic != 1)
+        p.delta = std::min(p.delta, dq);
+        p.max_waves = std::max(p.max_waves, x.max_waves);
+        if (x.near_scan > 0) p.near_scan = x.near_scan;
+        if (x.heuristic != 0 && x.heuristic != 1)
             return fail(MPAP_ERR_INVAL, "heuristic must be 0 (analytic) or 1 (surrogate)");
-        if (p.heuristic == 1 && (!g->sdrift || !g->symmetric_alias))
-            return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph (mpap_surrogate_score)");
-        if (p.stage_cap > 0) stage_cap = p.stage_cap;
+        if (x.heuristic == 1 && !g->symmetric_alias)
+            return fail(MPAP_ERR_INVAL, "the surrogate drift needs a symmetric roadmap");
+        if (x.stage_cap > 0) p.stage_cap = x.stage_cap;
     }
-    if (max_waves <= 0) max_waves = 1 << 18;
+    if (p.max_waves <= 0) p.max_waves = 1 << 18;
     if (nsp == 1 && nq > 1) {
         for (int q = 1; q < nq; ++q)
             if (sp[0].init_node >= g->qoff_h[q + 1] - g->qoff_h[q])
                 return fail(MPAP_ERR_INVAL, "init_node out of range for a query");
     }
+    p.beta.resize(nq);
+    p.nobj.resize(nq);
+    p.root.resize(nq);
+    p.heur.resize(nq);
+    for (int q = 0; q < nq; ++q) {
+        const mpap_search_params &x = sp[nsp == 1 ? 0 : q];
+        p.beta[q] = x.beta;
+        p.nobj[q] = x.n_obj;
+        p.root[q] = g->qoff_h[q] + x.init_node;
+        p.heur[q] = x.heuristic;
+    }
+    return MPAP_OK;
+}
+
+int search_shape(int stage_cap, SearchShape &L) {
     DeviceInfo di;
     int r = device_info(&di);
     if (r) return r;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-
-    // launch shape: 1024-thread blocks, LDS staging sized from the device limit
-    const int threads = 1024;
-    const int capC = 1024;  // a power of two, a multiple of the block size
-    const size_t fixed = 16 * (size_t)capC + 16 * (size_t)threads + 8 * (size_t)capC + 128 +
-                         32 + capC;
+    // 1024-thread blocks, LDS staging sized from the device limit
+    L.threads = 1024;
+    L.capC = 1024;  // a power of two, a multiple of the block size
+    const size_t fixed = 16 * (size_t)L.capC + 16 * (size_t)L.threads + 8 * (size_t)L.capC +
+                         128 + 32 + L.capC;
     // leave 1 KiB for the kernel's static LDS
-    size_t lds_budget = std::min<size_t>(di.max_lds, 160 * 1024) - 1024;
+    const size_t lds_budget = std::min<size_t>(di.max_lds, 160 * 1024) - 1024;
     int capB = (int)((lds_budget - fixed) / 17);
-    capB = std::min(capB, 8 * threads);
+    capB = std::min(capB, 8 * L.threads);
     capB -= capB % 64;
     if (capB < 256) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
-    const size_t lds = fixed + 17 * (size_t)capB;
+    L.lds = fixed + 17 * (size_t)capB;
     if (stage_cap > 0) capB = std::min(capB, std::max(stage_cap, 1));
+    L.capB = capB;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search, threads, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search, L.threads, L.lds));
     if (per_cu < 1) return fail(MPAP_ERR_DEVICE, "search kernel does not fit on a CU");
-    int nblocks = di.cus * std::min(per_cu, 2);
+    L.nblocks = di.cus * std::min(per_cu, 2);
+    return MPAP_OK;
+}
 
-    Workspace *w = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g->mu);
-        if (!g->spare.empty()) {
-            w = g->spare.back();
-            g->spare.pop_back();
-        }
-    }
-    if (w && w->nblocks != nblocks) {
-        w->free_all();
-        delete w;
-        w = nullptr;
-    }
-    if (!w) {
-        w = new Workspace();
-        if ((r = ws_alloc_nodes(w, g->n, nblocks))) {
-            w->free_all();
-            delete w;
-            return r;
-        }
-    }
-    mpap_result *res = new mpap_result();
-    res->g = g;
-    res->ws = w;
-    res->n_obj = sp[0].n_obj;
-    auto bail = [&](int st) {
-        mpap_result_free(res);
-        return st;
-    };
-    if ((r = ws_queries(w, nq))) return bail(r);
-    {
-        std::vector<float> hb(nq);
-        std::vector<int> hn(nq), hr(nq), hh(nq);
+int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s) {
+    int r;
+    if ((r = ws_queries(w, p.nq))) return r;
+    const size_t nq = p.nq;
+    HIP_TRY(hipMemcpyAsync(w->qheur, p.heur.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qbeta, p.beta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qnobj, p.nobj.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qroot, p.root.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MPAP_OK;
+}
+
+SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
+                       const SearchShape &L) {
+    SearchArgs a{};
+    a.n = g->n; a.rptr = g->rptr; a.rsrc = g->rsrc; a.rcost = g->rcost;
+    a.rdrift = g->rdrift; a.optr = g->optr; a.ocol = g->ocol; a.nflag = g->nflag;
+    a.sdrift = g->sdrift; a.qheur = w->qheur;
+    a.nq = p.nq; a.qoff = g->qoff; a.qbeta = w->qbeta; a.qnobj = w->qnobj;
+    a.qroot = w->qroot; a.qlast = w->qlast;
+    a.delta = p.delta; a.max_waves = p.max_waves; a.near_scan = p.near_scan;
+    a.capB = L.capB; a.capC = L.capC; a.nblocks = L.nblocks;
+    a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
+    a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
+    a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
+    a.arena = w->arena; a.arena_cap = std::min<long long>(w->arena_cap, 0x7ffffff0ll);
+    a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_min = w->part_min;
+    a.bar = w->bar; a.err = w->err; a.out = w->out;
+    a.wstat = w->wstat; a.wstat_cap = kTraceCap;
+    a.spill = w->spill; a.spill_flags = w->spill_flags; a.capG = (int)w->spill_cap;
+    return a;
+}
+
+GoalArgs goal_args(const mpap_graph *g, Workspace *w) {
+    GoalArgs ga{};
+    ga.nq = g->nq; ga.qgoff = g->qgoff; ga.goal_list = g->goal_list;
+    ga.lab_off = w->g_laboff; ga.lab_cap = w->g_labcap;
+    ga.out_lab = w->g_out; ga.out_node = w->g_out_node; ga.out_count = w->g_count;
+    ga.overflow = w->g_overflow;
+    return ga;
+}
+
+void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_out,
+                   const int *counts, const float4 *plab, const int *pnode, const int *qlast,
+                   const long long *trace, float ms, int retries, const SearchShape &L) {
+    const mpap_graph *g = res->g;
+    const int nq = p.nq;
+    res->n_obj = p.nobj.empty() ? 2 : p.nobj[0];
+    res->qbeta = p.beta;
+    res->qnobj = p.nobj;
+    res->qheur = p.heur;
+    res->front_off.assign(nq + 1, 0);
+    for (int q = 0; q < nq; ++q) res->front_off[q + 1] = res->front_off[q] + counts[q];
+    const long long tot = res->front_off[nq];
+    res->front.assign(plab, plab + tot);
+    res->front_node.assign(pnode, pnode + tot);
+    // global goal node ids -> ids within the query
+    for (int q = 0; q < nq; ++q)
+        for (long long i = res->front_off[q]; i < res->front_off[q + 1]; ++i)
+            res->front_node[i] -= g->qoff_h[q];
+    res->qlast.assign(qlast, qlast + nq);
+    res->stats.waves = (int32_t)dev_out[kOutWaves];
+    res->stats.retries = retries;
+    res->stats.labels_expanded = dev_out[kOutLabels];
+    res->stats.front_labels = dev_out[kOutFront];
+    res->stats.merges = dev_out[kOutMerges];
+    res->stats.candidates = dev_out[kOutCandidates];
+    res->stats.relaxations = dev_out[kOutRelax];
+    res->stats.lds_front_cap = L.capB;
+    res->stats.max_front = (int32_t)dev_out[kOutMaxFront];
+    res->stats.blocks = L.nblocks;
+    res->stats.gpu_ms = ms;
+    // per-query latency from the per-wave device clock (100 MHz)
+    const int tw = std::min<int>(res->stats.waves, kTraceCap);
+    res->trace.assign(trace, trace + (size_t)tw * kTraceWords);
+    res->qlatency_ms.assign(nq, ms);
+    if (tw > 0) {
+        const int64_t t0 = res->trace[kTrStart];
         for (int q = 0; q < nq; ++q) {
-            const mpap_search_params &p = sp[nsp == 1 ? 0 : q];
-            hb[q] = p.beta;
-            hn[q] = p.n_obj;
-            hr[q] = g->qoff_h[q] + p.init_node;
-            hh[q] = p.heuristic;
+            const int lw = res->qlast[q];
+            if (lw >= 0 && lw < tw && res->trace[(size_t)lw * kTraceWords + kTrMerged] > 0)
+                res->qlatency_ms[q] =
+                    (float)((res->trace[(size_t)lw * kTraceWords + kTrMerged] - t0) * 1e-5);
         }
-        res->qbeta = hb;
-        res->qnobj = hn;
-        res->qheur = hh;
-        HIP_TRY(hipMemcpyAsync(w->qheur, hh.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(w->qbeta, hb.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(w->qnobj, hn.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(w->qroot, hr.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
     }
+}
 
+int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Workspace *w,
+                 hipStream_t s, mpap_result *res) {
+    const int nq = p.nq;
+    int r;
+    if ((r = search_upload(w, p, s))) return r;
     // first guesses; a workspace keeps what earlier searches needed
     unsigned long long pool_cap = std::max<unsigned long long>(w->pool_cap, 256ull * g->n + 65536);
     long long arena_cap = std::max<long long>(w->arena_cap, 128ll * g->n + 65536);
     long long F_cap = std::max<long long>(w->F_cap, 32ll * g->n + 65536);
     pool_cap = std::min<unsigned long long>(pool_cap, (1ull << 31) - 1);
-    long long capG = std::max<long long>(w->spill_cap, std::max(4 * capB, 32768));
+    long long capG = std::max<long long>(w->spill_cap, std::max(4 * L.capB, 32768));
     long long dev_out[kOutWords];
     int dev_err = 0;
     int retries = 0;
     float ms = 0.f;
     SearchArgs a{};
     for (;;) {
-        if ((r = ws_grow(w, pool_cap, arena_cap, F_cap, 0))) return bail(r);
-        if ((r = ws_spill(w, capG))) return bail(r);
-        a = SearchArgs{};
-        a.n = g->n; a.rptr = g->rptr; a.rsrc = g->rsrc; a.rcost = g->rcost;
-        a.rdrift = g->rdrift; a.optr = g->optr; a.ocol = g->ocol; a.nflag = g->nflag;
-        a.sdrift = g->sdrift; a.qheur = w->qheur;
-        a.nq = nq; a.qoff = g->qoff; a.qbeta = w->qbeta; a.qnobj = w->qnobj;
-        a.qroot = w->qroot; a.qlast = w->qlast;
-        a.delta = delta; a.max_waves = max_waves; a.near_scan = near_scan;
-        a.capB = capB; a.capC = capC; a.nblocks = nblocks;
-        a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
-        a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
-        a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
-        a.arena = w->arena; a.arena_cap = std::min<long long>(w->arena_cap, 0x7ffffff0ll);
-        a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_min = w->part_min;
-        a.bar = w->bar; a.err = w->err; a.out = w->out;
-        a.wstat = w->wstat; a.wstat_cap = kTraceCap;
-        a.spill = w->spill; a.spill_flags = w->spill_flags; a.capG = (int)capG;
-
+        if ((r = ws_grow(w, pool_cap, arena_cap, F_cap, 0))) return r;
+        if ((r = ws_spill(w, capG))) return r;
+        a = search_args(g, w, p, L);
         k_search_init<<<div_up(g->n, 256), 256, 0, s>>>(a);
         k_search_roots<<<div_up(nq, 256), 256, 0, s>>>(a);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(w->ev0, s));
         void *kargs[] = {&a};
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search),
-                                           dim3(nblocks), dim3(threads), kargs, lds, s));
+                                           dim3(L.nblocks), dim3(L.threads), kargs, L.lds, s));
         HIP_TRY(hipEventRecord(w->ev1, s));
         k_count_front<<<std::max(1, std::min(div_up(g->n, 256), 1024)), 256, 0, s>>>(a);
         HIP_TRY(hipGetLastError());
@@ -533,18 +573,18 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
         const int status = (int)dev_out[kOutStatus];
         if (status == kStatusOk && dev_err == 0) break;
         if (dev_err & kErrTimeout)
-            return bail(fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)"));
+            return fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)");
         if (status == kStatusNoConverge)
-            return bail(fail(MPAP_ERR_NOCONVERGE, "max_waves reached with open plans"));
-        if (++retries > 12) return bail(fail(MPAP_ERR_OVERFLOW, "capacity retries exhausted"));
+            return fail(MPAP_ERR_NOCONVERGE, "max_waves reached with open plans");
+        if (++retries > 12) return fail(MPAP_ERR_OVERFLOW, "capacity retries exhausted");
         if (dev_err & kErrBucket) {
             if (capG >= (1ll << 22))
-                return bail(fail(MPAP_ERR_OVERFLOW, "a per-node front exceeds 2^22 labels"));
+                return fail(MPAP_ERR_OVERFLOW, "a per-node front exceeds 2^22 labels");
             capG *= 4;
         }
         if (dev_err & kErrPool) {
             if (w->pool_cap >= (1ull << 31) - 1)
-                return bail(fail(MPAP_ERR_OVERFLOW, "bucket pool beyond 2^31 labels"));
+                return fail(MPAP_ERR_OVERFLOW, "bucket pool beyond 2^31 labels");
             pool_cap = std::min<unsigned long long>(pool_cap * 4, (1ull << 31) - 1);
         }
         if (status == kStatusArena) {
@@ -553,91 +593,104 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
         }
     }
 
-    // goal fronts (a7): query q writes its front to [lab_off[q], + lab_cap[q])
+    // goal fronts (a7): exact per-query regions, the fronts, then packed
+    std::vector<int> counts(nq, 0), qlast(nq, 0);
     {
-        const long long mf = std::max<long long>(dev_out[kOutMaxFront], 1);
-        std::vector<long long> laboff(nq);
-        std::vector<int> labcap(nq);
-        long long tot = 0;
-        for (int q = 0; q < nq; ++q) {
-            const long long c = (long long)(g->qgoff_h[q + 1] - g->qgoff_h[q]) * mf;
-            laboff[q] = tot;
-            labcap[q] = (int)std::min<long long>(c, 0x7fffffff);
-            tot += labcap[q];
-        }
-        if ((r = ws_grow(w, 0, 0, 0, std::max<long long>(tot, 1)))) return bail(r);
-        HIP_TRY(hipMemcpyAsync(w->g_laboff, laboff.data(), sizeof(long long) * nq,
-                               hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(w->g_labcap, labcap.data(), sizeof(int) * nq,
-                               hipMemcpyHostToDevice, s));
-        std::vector<int> counts(nq, 0);
-        int ovf = 0, gerr = 0;
-        if (tot > 0) {
-            GoalArgs ga{};
-            ga.nq = nq; ga.qgoff = g->qgoff; ga.goal_list = g->goal_list;
-            ga.lab_off = w->g_laboff; ga.lab_cap = w->g_labcap;
-            ga.out_lab = w->g_out; ga.out_node = w->g_out_node; ga.out_count = w->g_count;
-            ga.overflow = w->g_overflow;
-            k_zero_i32<<<div_up(nq, 256), 256, 0, s>>>(w->g_count, nq);
-            k_zero_i32<<<1, 32, 0, s>>>(w->g_overflow, 1);
-            k_goal_front<<<std::min(nq, nblocks), threads, lds, s>>>(a, ga);
-            HIP_TRY(hipGetLastError());
-            HIP_TRY(hipMemcpyAsync(counts.data(), w->g_count, sizeof(int) * nq,
-                                   hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(&gerr, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (ovf || gerr) return bail(fail(MPAP_ERR_OVERFLOW, "goal front overflow"));
-        }
-        res->front_off.assign(nq + 1, 0);
-        for (int q = 0; q < nq; ++q) res->front_off[q + 1] = res->front_off[q] + counts[q];
-        res->front.resize(res->front_off[nq]);
-        res->front_node.resize(res->front_off[nq]);
-        for (int q = 0; q < nq; ++q) {
-            if (counts[q] == 0) continue;
-            HIP_TRY(hipMemcpyAsync(res->front.data() + res->front_off[q], w->g_out + laboff[q],
-                                   sizeof(float4) * counts[q], hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(res->front_node.data() + res->front_off[q],
-                                   w->g_out_node + laboff[q], sizeof(int32_t) * counts[q],
-                                   hipMemcpyDeviceToHost, s));
-        }
-        // global goal node ids -> ids within the query
-        res->qlast.resize(nq);
-        HIP_TRY(hipMemcpyAsync(res->qlast.data(), w->qlast, sizeof(int) * nq,
-                               hipMemcpyDeviceToHost, s));
+        GoalArgs ga = goal_args(g, w);
+        long long total = 0;
+        k_zero_i32<<<div_up(nq, 256), 256, 0, s>>>(w->g_count, nq);
+        k_zero_i32<<<1, 32, 0, s>>>(w->g_overflow, 1);
+        k_goal_bound<<<1, 1024, 0, s>>>(a, ga, 0x7fffffffffffffffll, w->g_total);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&total, w->g_total, sizeof(long long), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        for (int q = 0; q < nq; ++q)
-            for (long long i = res->front_off[q]; i < res->front_off[q + 1]; ++i)
-                res->front_node[i] -= g->qoff_h[q];
-    }
-    res->stats.waves = (int32_t)dev_out[kOutWaves];
-    res->stats.retries = retries;
-    res->stats.labels_expanded = dev_out[kOutLabels];
-    res->stats.front_labels = dev_out[kOutFront];
-    res->stats.merges = dev_out[kOutMerges];
-    res->stats.candidates = dev_out[kOutCandidates];
-    res->stats.relaxations = dev_out[kOutRelax];
-    res->stats.lds_front_cap = capB;
-    res->stats.max_front = (int32_t)dev_out[kOutMaxFront];
-    res->stats.blocks = nblocks;
-    res->stats.gpu_ms = ms;
-    // per-query latency from the per-wave device clock
-    {
-        const int tw = std::min<int>(res->stats.waves, kTraceCap);
-        res->trace.resize((size_t)tw * kTraceWords);
-        if (tw > 0)
-            HIP_TRY(hipMemcpy(res->trace.data(), w->wstat, sizeof(int64_t) * tw * kTraceWords,
-                              hipMemcpyDeviceToHost));
-        res->qlatency_ms.assign(nq, ms);
-        if (tw > 0) {
-            const int64_t t0 = res->trace[kTrStart];
-            for (int q = 0; q < nq; ++q) {
-                const int lw = res->qlast[q];
-                if (lw >= 0 && lw < tw && res->trace[(size_t)lw * kTraceWords + kTrMerged] > 0)
-                    res->qlatency_ms[q] =
-                        (float)((res->trace[(size_t)lw * kTraceWords + kTrMerged] - t0) * 1e-5);
-            }
+        if ((r = ws_grow(w, 0, 0, 0, std::max<long long>(total, 1)))) return r;
+        ga = goal_args(g, w);
+        int ovf = 0, gerr = 0;
+        if (total > 0) {
+            k_goal_front<<<std::min(nq, L.nblocks), L.threads, L.lds, s>>>(a, ga);
+            HIP_TRY(hipGetLastError());
         }
+        HIP_TRY(hipMemcpyAsync(counts.data(), w->g_count, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&gerr, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ovf || gerr) return fail(MPAP_ERR_OVERFLOW, "goal front overflow");
+        long long packed = 0;
+        for (int q = 0; q < nq; ++q) packed += counts[q];
+        if ((r = ws_pack(w, std::max<long long>(packed, 1)))) return r;
+        if (packed > 0) {
+            k_goal_pack<<<std::min(nq, 1024), 256, 0, s>>>(ga, w->p_lab, w->p_node, w->p_cap);
+            HIP_TRY(hipGetLastError());
+        }
+        std::vector<float4> plab(packed);
+        std::vector<int> pnode(packed);
+        if (packed > 0) {
+            HIP_TRY(hipMemcpyAsync(plab.data(), w->p_lab, sizeof(float4) * packed,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(pnode.data(), w->p_node, sizeof(int) * packed,
+                                   hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(hipMemcpyAsync(qlast.data(), w->qlast, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ovf) return fail(MPAP_ERR_OVERFLOW, "goal front pack overflow");
+        const int tw = std::min<int>((int)dev_out[kOutWaves], kTraceCap);
+        std::vector<long long> trace((size_t)std::max(tw, 0) * kTraceWords);
+        if (tw > 0)
+            HIP_TRY(hipMemcpy(trace.data(), w->wstat, sizeof(long long) * trace.size(),
+                              hipMemcpyDeviceToHost));
+        search_finish(res, p, dev_out, counts.data(), plab.data(), pnode.data(), qlast.data(),
+                      trace.data(), ms, retries, L);
+    }
+    return MPAP_OK;
+}
+
+extern "C" {
+
+int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_t nsp,
+                      void *stream, mpap_result **out) {
+    if (!out) return fail(MPAP_ERR_INVAL, "out is null");
+    *out = nullptr;
+    if (!gc || !sp) return fail(MPAP_ERR_INVAL, "null graph or params");
+    mpap_graph *g = const_cast<mpap_graph *>(gc);
+    SearchPrep p;
+    int r = search_prep(g, sp, nsp, p);
+    if (r) return r;
+    for (int q = 0; q < p.nq; ++q)
+        if (p.heur[q] == 1 && !g->sdrift)
+            return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph (mpap_surrogate_score)");
+    SearchShape L;
+    if ((r = search_shape(p.stage_cap, L))) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (!g->spare.empty()) {
+            w = g->spare.back();
+            g->spare.pop_back();
+        }
+    }
+    if (w && w->nblocks != L.nblocks) {
+        w->free_all();
+        delete w;
+        w = nullptr;
+    }
+    if (!w) {
+        w = new Workspace();
+        if ((r = ws_alloc_nodes(w, g->n, L.nblocks))) {
+            w->free_all();
+            delete w;
+            return r;
+        }
+    }
+    mpap_result *res = new mpap_result();
+    res->g = g;
+    res->ws = w;
+    if ((r = search_eager(g, p, L, w, s, res))) {
+        mpap_result_free(res);
+        return r;
     }
     *out = res;
     return MPAP_OK;
@@ -737,8 +790,7 @@ int mpap_wave_trace(const mpap_result *r, int64_t *out, int32_t capacity, int32_
     *waves = w;
     if (capacity < w) return fail(MPAP_ERR_CAPACITY, "capacity below the traced wave count");
     if (w > 0 && out)
-        HIP_TRY(hipMemcpy(out, r->ws->wstat, sizeof(int64_t) * kTraceWords * w,
-                          hipMemcpyDeviceToHost));
+        std::memcpy(out, r->trace.data(), sizeof(int64_t) * kTraceWords * w);
     return MPAP_OK;
 }
 
@@ -750,7 +802,9 @@ int mpap_result_stats(const mpap_result *r, mpap_stats *out) {
 
 void mpap_result_free(mpap_result *r) {
     if (!r) return;
-    if (r->ws && r->g) {
+    if (r->ws_borrowed) {
+        // the workspace belongs to a plan
+    } else if (r->ws && r->g) {
         std::lock_guard<std::mutex> lk(r->g->mu);
         r->g->spare.push_back(r->ws);
     } else if (r->ws) {

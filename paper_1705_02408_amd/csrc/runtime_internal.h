@@ -167,9 +167,13 @@ struct Workspace {
     long long *g_laboff = nullptr;
     int *g_labcap = nullptr;
     int *g_overflow = nullptr;
-    // goal front
+    // goal front: per-query regions, then packed densely in query order
     float4 *g_out = nullptr;
     int *g_out_node = nullptr, *g_n = nullptr, *g_count = nullptr;
+    long long *g_total = nullptr;
+    float4 *p_lab = nullptr;
+    int *p_node = nullptr;
+    long long p_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     void free_all() {
@@ -177,7 +181,8 @@ struct Workspace {
         dfree(mark); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
         dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out); dfree(wstat);
         dfree(spill); dfree(spill_flags);
-        dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count);
+        dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count); dfree(g_total);
+        dfree(p_lab); dfree(p_node);
         dfree(qbeta); dfree(qnobj); dfree(qroot); dfree(qlast); dfree(qheur); dfree(g_laboff);
         dfree(g_labcap); dfree(g_overflow);
         if (ev0) (void)hipEventDestroy(ev0);
@@ -206,6 +211,7 @@ inline int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     if ((r = dalloc(&w->err, 1))) return r;
     if ((r = dalloc(&w->out, kOutWords))) return r;
     if ((r = dalloc(&w->wstat, (size_t)kTraceCap * kTraceWords))) return r;
+    if ((r = dalloc(&w->g_total, 1))) return r;
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
     return MPAP_OK;
@@ -266,6 +272,17 @@ inline int ws_grow(Workspace *w, unsigned long long pool_cap, long long arena_ca
     return MPAP_OK;
 }
 
+inline int ws_pack(Workspace *w, long long cap) {
+    if (cap <= w->p_cap) return MPAP_OK;
+    int r;
+    dfree(w->p_lab);
+    dfree(w->p_node);
+    w->p_cap = 0;
+    if ((r = dalloc(&w->p_lab, cap)) || (r = dalloc(&w->p_node, cap))) return r;
+    w->p_cap = cap;
+    return MPAP_OK;
+}
+
 // ------------------------------------------------------------------ result
 struct mpap_result {
     mpap_graph *g = nullptr;
@@ -284,5 +301,41 @@ struct mpap_result {
     mpap_stats stats{};
     std::vector<int2> arena_host;  // filled on first mpap_label_path
     bool arena_loaded = false;
+    bool ws_borrowed = false;  // ws belongs to a plan (valid until its next run)
 };
+
+// ------------------------------------------------------ search preparation
+// Validated per-query parameters of one batched search.
+struct SearchPrep {
+    int nq = 0;
+    float delta = 0.f;
+    int max_waves = 0, near_scan = 16, stage_cap = 0;
+    std::vector<float> beta;
+    std::vector<int> nobj, root, heur;
+};
+// Launch shape of the persistent search kernel.
+struct SearchShape {
+    int threads = 1024, capC = 1024, capB = 0, nblocks = 0;
+    size_t lds = 0;
+};
+int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, SearchPrep &p);
+int search_shape(int stage_cap, SearchShape &L);
+// Uploads the per-query parameters into w (synchronous).
+int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s);
+// The search with capacity growth and retries, goal fronts and statistics,
+// eagerly on stream s into res (whose ws is w).
+int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Workspace *w,
+                 hipStream_t s, mpap_result *res);
+SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
+                       const SearchShape &L);
+GoalArgs goal_args(const mpap_graph *g, Workspace *w);
+// Fills res's fronts, statistics, trace and latencies from host copies.
+void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_out,
+                   const int *counts, const float4 *plab, const int *pnode, const int *qlast,
+                   const long long *trace, float ms, int retries, const SearchShape &L);
+
+// Surrogate scoring of one roadmap (features, then inference) enqueued on a
+// stream, writing the drift to out[e]; used by plans and mpap_surrogate_score.
+struct mpap_surrogate;
+int sur_enqueue_score(const mpap_surrogate *s, mpap_graph *g, float *out, hipStream_t st);
 

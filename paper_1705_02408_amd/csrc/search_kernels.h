@@ -102,8 +102,8 @@ struct GoalArgs {
     int nq;
     const int *qgoff;      // [nq+1]
     const int *goal_list;
-    const long long *lab_off;  // [nq]
-    const int *lab_cap;    // [nq]
+    long long *lab_off;    // [nq] region of query q in out_lab/out_node
+    int *lab_cap;          // [nq] its size
     float4 *out_lab;
     int *out_node;
     int *out_count;        // [nq]
@@ -120,3 +120,11 @@ __global__ void k_search_roots(SearchArgs a);
 __global__ void k_search(SearchArgs a);
 __global__ void k_count_front(SearchArgs a);
 __global__ void k_goal_front(SearchArgs a, GoalArgs g);
+// per-query goal-front regions: lab_cap[q] = sum of the front sizes of the
+// query's goal nodes (a bound on its goal front), lab_off = exclusive scan;
+// *total = the sum; overflow |= 1 when it exceeds cap (then k_goal_front does
+// nothing).  One block.
+__global__ void k_goal_bound(SearchArgs a, GoalArgs g, long long cap, long long *total);
+// goal fronts packed densely in query order: query q's out_count[q] labels go
+// to plab/pnode at sum_{j<q} out_count[j]; overflow |= 2 beyond pcap
+__global__ void k_goal_pack(GoalArgs g, float4 *plab, int *pnode, long long pcap);

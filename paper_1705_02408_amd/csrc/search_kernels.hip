@@ -158,12 +158,22 @@ __device__ void phase_select(const SearchArgs &a, float T, int wave, long long a
                 if (a.nq > 1) atomicMax(&a.qlast[query_of(a, vv)], wave);
                 else if (vv >= 0) a.qlast[0] = wave;
             }
-            // queue out-neighbours as merge targets of this wave
-            for (int e = a.optr[vv] + l; e < a.optr[vv + 1]; e += 64) {
-                const int x = a.ocol[e];
-                if (atomicExch(&a.mark[x], wave) != wave) {
-                    const int s = atomicAdd(&a.acnt[wp], 1);
-                    a.alist[s] = x;
+            // queue out-neighbours as merge targets of this wave (one slot
+            // reservation per wave of 64 out-edges)
+            for (int e0 = a.optr[vv]; e0 < a.optr[vv + 1]; e0 += 64) {
+                const int e = e0 + l;
+                int x = -1;
+                bool fresh = false;
+                if (e < a.optr[vv + 1]) {
+                    x = a.ocol[e];
+                    fresh = atomicExch(&a.mark[x], wave) != wave;
+                }
+                const uint64_t fm = ballot64(fresh);
+                if (fm) {
+                    int base = 0;
+                    if (l == 0) base = atomicAdd(&a.acnt[wp], (int)__popcll(fm));
+                    base = __shfl(base, 0, 64);
+                    if (fresh) a.alist[base + lanes_below(fm)] = x;
                 }
             }
         }
@@ -753,6 +763,7 @@ __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
 // query (looping if there are more queries than workgroups).
 __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
     extern __shared__ __align__(16) unsigned char lds[];
+    if (*(volatile int *)g.overflow) return;  // regions did not fit (k_goal_bound)
     MergeLds s;
     carve_lds(lds, a, s);
     for (int q = blockIdx.x; q < g.nq; q += gridDim.x) {
@@ -782,6 +793,58 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
         }
         if (threadIdx.x == 0) g.out_count[q] = nB;
         __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_goal_bound(SearchArgs a, GoalArgs g, long long cap,
+                                                    long long *total) {
+    __shared__ long long wsum[16];
+    const int l = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    long long carry = 0;
+    for (int q0 = 0; q0 < g.nq; q0 += blockDim.x) {
+        const int q = q0 + threadIdx.x;
+        long long b = 0;
+        if (q < g.nq)
+            for (int gi = g.qgoff[q]; gi < g.qgoff[q + 1]; ++gi) b += a.nb[g.goal_list[gi]].z;
+        const long long incl = wave_incl_scan_add(b);
+        if (l == 63) wsum[w] = incl;
+        __syncthreads();
+        long long before = 0, all = 0;
+        for (int i = 0; i < nw; ++i) {
+            before += i < w ? wsum[i] : 0;
+            all += wsum[i];
+        }
+        if (q < g.nq) {
+            g.lab_off[q] = carry + before + incl - b;
+            g.lab_cap[q] = (int)min(b, 0x7fffffffll);
+        }
+        carry += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *total = carry;
+        if (carry > cap) atomicOr(g.overflow, 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_goal_pack(GoalArgs g, float4 *plab, int *pnode,
+                                                   long long pcap) {
+    __shared__ long long red[8];
+    if (*(volatile int *)g.overflow) return;
+    for (int q = blockIdx.x; q < g.nq; q += gridDim.x) {
+        long long o = 0;
+        for (int i = threadIdx.x; i < q; i += blockDim.x) o += g.out_count[i];
+        o = block_sum_ll(o, red);
+        const int k = g.out_count[q];
+        if (o + k > pcap) {
+            if (threadIdx.x == 0) atomicOr(g.overflow, 2);
+            continue;
+        }
+        const long long src = g.lab_off[q];
+        for (int i = threadIdx.x; i < k; i += blockDim.x) {
+            plab[o + i] = g.out_lab[src + i];
+            pnode[o + i] = g.out_node[src + i];
+        }
     }
 }
 

@@ -326,37 +326,25 @@ int mpap_surrogate_train(mpap_surrogate *s, const mpap_graph *gc, const int64_t 
 
 int mpap_surrogate_score(const mpap_surrogate *s, mpap_graph *g, void *stream, float *ms) {
     if (!s || !g) return fail(MPAP_ERR_INVAL, "null argument");
-    if (!g->symmetric_alias) return fail(MPAP_ERR_INVAL, "graph is not a symmetric roadmap");
-    if (!g->pos) return fail(MPAP_ERR_INVAL, "graph has no environment (build it with mpap_build_graph)");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int r;
-    if (!g->feat && (r = dalloc(&g->feat, (size_t)std::max<long long>(g->e, 1) * kMlpIn))) return r;
-    if (!g->sdrift && (r = dalloc(&g->sdrift, std::max<long long>(g->e, 1)))) return r;
+    if (!g->sdrift && g->symmetric_alias && (r = dalloc(&g->sdrift, std::max<long long>(g->e, 1))))
+        return r;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    {
-        // the inputs are part of the cost of scoring a roadmap: recompute them
-        BuildArgs a{};
-        a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu;
-        a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
-        a.reset_q = g->reset_q;
-        const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
-        if (g->n > 0)
-            k_edge_features<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->feat);
+    r = sur_enqueue_score(s, g, g->sdrift, st);
+    if (r == MPAP_OK) {
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (ms) *ms = t;
     }
-    const int blocks = std::max(1, std::min(div_up(g->e, 128), 2048));
-    k_mlp_infer<<<blocks, 256, 0, st>>>(dev_view(s), g->feat, g->e, g->ocost, nullptr, g->sdrift);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipEventSynchronize(e1));
-    float t = 0.f;
-    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    if (ms) *ms = t;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return MPAP_OK;
+    return r;
 }
 
 int mpap_analytic_drift(mpap_graph *g, void *stream, float *ms) {
@@ -395,17 +383,23 @@ int mpap_graph_drift(const mpap_graph *g, int32_t which, float *out) {
 int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *drift,
                        float *maxdrift, uint8_t *feasible, int32_t capacity, int32_t *count) {
     if (!r || !count) return fail(MPAP_ERR_INVAL, "null argument");
-    if (query < 0 || query >= r->g->nq) return fail(MPAP_ERR_INVAL, "query out of range");
-    const int64_t o = r->front_off[query];
-    const int n = (int)(r->front_off[query + 1] - o);
+    const int nq = r->g->nq;
+    if (query < -1 || query >= nq) return fail(MPAP_ERR_INVAL, "query out of range");
+    const int q0 = query < 0 ? 0 : query, q1 = query < 0 ? nq : query + 1;
+    const int64_t o = r->front_off[q0];
+    const int n = (int)(r->front_off[q1] - o);
     *count = n;
     if (capacity < n) return fail(MPAP_ERR_CAPACITY, "capacity below the front size");
     if (n == 0) return MPAP_OK;
-    std::vector<int> lab(n);
-    std::vector<float> beta(n, r->qbeta[query]);
-    std::vector<int> nobj(n, r->qnobj[query]);
-    for (int i = 0; i < n; ++i) std::memcpy(&lab[i], &r->front[o + i].w, sizeof(int));
-    const int maxlen = 1 << 14;
+    std::vector<int> lab(n), nobj(n);
+    std::vector<float> beta(n);
+    for (int q = q0; q < q1; ++q)
+        for (int64_t i = r->front_off[q]; i < r->front_off[q + 1]; ++i) {
+            std::memcpy(&lab[i - o], &r->front[i].w, sizeof(int));
+            beta[i - o] = r->qbeta[q];
+            nobj[i - o] = r->qnobj[q];
+        }
+    const int maxlen = 4096;
     int *dlab = nullptr, *dnobj = nullptr, *dpath = nullptr, *derr = nullptr;
     float *dbeta = nullptr;
     float4 *dout = nullptr;
@@ -436,7 +430,7 @@ int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *
     if (he == hipSuccess) he = hipMemcpy(&err, derr, sizeof(int), hipMemcpyDeviceToHost);
     cleanup();
     if (he != hipSuccess) return fail(MPAP_ERR_HIP, hipGetErrorString(he));
-    if (err) return fail(MPAP_ERR_HIP, "a plan could not be re-walked");
+    if (err) return fail(MPAP_ERR_HIP, "a plan could not be re-walked (longer than 4096 steps?)");
     for (int i = 0; i < n; ++i) {
         if (cost) cost[i] = out[i].x;
         if (drift) drift[i] = out[i].y;
@@ -447,3 +441,28 @@ int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *
 }
 
 }  // extern "C"
+
+int sur_enqueue_score(const mpap_surrogate *s, mpap_graph *g, float *out, hipStream_t st) {
+    if (!s || !g) return fail(MPAP_ERR_INVAL, "null argument");
+    if (!g->symmetric_alias) return fail(MPAP_ERR_INVAL, "graph is not a symmetric roadmap");
+    if (!out) return fail(MPAP_ERR_INVAL, "no drift array to score into");
+    if (!g->pos) return fail(MPAP_ERR_INVAL, "graph has no environment (build it with mpap_build_graph)");
+    int r;
+    if (!g->feat && (r = dalloc(&g->feat, (size_t)std::max<long long>(g->e, 1) * kMlpIn))) return r;
+    {
+        // the inputs are part of the cost of scoring a roadmap: recompute them
+        BuildArgs a{};
+        a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu;
+        a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
+        a.reset_q = g->reset_q;
+        const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
+        if (g->n > 0)
+            k_edge_features<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->feat);
+    }
+    if (g->e > 0) {
+        const int blocks = std::max(1, std::min(div_up(g->e, 128), 2048));
+        k_mlp_infer<<<blocks, 256, 0, st>>>(dev_view(s), g->feat, g->e, g->ocost, nullptr, out);
+    }
+    HIP_TRY(hipGetLastError());
+    return MPAP_OK;
+}

@@ -73,6 +73,7 @@ SYMBOLS = [
     "mpap_surrogate_get_params", "mpap_surrogate_init", "mpap_edge_features",
     "mpap_surrogate_forward", "mpap_surrogate_gradient", "mpap_surrogate_train",
     "mpap_surrogate_score", "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
+    "mpap_plan_create", "mpap_plan_run", "mpap_plan_info", "mpap_plan_free",
 ]
 
 _lib = None
@@ -124,6 +125,11 @@ def load(path: str = LIB_PATH):
     lib.mpap_graph_drift.argtypes = [P, I32, P]
     lib.mpap_analytic_drift.argtypes = [P, P, P]
     lib.mpap_rescore_front.argtypes = [P, I32, P, P, P, P, I32, P]
+    lib.mpap_plan_create.argtypes = [P, P, I32, P, P, I32, P, ctypes.POINTER(P)]
+    lib.mpap_plan_run.argtypes = [P, P, ctypes.POINTER(P)]
+    lib.mpap_plan_info.argtypes = [P, P, P, P]
+    lib.mpap_plan_free.argtypes = [P]
+    lib.mpap_plan_free.restype = None
     lib.mpap_result_free.argtypes = [P]
     lib.mpap_result_free.restype = None
     lib.mpap_status_string.argtypes = [ctypes.c_int]
@@ -523,6 +529,28 @@ def mpap_rescore_front(res: Result, query: int = 0) -> dict:
     return dict(cost=c, drift=d, maxdrift=m, feasible=f.astype(bool))
 
 
+def surrogate_judge(res: Result, betas, tol: float = 1e-2) -> list:
+    """surrogate_front_ok for every query of a result, from one re-walk launch."""
+    nq = len(betas)
+    fronts = [mpap_query_goal_front(res, q) for q in range(nq)]
+    rs = mpap_rescore_front(res, -1)
+    out, o = [], 0
+    for q, fr in enumerate(fronts):
+        k = fr.vecs.shape[0]
+        ok = True
+        if k:
+            feas = rs["feasible"][o:o + k]
+            floor = 1e-3 * betas[q]
+            ok = bool(feas.all())
+            for col, key in ((1, "drift"), (2, "maxdrift")):
+                a = rs[key][o:o + k].astype(np.float64)
+                err = np.abs(fr.vecs[:, col].astype(np.float64) - a) / np.maximum(a, floor)
+                ok = ok and bool((err <= tol).all())
+        out.append(ok)
+        o += k
+    return out
+
+
 def surrogate_front_ok(res: Result, query: int, beta: float, tol: float = 1e-2) -> bool:
     """Judge a search run on the surrogate's drift: every goal-front plan,
     re-walked with the analytic drift, stays within the bound and its drift
@@ -540,3 +568,50 @@ def surrogate_front_ok(res: Result, query: int, beta: float, tol: float = 1e-2) 
         if (err > tol).any():
             return False
     return True
+
+
+class Plan:
+    """A fixed batch recorded as one HIP graph (mpap_plan_*): scoring of the
+    parts by their surrogates (optional), the search of every query and the
+    goal fronts, launched with run().  A result of run() reads the plan's
+    workspace for per-node queries until the next run()."""
+
+    def __init__(self, graph: Graph, params, parts=None, models=None, stream=None):
+        lib = load()
+        if isinstance(params, mpap_search_params):
+            params = [params]
+        arr = (mpap_search_params * len(params))(*params)
+        n = 0
+        pa = ma = None
+        if parts is not None:
+            n = len(parts)
+            models = list(models) if models is not None else [None] * n
+            pa = (ctypes.c_void_p * n)(*[p.handle for p in parts])
+            ma = (ctypes.c_void_p * n)(*[(m.handle if m is not None else None) for m in models])
+        self.graph, self.parts, self.models = graph, parts, models
+        h = ctypes.c_void_p()
+        _check(lib.mpap_plan_create(graph.handle, arr, len(params), pa, ma, n, _stream(stream),
+                                    ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None) -> Result:
+        h = ctypes.c_void_p()
+        _check(load().mpap_plan_run(self.handle, _stream(stream), ctypes.byref(h)))
+        return Result(h, self.graph)
+
+    def info(self) -> dict:
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().mpap_plan_info(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                     ctypes.byref(c)))
+        return {"launches": a.value, "records": b.value, "fallbacks": c.value}
+
+    def close(self):
+        if self.handle:
+            load().mpap_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -73,7 +73,9 @@ class Env:
     """A planning instance: roadmap samples plus the mapped environment.
 
     ``pos[0]`` is the initial state (node 0); rows 1..n are free samples.
-    ``vel`` is set only for the double-integrator state space.
+    ``vel`` is set only for the double-integrator state space (dim 6: position
+    and velocity in 3D, boxes/blobs/goal in the 3D workspace); ``k_out`` and
+    ``horizon`` are that roadmap's out-degree and steering time.
     """
     dim: int
     pos: np.ndarray            # float32 [n_nodes, dim]
@@ -93,10 +95,18 @@ class Env:
     name: str = ""
     seed: int = 0
     vel: np.ndarray | None = None
+    k_out: int = 0
+    horizon: float = 0.0
+    traj_steps: int = 0
 
     @property
     def n_nodes(self) -> int:
         return int(self.pos.shape[0])
+
+    @property
+    def wdim(self) -> int:
+        """Dimension of the workspace (positions, boxes, blobs, goal)."""
+        return 3 if self.dim == 6 else self.dim
 
 
 def _point_in_any_box(p, lo, hi):
@@ -195,6 +205,39 @@ def plain3d(seed: int = 0, n: int = 20000) -> Env:
     drift bound 0.25, three objectives (cost, drift, max drift so far)."""
     return make_env(seed, 3, n, 100, 80, 40.0, 0.25, 3, blob_amp=0.4,
                     name=f"plain3d_n{n}_s{seed}")
+
+
+def _unit_ball(seed: int, n: int) -> np.ndarray:
+    """n velocities uniform in the open unit ball, by rejection from the cube
+    [-1, 1)^3 (draw order kept)."""
+    s = Stream(seed, TAG_VEL)
+    out, have = [], 0
+    while have < n:
+        m = max(1024, 2 * (n - have))
+        v = (np.float32(2.0) * s.uniform(3 * m).reshape(m, 3) - np.float32(1.0)).astype(np.float32)
+        v = v[(v.astype(np.float64) ** 2).sum(axis=1) < 1.0]
+        out.append(v[: n - have])
+        have += min(v.shape[0], n - have)
+    return np.concatenate(out, axis=0).astype(np.float32)
+
+
+def plain6d(seed: int = 0, n: int = 50000) -> Env:
+    """Double-integrator roadmap: states (position, velocity), positions
+    uniform free in the unit cube (150 boxes, half-extents 0.02-0.06),
+    velocities uniform in the unit ball; start at rest at (0.1, 0.1, 0.1), goal
+    ball r=0.05 at (0.9, 0.9, 0.9) in position (any velocity); 100 feature
+    blobs of amplitude 0.4; 30 out-edges per node under a steering time of
+    0.5 with 100 check steps; drift bound 0.3, two objectives."""
+    init = np.full(3, 0.1, dtype=np.float32)
+    goal = np.full(3, 0.9, dtype=np.float32)
+    lo, hi = _boxes(seed, 3, 150, 0.02, 0.06, init, goal, 0.05)
+    mu, sig, amp = _blobs(seed, 3, 100, 0.4)
+    pos = np.concatenate([init[None, :], _free_samples(seed, 3, n, lo, hi)], axis=0)
+    vel = np.concatenate([np.zeros((1, 3), np.float32), _unit_ball(seed, n)], axis=0)
+    return Env(dim=6, pos=pos.astype(np.float32), box_lo=lo, box_hi=hi, blob_mu=mu,
+               blob_sigma=sig, blob_amp=amp, goal=goal, goal_radius=float(np.float32(0.05)),
+               radius=0.1, beta=float(np.float32(0.3)), n_obj=2, name=f"plain6d_n{n}_s{seed}",
+               seed=seed, vel=vel, k_out=30, horizon=0.5, traj_steps=100)
 
 
 def tiny_random_graph(seed: int, n: int = 30, p_reset: float = 0.2,
