@@ -52,24 +52,30 @@ typedef struct mpap_result mpap_result; /* outcome of one search */
  * axis-aligned box obstacles; Sec. 4.1 mapped perception features, here as
  * isotropic Gaussian blobs whose summed density is the quality q(x)). */
 typedef struct {
-    int32_t dim;              /* 2 or 3 */
+    int32_t dim;              /* 2 or 3: geometric roadmap; 6: double integrator
+                                 (3D position and velocity) */
     int32_t n_nodes;          /* number of roadmap nodes; node 0 is x_init */
-    const float *pos;         /* host [n_nodes][dim] node positions */
+    const float *pos;         /* host [n_nodes][w] node positions, w = dim (3 for dim 6) */
     int32_t n_boxes;          /* obstacle count (>= 0) */
-    const float *box_lo;      /* host [n_boxes][dim] lower corners */
-    const float *box_hi;      /* host [n_boxes][dim] upper corners (closed) */
+    const float *box_lo;      /* host [n_boxes][w] lower corners */
+    const float *box_hi;      /* host [n_boxes][w] upper corners (closed) */
     int32_t n_blobs;          /* feature blob count (>= 0) */
-    const float *blob_mu;     /* host [n_blobs][dim] centres */
+    const float *blob_mu;     /* host [n_blobs][w] centres */
     const float *blob_sigma;  /* host [n_blobs] widths (> 0) */
     const float *blob_amp;    /* host [n_blobs] amplitudes */
-    float goal[3];            /* goal ball centre (first dim entries used) */
-    float goal_radius;        /* goal ball radius (closed ball) */
+    float goal[3];            /* goal ball centre (first w entries used) */
+    float goal_radius;        /* goal ball radius (closed ball, positions only) */
+    const float *vel;         /* host [n_nodes][3] velocities (dim 6 only, else NULL) */
 } mpap_env;
 
 typedef struct {
-    float radius;     /* r_n: an edge u->v exists iff Cost(u,v) < radius (Alg. 2, Near) */
+    float radius;     /* r_n: an edge u->v exists iff Cost(u,v) < radius (Alg. 2, Near);
+                         for dim 6 only the group step of searches (cost units) */
     float check_step; /* sub-step length of Collision and of the drift integral */
     float reset_q;    /* a node relocalises (drift resets to 0) iff q(x) > reset_q */
+    int32_t k_out;      /* dim 6: out-degree (1..64) */
+    float horizon;      /* dim 6: steering time T (> 0) */
+    int32_t traj_steps; /* dim 6: check steps K per trajectory (1..255) */
 } mpap_graph_params;
 
 /*
@@ -84,9 +90,21 @@ typedef struct {
  *   q(x) = clamp(sum_j amp_j exp(-|x - mu_j|^2 / (2 sigma_j^2)), 0, 1),
  *   evaluated in float32 with the device expf (not bit-identical to a host
  *   libm; drift and reset agree with a float64 evaluation within a few ulp).
- * Errors: MPAP_ERR_INVAL (null, dim not 2/3, n_nodes < 1, non-finite
- * position, radius <= 0), MPAP_ERR_NOGOAL (no node in the goal ball; no
- * graph is returned), MPAP_ERR_NOMEM, MPAP_ERR_HIP.
+ * dim 6 (double integrator; the dynamics class of Sec. 4.1 and Sec. 5):
+ *   steering u -> v is the minimum-energy control of p'' = a over the fixed
+ *   time T = horizon; per axis, with a = (p_v - p_u) - v_u T, b = v_v - v_u,
+ *   J = 12a^2/T^3 - 12ab/T^2 + 4b^2/T (summed over axes: the edge cost).
+ *   The trajectory is checked at t_k = (k T)/K, k = 0..K: inside the closed
+ *   unit cube, in no closed box, speed <= 1.  Each node keeps the k_out
+ *   reachable targets of least (J, id) (a directed roadmap).  drift = sum
+ *   over the K chords of |chord| (1 - q(chord midpoint)).  All float32 with
+ *   separately rounded operations.
+ * Errors: MPAP_ERR_INVAL (null, dim not 2/3/6, n_nodes < 1, non-finite
+ * position, radius <= 0, dim 6 without velocities or with k_out, horizon or
+ * traj_steps out of range, more than 1024 boxes), MPAP_ERR_NOGOAL (no node in
+ * the goal ball; no graph is returned), MPAP_ERR_OVERFLOW (dim 6: more than
+ * 2048 candidates of one node share one steering cost), MPAP_ERR_NOMEM,
+ * MPAP_ERR_HIP.
  */
 int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *stream,
                      mpap_graph **out);
@@ -266,16 +284,23 @@ void mpap_surrogate_free(mpap_surrogate *s);
 int mpap_surrogate_set_params(mpap_surrogate *s, const float *params, int32_t count);
 int mpap_surrogate_get_params(const mpap_surrogate *s, float *params, int32_t capacity,
                               int32_t *count);
-/* He-normal weights from a counter-based SplitMix64 stream of `seed`, zero biases. */
+/* He-normal hidden weights from a counter-based SplitMix64 stream of `seed`;
+ * zero biases and zero output weights (the untrained network adds nothing to
+ * the 8-point base). */
 int mpap_surrogate_init(mpap_surrogate *s, uint64_t seed);
 
 /* The network's inputs for every edge of g (forward CSR order), 16 bfloat16
  * bit patterns per edge, computed on the device from the id-ordered endpoint
- * pair: x_a (3), x_b (3; z = 0 in 2D), length, q at the points
- * x_a + (k + 1/2)/8 (x_b - x_a), k = 0..7, and q(x_b).  Needs a roadmap built
- * by mpap_build_graph (MPAP_ERR_INVAL otherwise).  out (host, nullable) holds
- * capacity >= 16 * edges values. */
-int mpap_edge_features(const mpap_graph *g, void *stream, uint16_t *out, int64_t capacity);
+ * pair: x_a (3), x_b (3; z = 0 in 2D), length, 1 - q at the points
+ * x_a + (k + 1/2)/8 (x_b - x_a), k = 0..7, and 1 - q(x_b) (complements taken
+ * in float32 before the rounding, so that q near 1 keeps its precision).
+ * base (host, nullable, edges values) receives the float32 mean of the eight
+ * 1 - q values: the 8-point estimate of drift / length that the network
+ * corrects (predicted drift = length * clamp(base + network/256, 0, 1)).  Needs a
+ * roadmap built by mpap_build_graph (MPAP_ERR_INVAL otherwise).  out (host,
+ * nullable) holds capacity >= 16 * edges values. */
+int mpap_edge_features(const mpap_graph *g, void *stream, uint16_t *out, int64_t capacity,
+                       float *base);
 
 /* Outputs of the network for n rows of inputs (host memory, 16 bfloat16 bit
  * patterns per row). */
@@ -289,16 +314,20 @@ int mpap_surrogate_gradient(mpap_surrogate *s, const uint16_t *X, const float *t
                             float *grad, float *y_out);
 
 /* Train on the edges `edges[0..n_train)` of g (host indices into the forward
- * edge order), targets drift/length of the roadmap's analytic values, in
+ * edge order), targets 256 * (drift/length - base): the roadmap's analytic
+ * values less the 8-point base of mpap_edge_features, scaled by 2^8 (the
+ * network learns the correction in units of 1/256), in
  * batches of `batch` consecutive entries (a power of two >= 64; a short tail
- * is dropped), `epochs` passes, learning rate lr.  epoch_loss (nullable)
+ * is dropped), `epochs` passes, Adam with a learning rate decaying from lr to
+ * lr/100 along a half cosine over the run.  epoch_loss (nullable)
  * receives the mean squared error over the training edges after each epoch. */
 int mpap_surrogate_train(mpap_surrogate *s, const mpap_graph *g, const int64_t *edges,
                          int64_t n_train, int32_t epochs, int32_t batch, float lr, void *stream,
                          float *epoch_loss);
 
-/* Predicted drift of every edge of g, kept in the graph for searches with
- * heuristic = 1 (and carried into mpap_graph_concat when every part has it).
+/* Predicted drift of every edge of g, length * clamp(base + network/256, 0, 1),
+ * kept in the graph for searches with heuristic = 1 (and carried into
+ * mpap_graph_concat when every part has it).
  * The inputs are recomputed on every call; ms (nullable) receives the device
  * time of inputs plus inference.  Needs a roadmap built by mpap_build_graph. */
 int mpap_surrogate_score(const mpap_surrogate *s, mpap_graph *g, void *stream, float *ms);

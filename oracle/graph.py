@@ -183,9 +183,12 @@ def graph_stats(g):
 
 def edge_features(pos, row_ptr, col, cost, mu, sigma, amp):
     """Inputs of the learned drift surrogate per edge (forward CSR order), from
-    the id-ordered pair (a, b): x_a (3), x_b (3, zero z in 2D), the length, q at
-    x_a + (k + 1/2)/8 (x_b - x_a) for k = 0..7 (float64 q), q(x_b).  float32
-    values before the bfloat16 rounding of the model."""
+    the id-ordered pair (a, b): x_a (3), x_b (3, zero z in 2D), the length,
+    1 - q at x_a + (k + 1/2)/8 (x_b - x_a) for k = 0..7, and 1 - q(x_b)
+    (float64 q, complement in float64), as float32 values before the bfloat16
+    rounding of the model.  Also returns base = the mean of the eight 1 - q
+    values (float64, rounded to float32): the 8-point midpoint estimate of
+    drift / length that the network corrects."""
     n = row_ptr.shape[0] - 1
     src = np.repeat(np.arange(n), np.diff(row_ptr))
     a = np.minimum(src, col)
@@ -199,9 +202,12 @@ def edge_features(pos, row_ptr, col, cost, mu, sigma, amp):
     f[:, 3:3 + d] = pb
     f[:, 6] = cost
     diff = (pb - pa).astype(np.float32)
+    acc = np.zeros(e, dtype=np.float64)
     for k in range(8):
         s = np.float32((k + 0.5) / 8.0)
         pts = (pa + s * diff).astype(np.float32)
-        f[:, 7 + k] = quality(pts, mu, sigma, amp)
-    f[:, 15] = quality(pb, mu, sigma, amp)
-    return f
+        w = 1.0 - quality(pts, mu, sigma, amp)
+        f[:, 7 + k] = w
+        acc += w
+    f[:, 15] = 1.0 - quality(pb, mu, sigma, amp)
+    return f, (acc / 8.0).astype(np.float32)

@@ -187,3 +187,46 @@ def build_graph6d(env, block=32, width=64):
                 drift=np.concatenate(drifts or [np.zeros(0, F32)]),
                 reset=(q > float(env.reset_q)).astype(np.uint8),
                 goal=goal_mask(pos, env.goal, env.goal_radius), q=q)
+
+
+def edge_features6d(env, g):
+    """Inputs of the learned drift surrogate for the edges of a 6D roadmap
+    (forward CSR order): p_u (3), p_v (3), trajectory length (sum of the
+    chords of the check points), 1 - q at t = (k + 1/2) T / 8, k = 0..7, on
+    the trajectory, 1 - q(p_v); float32 values before the bfloat16 rounding.
+    Also returns base = the speed-weighted mean of the eight 1 - q values
+    (sum s_k w_k / sum s_k with s_k = |v(t_k)|, the arc-length weighting of
+    the drift integral), float64 rounded to float32."""
+    pos = np.ascontiguousarray(env.pos, F32)
+    vel = np.ascontiguousarray(env.vel, F32)
+    row_ptr, col = g["row_ptr"], g["col"]
+    n = row_ptr.shape[0] - 1
+    src = np.repeat(np.arange(n), np.diff(row_ptr))
+    T, K = float(env.horizon), int(env.traj_steps)
+    _, c0, c1 = steer(pos[src], vel[src], pos[col], vel[col], T)
+    p, _ = trajectory(pos[src], vel[src], c0, c1, T, K)
+    P = p.astype(np.float64)
+    seg = P[:, 1:, :] - P[:, :-1, :]
+    elen = np.sqrt((seg * seg).sum(axis=2)).sum(axis=1)
+    e = col.shape[0]
+    f = np.zeros((e, 16), dtype=F32)
+    f[:, 0:3] = pos[src]
+    f[:, 3:6] = pos[col]
+    f[:, 6] = elen
+    t = ((np.arange(8, dtype=F32) + F32(0.5)) * F32(T) / F32(8)).astype(F32)
+    h2, h3, g1 = c0 * F32(0.5), c1 / F32(6), c1 * F32(0.5)
+    sw = np.zeros(e)
+    ss = np.zeros(e)
+    for k in range(8):
+        tk = t[k]
+        pk = pos[src] + tk * (vel[src] + tk * (h2 + tk * h3))
+        vk = vel[src] + tk * (c0 + tk * g1)
+        w = 1.0 - quality(pk.astype(F32), env.blob_mu, env.blob_sigma, env.blob_amp)
+        sp = np.sqrt((vk.astype(np.float64) ** 2).sum(axis=1))
+        f[:, 7 + k] = w
+        sw += sp * w
+        ss += sp
+    f[:, 15] = 1.0 - quality(pos[col], env.blob_mu, env.blob_sigma, env.blob_amp)
+    mean_w = f[:, 7:15].astype(np.float64).mean(axis=1)
+    base = np.where(ss > 0, sw / np.where(ss > 0, ss, 1.0), mean_w)
+    return f, base.astype(F32), elen.astype(F32)

@@ -24,6 +24,22 @@ struct BuildArgs {
     float goal_r;
 };
 
+// Feature quality q(x) = clamp(sum_j a_j exp(-|x - mu_j|^2 / (2 s_j^2)), 0, 1)
+// over the blobs of g (dim coordinates), float32 in blob order.
+__device__ __forceinline__ float blob_quality(const BuildArgs &g, const float *x) {
+    float acc = 0.0f;
+    for (int j = 0; j < g.nblob; ++j) {
+        float d2 = 0.0f;
+        for (int k = 0; k < g.dim; ++k) {
+            const float t = x[k] - g.mu[j * g.dim + k];
+            d2 = d2 + t * t;
+        }
+        const float s = g.sig[j];
+        acc = acc + g.amp[j] * expf(-d2 / (2.0f * s * s));
+    }
+    return fminf(fmaxf(acc, 0.0f), 1.0f);
+}
+
 __global__ void k_near_count(BuildArgs g, int *cnt);
 __global__ void k_near_fill(BuildArgs g, const int *off, int *cand_u, int *cand_v,
                             float *cand_c);
@@ -42,6 +58,9 @@ __global__ void k_scan_sums(int *bsum, int nb);
 __global__ void k_scan_apply(const int *in, long long n, const int *bsum, int *out);
 __global__ void k_add_i32(int *p, long long n, int add);
 __global__ void k_zero_i32(int *p, long long n);
+// surrogate inputs per edge (16 bf16) and the 8-point estimate of the mean
+// of (1 - q) along it (base, nullable)
 __global__ void k_edge_features(BuildArgs g, int n, const int *row_ptr, const int *col,
-                                const float *cost, uint16_t *X);
-__global__ void k_drift_ratio(long long m, const float *drift, const float *cost, float *t);
+                                const float *cost, uint16_t *X, float *base);
+__global__ void k_drift_ratio(long long m, const float *drift, const float *cost,
+                              const float *base, float scale, float *t);

@@ -23,19 +23,6 @@ __device__ __forceinline__ float sqdist(const float *a, const float *b, int dim)
     return s;
 }
 
-__device__ __forceinline__ float quality(const BuildArgs &g, const float *x) {
-    float acc = 0.0f;
-    for (int j = 0; j < g.nblob; ++j) {
-        float d2 = 0.0f;
-        for (int k = 0; k < g.dim; ++k) {
-            const float t = x[k] - g.mu[j * g.dim + k];
-            d2 = d2 + t * t;
-        }
-        const float s = g.sig[j];
-        acc = acc + g.amp[j] * expf(-d2 / (2.0f * s * s));
-    }
-    return fminf(fmaxf(acc, 0.0f), 1.0f);
-}
 
 }  // namespace
 
@@ -190,7 +177,7 @@ __global__ void __launch_bounds__(256) k_edge_drift(BuildArgs g, int n, const in
             const float s = ((float)j + 0.5f) / fK;
             float p[3];
             for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + s * df[k];
-            acc = acc + w * (1.0f - quality(gl, p));
+            acc = acc + w * (1.0f - blob_quality(gl, p));
         }
         drift[e] = acc;
     }
@@ -202,7 +189,7 @@ __global__ void __launch_bounds__(256) k_node_flags(BuildArgs g, uint8_t *flag) 
     float x[3] = {0.f, 0.f, 0.f};
     for (int k = 0; k < g.dim; ++k) x[k] = g.pos[v * g.dim + k];
     uint8_t f = 0;
-    if (quality(g, x) > g.reset_q) f |= 1u;
+    if (blob_quality(g, x) > g.reset_q) f |= 1u;
     float gg[3] = {g.goal[0], g.goal[1], g.goal[2]};
     const float r = g.goal_r;
     if (sqdist(gg, x, g.dim) <= r * r) f |= 2u;
@@ -295,7 +282,7 @@ __global__ void __launch_bounds__(256) k_zero_i32(int *p, long long n) {
 // 2D), the length, q at the 8 segment points (k + 1/2)/8, q(x_b); bfloat16.
 __global__ void __launch_bounds__(64) k_edge_features(BuildArgs g, int n, const int *row_ptr,
                                                       const int *col, const float *cost,
-                                                      uint16_t *X) {
+                                                      uint16_t *X, float *base) {
     extern __shared__ float blob[];
     for (int i = threadIdx.x; i < g.nblob * g.dim; i += blockDim.x) blob[i] = g.mu[i];
     for (int i = threadIdx.x; i < g.nblob; i += blockDim.x) {
@@ -324,20 +311,26 @@ __global__ void __launch_bounds__(64) k_edge_features(BuildArgs g, int n, const 
             f[3 + k] = f2bf(xb[k]);
         }
         f[6] = f2bf(cost[e]);
+        float acc = 0.0f;
         for (int j = 0; j < 8; ++j) {
             const float s = ((float)j + 0.5f) / 8.0f;
             float p[3] = {0.f, 0.f, 0.f};
             for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + s * df[k];
-            f[7 + j] = f2bf(quality(gl, p));
+            const float w = 1.0f - blob_quality(gl, p);
+            f[7 + j] = f2bf(w);
+            acc = acc + w;
         }
-        f[15] = f2bf(quality(gl, xb));
+        f[15] = f2bf(1.0f - blob_quality(gl, xb));
+        if (base) base[e] = acc * 0.125f;
     }
 }
 
-// t[e] = drift[e] / cost[e]: the analytic per-edge mean of (1 - q), the
-// surrogate's training target
+// t[e] = scale * (drift[e] / cost[e] - base[e]): the analytic per-edge mean
+// of (1 - q) less its 8-point estimate, scaled, the surrogate network's
+// training target
 __global__ void __launch_bounds__(256) k_drift_ratio(long long m, const float *drift,
-                                                     const float *cost, float *t) {
+                                                     const float *cost, const float *base,
+                                                     float scale, float *t) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < m) t[e] = drift[e] / cost[e];
+    if (e < m) t[e] = scale * (drift[e] / cost[e] - (base ? base[e] : 0.0f));
 }

@@ -58,8 +58,14 @@ struct MlpAdam {
     int apply;        // 0: only sum the gradient
 };
 
+// The network predicts the correction to the 8-point base in units of
+// 1/kResidualScale (a power of two, so the rescaling is exact).
+constexpr float kResidualScale = 256.0f;
+
+// y = network(X[i]) (nullable) and
+// drift = len * clamp(base + y / kResidualScale, 0, 1) (nullable; base nullable = 0)
 __global__ void k_mlp_infer(MlpDev d, const uint16_t *X, long long n, const float *len,
-                            float *y, float *drift);
+                            const float *base, float *y, float *drift);
 __global__ void k_mlp_train_fwd(MlpDev d, MlpTrain t);
 __global__ void k_mlp_train_bwd_h(MlpDev d, MlpTrain t);
 __global__ void k_mlp_train_bwd_w(MlpDev d, MlpTrain t);

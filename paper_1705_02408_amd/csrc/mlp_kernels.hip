@@ -133,9 +133,10 @@ __device__ __forceinline__ float half_sum(float v) {
 
 }  // namespace
 
-// y = network(X[i]) and drift = len * clamp(y, 0, 1) for i < n.
+// y = network(X[i]) and drift = len * clamp(base + y / kResidualScale, 0, 1).
 __global__ void __launch_bounds__(256) k_mlp_infer(MlpDev d, const uint16_t *X, long long n,
-                                                   const float *len, float *y, float *drift) {
+                                                   const float *len, const float *base, float *y,
+                                                   float *drift) {
     __shared__ float sb1[kMlpH], sb2[kMlpH], sw3[kMlpH], sb3;
     load_small(d, sb1, sb2, sw3, &sb3);
     const int l = lane_id(), h = l >> 5, c = l & 31;
@@ -152,7 +153,10 @@ __global__ void __launch_bounds__(256) k_mlp_infer(MlpDev d, const uint16_t *X, 
         const float out = forward32(f, bx, sb1, sb2, sw3, sb3, h, d1, h1, z2);
         if (h == 0 && valid) {
             if (y) y[i] = out;
-            if (drift) drift[i] = len[i] * fminf(fmaxf(out, 0.0f), 1.0f);
+            if (drift) {
+                const float r = (base ? base[i] : 0.0f) + out * (1.0f / kResidualScale);
+                drift[i] = len[i] * fminf(fmaxf(r, 0.0f), 1.0f);
+            }
         }
     }
 }

@@ -5,6 +5,7 @@
 // an overflow, and copies results back.  No part of the search itself runs on
 // the host.
 #include "runtime_internal.h"
+#include "steer_kernels.h"
 
 thread_local std::string g_last_error;
 
@@ -54,7 +55,7 @@ int mpap_graph_from_csr(int32_t n, const int32_t *row_ptr, const int32_t *col,
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     // in-edge CSR: stable counting sort of the edges by target
-    std::vector<int32_t> rptr(n + 1, 0), rsrc(e);
+    std::vector<int32_t> rptr(n + 1, 0), rsrc(e), rperm(e);
     std::vector<float> rcost(e), rdrift(e);
     for (int64_t k = 0; k < e; ++k) rptr[col[k] + 1]++;
     for (int32_t v = 0; v < n; ++v) rptr[v + 1] += rptr[v];
@@ -66,6 +67,7 @@ int mpap_graph_from_csr(int32_t n, const int32_t *row_ptr, const int32_t *col,
                 rsrc[p] = u;
                 rcost[p] = cost[k];
                 rdrift[p] = drift[k];
+                rperm[p] = k;
             }
     }
     std::vector<uint8_t> flag(n);
@@ -84,12 +86,14 @@ int mpap_graph_from_csr(int32_t n, const int32_t *row_ptr, const int32_t *col,
         (r = dalloc(&g->ocost, e)) || (r = dalloc(&g->odrift, e)) ||
         (r = dalloc(&g->rptr, n + 1)) || (r = dalloc(&g->rsrc, e)) ||
         (r = dalloc(&g->rcost, e)) || (r = dalloc(&g->rdrift, e)) ||
-        (r = dalloc(&g->nflag, n)) || (r = dalloc(&g->goal_list, glist.size())))
+        (r = dalloc(&g->nflag, n)) || (r = dalloc(&g->goal_list, glist.size())) ||
+        (r = dalloc(&g->rperm, e)))
         return bail(r);
     hipError_t he = hipSuccess;
     auto cp = [&](void *d, const void *h, size_t bytes) {
         if (he == hipSuccess && bytes) he = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s);
     };
+    cp(g->rperm, rperm.data(), sizeof(int32_t) * e);
     cp(g->optr, row_ptr, sizeof(int32_t) * (n + 1));
     cp(g->ocol, col, sizeof(int32_t) * e);
     cp(g->ocost, cost, sizeof(float) * e);
@@ -111,13 +115,151 @@ int mpap_graph_from_csr(int32_t n, const int32_t *row_ptr, const int32_t *col,
 }
 
 // ------------------------------------------------------------- graph build
+}  // extern "C"
+
+// Double-integrator roadmap: steering selection, compaction, drift on the
+// device; the in-edge lists are built by the import path.
+static int build_graph6(const mpap_env *env, const mpap_graph_params *gp, void *stream,
+                        mpap_graph **out) {
+    const int n = env->n_nodes;
+    if (n < 2 || !env->vel) return fail(MPAP_ERR_INVAL, "dim 6 needs n >= 2 and velocities");
+    if (gp->k_out < 1 || gp->k_out > kSteerMaxOut)
+        return fail(MPAP_ERR_INVAL, "k_out must be in 1..64");
+    if (!(gp->horizon > 0.0f) || !std::isfinite(gp->horizon))
+        return fail(MPAP_ERR_INVAL, "horizon must be finite and > 0");
+    if (gp->traj_steps < 1 || gp->traj_steps > kSteerMaxSteps)
+        return fail(MPAP_ERR_INVAL, "traj_steps must be in 1..255");
+    if (!(gp->radius > 0.0f) || !std::isfinite(gp->radius))
+        return fail(MPAP_ERR_INVAL, "radius (the group step) must be finite and > 0");
+    if (env->n_boxes < 0 || env->n_boxes > 1024 || env->n_blobs < 0 ||
+        (env->n_boxes > 0 && (!env->box_lo || !env->box_hi)) ||
+        (env->n_blobs > 0 && (!env->blob_mu || !env->blob_sigma || !env->blob_amp)))
+        return fail(MPAP_ERR_INVAL, "bad obstacle or blob arrays (at most 1024 boxes)");
+    for (long long i = 0; i < 3ll * n; ++i)
+        if (!std::isfinite(env->pos[i]) || !std::isfinite(env->vel[i]))
+            return fail(MPAP_ERR_INVAL, "non-finite state");
+    for (int j = 0; j < env->n_blobs; ++j)
+        if (!(env->blob_sigma[j] > 0.0f)) return fail(MPAP_ERR_INVAL, "blob sigma must be > 0");
+    DeviceInfo di;
+    int r = device_info(&di);
+    if (r) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int k_out = gp->k_out;
+    const size_t nb_ = (size_t)env->n_boxes * 3, nf_ = env->n_blobs;
+    float *d_pos = nullptr, *d_vel = nullptr, *d_blo = nullptr, *d_bhi = nullptr, *d_mu = nullptr,
+          *d_sig = nullptr, *d_amp = nullptr, *ncost = nullptr, *cost = nullptr, *drift = nullptr,
+          *elen = nullptr;
+    int *nbr = nullptr, *ncnt = nullptr, *rp = nullptr, *col = nullptr, *tmp = nullptr,
+        *err = nullptr;
+    uint8_t *flag = nullptr;
+    auto cleanup = [&]() {
+        dfree(d_pos); dfree(d_vel); dfree(d_blo); dfree(d_bhi); dfree(d_mu); dfree(d_sig);
+        dfree(d_amp); dfree(ncost); dfree(cost); dfree(drift); dfree(elen); dfree(nbr);
+        dfree(ncnt); dfree(rp); dfree(col); dfree(tmp); dfree(err); dfree(flag);
+    };
+    auto bail = [&](int st) {
+        cleanup();
+        return st;
+    };
+    if ((r = dalloc(&d_pos, 3 * (size_t)n)) || (r = dalloc(&d_vel, 3 * (size_t)n)) ||
+        (r = dalloc(&d_blo, nb_)) || (r = dalloc(&d_bhi, nb_)) || (r = dalloc(&d_mu, 3 * nf_)) ||
+        (r = dalloc(&d_sig, nf_)) || (r = dalloc(&d_amp, nf_)) ||
+        (r = dalloc(&nbr, (size_t)n * k_out)) || (r = dalloc(&ncost, (size_t)n * k_out)) ||
+        (r = dalloc(&ncnt, n)) || (r = dalloc(&rp, n + 1)) || (r = dalloc(&err, 1)) ||
+        (r = dalloc(&flag, n)) || (r = dalloc(&tmp, div_up(n + 1, kScanTile) + 1)))
+        return bail(r);
+    hipError_t he = hipSuccess;
+    auto cp = [&](void *d, const void *h, size_t bytes) {
+        if (he == hipSuccess && bytes) he = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s);
+    };
+    const int zero = 0;
+    cp(d_pos, env->pos, sizeof(float) * 3 * n);
+    cp(d_vel, env->vel, sizeof(float) * 3 * n);
+    cp(d_blo, env->box_lo, sizeof(float) * nb_);
+    cp(d_bhi, env->box_hi, sizeof(float) * nb_);
+    cp(d_mu, env->blob_mu, sizeof(float) * 3 * nf_);
+    cp(d_sig, env->blob_sigma, sizeof(float) * nf_);
+    cp(d_amp, env->blob_amp, sizeof(float) * nf_);
+    cp(err, &zero, sizeof(int));
+    if (he != hipSuccess) return bail(fail(MPAP_ERR_HIP, hipGetErrorString(he)));
+
+    SteerArgs a{};
+    a.n = n; a.pos = d_pos; a.vel = d_vel; a.nbox = env->n_boxes; a.blo = d_blo; a.bhi = d_bhi;
+    a.nblob = env->n_blobs; a.mu = d_mu; a.sig = d_sig; a.amp = d_amp;
+    a.T = gp->horizon; a.K = gp->traj_steps; a.k_out = k_out;
+    const size_t lds = sizeof(int) * 2048 + 2 * (size_t)kSteerMaxWidth * 8 +
+                       sizeof(float) * 6 * (size_t)env->n_boxes +
+                       sizeof(int) * (kSteerThreads / 64) * (size_t)env->n_boxes;
+    k_steer_select<<<n, kSteerThreads, lds, s>>>(a, nbr, ncost, ncnt, err);
+    HIP_TRY(hipGetLastError());
+    // row pointers: exclusive scan of the counts, total in rp[n]
+    if ((r = scan_i32(ncnt, rp, n, tmp, s))) return bail(r);
+    int last_cnt = 0, last_off = 0, herr = 0;
+    HIP_TRY(hipMemcpyAsync(&last_cnt, ncnt + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&last_off, rp + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return bail(fail(MPAP_ERR_OVERFLOW, "too many candidates share one steering cost"));
+    const long long e = (long long)last_cnt + last_off;
+    const int e32 = (int)e;
+    HIP_TRY(hipMemcpy(rp + n, &e32, sizeof(int), hipMemcpyHostToDevice));
+    if ((r = dalloc(&col, std::max(e, 1ll))) || (r = dalloc(&cost, std::max(e, 1ll))) ||
+        (r = dalloc(&drift, std::max(e, 1ll))) || (r = dalloc(&elen, std::max(e, 1ll))))
+        return bail(r);
+    k_steer_compact<<<div_up(n, 256), 256, 0, s>>>(n, k_out, rp, nbr, ncost, ncnt, col, cost);
+    k_traj_drift<<<n, 64, sizeof(float) * 5 * nf_, s>>>(a, rp, col, drift, elen);
+    {
+        BuildArgs b{};
+        b.n = n; b.dim = 3; b.pos = d_pos; b.nblob = env->n_blobs; b.mu = d_mu; b.sig = d_sig;
+        b.amp = d_amp; b.reset_q = gp->reset_q;
+        b.goal[0] = env->goal[0]; b.goal[1] = env->goal[1]; b.goal[2] = env->goal[2];
+        b.goal_r = env->goal_radius;
+        k_node_flags<<<div_up(n, 256), 256, 0, s>>>(b, flag);
+    }
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> h_rp(n + 1), h_col(e);
+    std::vector<float> h_cost(e), h_drift(e);
+    std::vector<uint8_t> h_flag(n), h_reset(n), h_goal(n);
+    HIP_TRY(hipMemcpyAsync(h_rp.data(), rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    if (e > 0) {
+        HIP_TRY(hipMemcpyAsync(h_col.data(), col, sizeof(int32_t) * e, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_cost.data(), cost, sizeof(float) * e, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_drift.data(), drift, sizeof(float) * e, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipMemcpyAsync(h_flag.data(), flag, n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int n_goal = 0;
+    for (int v = 0; v < n; ++v) {
+        h_reset[v] = h_flag[v] & 1u;
+        h_goal[v] = (h_flag[v] >> 1) & 1u;
+        n_goal += h_goal[v];
+    }
+    if (n_goal == 0) return bail(fail(MPAP_ERR_NOGOAL, "no roadmap node lies in the goal ball"));
+    mpap_graph *g = nullptr;
+    if ((r = mpap_graph_from_csr(n, h_rp.data(), h_col.data(), h_cost.data(), h_drift.data(),
+                                 h_reset.data(), h_goal.data(), stream, &g)))
+        return bail(r);
+    // keep the environment for the surrogate's inputs
+    g->dim = 6; g->nbox = env->n_boxes; g->nblob = env->n_blobs;
+    g->check_step = gp->check_step; g->reset_q = gp->reset_q; g->radius = gp->radius;
+    g->horizon = gp->horizon; g->traj_steps = gp->traj_steps; g->k_out = k_out;
+    g->pos = d_pos; g->vel = d_vel; g->bmu = d_mu; g->bsig = d_sig; g->bamp = d_amp;
+    g->elen = elen;
+    d_pos = d_vel = d_mu = d_sig = d_amp = elen = nullptr;
+    cleanup();
+    *out = g;
+    return MPAP_OK;
+}
+
+extern "C" {
 int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *stream,
                      mpap_graph **out) {
     if (!out) return fail(MPAP_ERR_INVAL, "out is null");
     *out = nullptr;
     if (!env || !gp || !env->pos) return fail(MPAP_ERR_INVAL, "null env, params or positions");
     const int dim = env->dim, n = env->n_nodes;
-    if ((dim != 2 && dim != 3) || n < 1) return fail(MPAP_ERR_INVAL, "dim must be 2 or 3, n >= 1");
+    if (dim == 6) return build_graph6(env, gp, stream, out);
+    if ((dim != 2 && dim != 3) || n < 1) return fail(MPAP_ERR_INVAL, "dim must be 2, 3 or 6, n >= 1");
     if (!(gp->radius > 0.0f) || !(gp->check_step > 0.0f) || !std::isfinite(gp->radius))
         return fail(MPAP_ERR_INVAL, "radius and check_step must be > 0");
     if (env->n_boxes < 0 || env->n_blobs < 0 ||
@@ -400,8 +542,6 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
         if (x.near_scan > 0) p.near_scan = x.near_scan;
         if (x.heuristic != 0 && x.heuristic != 1)
             return fail(MPAP_ERR_INVAL, "heuristic must be 0 (analytic) or 1 (surrogate)");
-        if (x.heuristic == 1 && !g->symmetric_alias)
-            return fail(MPAP_ERR_INVAL, "the surrogate drift needs a symmetric roadmap");
         if (x.stage_cap > 0) p.stage_cap = x.stage_cap;
     }
     if (p.max_waves <= 0) p.max_waves = 1 << 18;
@@ -466,7 +606,7 @@ SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
     SearchArgs a{};
     a.n = g->n; a.rptr = g->rptr; a.rsrc = g->rsrc; a.rcost = g->rcost;
     a.rdrift = g->rdrift; a.optr = g->optr; a.ocol = g->ocol; a.nflag = g->nflag;
-    a.sdrift = g->sdrift; a.qheur = w->qheur;
+    a.sdrift = g->symmetric_alias ? g->sdrift : g->srdrift; a.qheur = w->qheur;
     a.nq = p.nq; a.qoff = g->qoff; a.qbeta = w->qbeta; a.qnobj = w->qnobj;
     a.qroot = w->qroot; a.qlast = w->qlast;
     a.delta = p.delta; a.max_waves = p.max_waves; a.near_scan = p.near_scan;
@@ -658,7 +798,7 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
     int r = search_prep(g, sp, nsp, p);
     if (r) return r;
     for (int q = 0; q < p.nq; ++q)
-        if (p.heur[q] == 1 && !g->sdrift)
+        if (p.heur[q] == 1 && !(g->symmetric_alias ? g->sdrift : g->srdrift))
             return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph (mpap_surrogate_score)");
     SearchShape L;
     if ((r = search_shape(p.stage_cap, L))) return r;
@@ -827,6 +967,7 @@ void graph_release(mpap_graph *g) {
     }
     dfree(g->optr); dfree(g->ocol); dfree(g->ocost); dfree(g->odrift);
     dfree(g->nflag); dfree(g->goal_list); dfree(g->qoff); dfree(g->qgoff);
-    dfree(g->pos); dfree(g->bmu); dfree(g->bsig); dfree(g->bamp); dfree(g->feat); dfree(g->sdrift);
+    dfree(g->pos); dfree(g->bmu); dfree(g->bsig); dfree(g->bamp); dfree(g->feat); dfree(g->sbase); dfree(g->sdrift);
+    dfree(g->vel); dfree(g->elen); dfree(g->rperm); dfree(g->srdrift);
     delete g;
 }

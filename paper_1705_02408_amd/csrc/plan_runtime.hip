@@ -257,7 +257,7 @@ int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
     if (scoring && !g->sdrift && (r = dalloc(&g->sdrift, std::max<long long>(g->e, 1))))
         return bail(r);
     for (int q = 0; q < p->prep.nq; ++q)
-        if (p->prep.heur[q] == 1 && !g->sdrift)
+        if (p->prep.heur[q] == 1 && !(g->symmetric_alias ? g->sdrift : g->srdrift))
             return bail(fail(MPAP_ERR_INVAL, "no surrogate drift on this graph"));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // score once eagerly so the sizing search sees the same drift

@@ -113,7 +113,17 @@ struct mpap_graph {
     int dim = 0, nbox = 0, nblob = 0;
     float check_step = 0.f, reset_q = 0.f, radius = 0.f;
     float *pos = nullptr, *bmu = nullptr, *bsig = nullptr, *bamp = nullptr;
+    // double integrator (dim 6): velocities, steering time, check steps, and
+    // the trajectory length of every edge (the drift's length)
+    float *vel = nullptr, *elen = nullptr;
+    float horizon = 0.f;
+    int traj_steps = 0, k_out = 0;
+    // directed roadmaps: reverse slot -> forward edge index, and the
+    // surrogate drift in reverse order
+    int32_t *rperm = nullptr;
+    float *srdrift = nullptr;
     uint16_t *feat = nullptr;  // [E][16] bf16 surrogate inputs, computed on demand
+    float *sbase = nullptr;    // [E] 8-point estimate of the mean of (1 - q) per edge
     float *sdrift = nullptr;   // [E] surrogate drift (forward edge order)
     std::vector<Workspace *> spare;
     std::mutex mu;

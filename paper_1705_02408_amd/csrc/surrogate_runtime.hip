@@ -4,6 +4,13 @@
 #include "device_common.h"
 #include "mlp_kernels.h"
 #include "runtime_internal.h"
+#include "steer_kernels.h"
+
+// out[i] = in[perm[i]]
+__global__ void k_gather_f32(long long n, const int *perm, const float *in, float *out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[perm[i]];
+}
 
 struct mpap_surrogate {
     int dev = -1;
@@ -107,18 +114,44 @@ __global__ void k_zero_f32(float *p, int n) {
     if (i < n) p[i] = 0.f;
 }
 
+SteerArgs steer_view(const mpap_graph *g) {
+    SteerArgs a{};
+    a.n = g->n; a.pos = g->pos; a.vel = g->vel; a.nbox = 0; a.nblob = g->nblob; a.mu = g->bmu;
+    a.sig = g->bsig; a.amp = g->bamp; a.T = g->horizon; a.K = g->traj_steps; a.k_out = g->k_out;
+    return a;
+}
+
+// edge lengths the drift is proportional to (trajectory length for dim 6)
+const float *drift_length(const mpap_graph *g) { return g->elen ? g->elen : g->ocost; }
+
+// surrogate inputs and 8-point base of every edge, enqueued on st
+int enqueue_features(mpap_graph *g, hipStream_t st) {
+    if (!g->pos) return fail(MPAP_ERR_INVAL, "graph has no environment (build it with mpap_build_graph)");
+    int r;
+    if (!g->feat && (r = dalloc(&g->feat, (size_t)std::max<long long>(g->e, 1) * kMlpIn))) return r;
+    if (!g->sbase && (r = dalloc(&g->sbase, std::max<long long>(g->e, 1)))) return r;
+    if (g->n == 0) return MPAP_OK;
+    if (g->dim == 6) {
+        k_traj_features<<<g->n, 64, sizeof(float) * 5 * (size_t)g->nblob, st>>>(
+            steer_view(g), g->optr, g->ocol, g->elen, g->feat, g->sbase);
+    } else {
+        BuildArgs a{};
+        a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu;
+        a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
+        a.reset_q = g->reset_q;
+        const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
+        k_edge_features<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->feat,
+                                               g->sbase);
+    }
+    HIP_TRY(hipGetLastError());
+    return MPAP_OK;
+}
+
 // graph features on demand (roadmaps built by mpap_build_graph only)
 int ensure_features(mpap_graph *g, hipStream_t st) {
     if (g->feat) return MPAP_OK;
-    if (!g->pos) return fail(MPAP_ERR_INVAL, "graph has no environment (build it with mpap_build_graph)");
-    int r;
-    if ((r = dalloc(&g->feat, (size_t)std::max<long long>(g->e, 1) * kMlpIn))) return r;
-    BuildArgs a{};
-    a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu; a.sig = g->bsig;
-    a.amp = g->bamp; a.r = g->radius; a.step = g->check_step; a.reset_q = g->reset_q;
-    const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
-    if (g->n > 0) k_edge_features<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->feat);
-    HIP_TRY(hipGetLastError());
+    int r = enqueue_features(g, st);
+    if (r) return r;
     HIP_TRY(hipStreamSynchronize(st));
     return MPAP_OK;
 }
@@ -204,11 +237,12 @@ int mpap_surrogate_init(mpap_surrogate *s, uint64_t seed) {
     };
     for (int i = 0; i < kMlpIn * kMlpH; ++i) p[kOffW1 + i] = (float)(normal() * std::sqrt(2.0 / kMlpIn));
     for (int i = 0; i < kMlpH * kMlpH; ++i) p[kOffW2 + i] = (float)(normal() * std::sqrt(2.0 / kMlpH));
-    for (int i = 0; i < kMlpH; ++i) p[kOffW3 + i] = (float)(normal() * std::sqrt(2.0 / kMlpH));
+    // output layer zero: an untrained network predicts exactly the 8-point base
     return mpap_surrogate_set_params(s, p.data(), kMlpParams);
 }
 
-int mpap_edge_features(const mpap_graph *gc, void *stream, uint16_t *out, int64_t capacity) {
+int mpap_edge_features(const mpap_graph *gc, void *stream, uint16_t *out, int64_t capacity,
+                       float *base) {
     if (!gc) return fail(MPAP_ERR_INVAL, "null graph");
     mpap_graph *g = const_cast<mpap_graph *>(gc);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -218,6 +252,8 @@ int mpap_edge_features(const mpap_graph *gc, void *stream, uint16_t *out, int64_
         if (capacity < g->e * kMlpIn) return fail(MPAP_ERR_CAPACITY, "capacity below 16 * edges");
         HIP_TRY(hipMemcpy(out, g->feat, sizeof(uint16_t) * kMlpIn * g->e, hipMemcpyDeviceToHost));
     }
+    if (base && g->e > 0)
+        HIP_TRY(hipMemcpy(base, g->sbase, sizeof(float) * g->e, hipMemcpyDeviceToHost));
     return MPAP_OK;
 }
 
@@ -234,7 +270,7 @@ int mpap_surrogate_forward(const mpap_surrogate *s, const uint16_t *X, int64_t n
     hipError_t he = hipMemcpy(dX, X, sizeof(uint16_t) * kMlpIn * n, hipMemcpyHostToDevice);
     if (he == hipSuccess) {
         const int blocks = std::max(1, std::min(div_up(n, 128), 1024));
-        k_mlp_infer<<<blocks, 256>>>(dev_view(s), dX, n, nullptr, dy, nullptr);
+        k_mlp_infer<<<blocks, 256>>>(dev_view(s), dX, n, nullptr, nullptr, dy, nullptr);
         he = hipGetLastError();
     }
     if (he == hipSuccess) he = hipMemcpy(y, dy, sizeof(float) * n, hipMemcpyDeviceToHost);
@@ -297,19 +333,26 @@ int mpap_surrogate_train(mpap_surrogate *s, const mpap_graph *gc, const int64_t 
         if ((r = dalloc(&s->idx, n_train))) return r;
         s->idx_cap = n_train;
     }
-    k_drift_ratio<<<div_up(g->e, 256), 256, 0, st>>>(g->e, g->odrift, g->ocost, s->t_all);
+    k_drift_ratio<<<div_up(g->e, 256), 256, 0, st>>>(g->e, g->odrift, drift_length(g), g->sbase,
+                                                     kResidualScale, s->t_all);
     HIP_TRY(hipMemcpyAsync(s->idx, edges, sizeof(long long) * n_train, hipMemcpyHostToDevice, st));
     const long long steps = n_train / batch;
+    const double total = std::max<double>(1.0, (double)steps * epochs);
     for (int ep = 0; ep < epochs; ++ep) {
-        for (long long k = 0; k < steps; ++k)
-            if ((r = sur_batch(s, g->feat, s->t_all, s->idx + k * batch, lr, true, nullptr, st)))
+        for (long long k = 0; k < steps; ++k) {
+            // cosine decay from lr to lr/100 over the whole run
+            const double f = ((double)ep * steps + k) / total;
+            const float lr_k = (float)(lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(3.141592653589793 * f))));
+            if ((r = sur_batch(s, g->feat, s->t_all, s->idx + k * batch, lr_k, true, nullptr, st)))
                 return r;
+        }
         if (epoch_loss) {
             // mean squared error of the updated network over the training edges
             float *yall = nullptr;
             if ((r = dalloc(&yall, g->e))) return r;
             const int blocks = std::max(1, std::min(div_up(g->e, 128), 2048));
-            k_mlp_infer<<<blocks, 256, 0, st>>>(dev_view(s), g->feat, g->e, nullptr, yall, nullptr);
+            k_mlp_infer<<<blocks, 256, 0, st>>>(dev_view(s), g->feat, g->e, nullptr, nullptr,
+                                                yall, nullptr);
             k_zero_f32<<<1, 64, 0, st>>>(s->sq, 1);
             k_sq_err<<<std::max(1, std::min(div_up(n_train, 256), 1024)), 256, 0, st>>>(
                 yall, s->t_all, s->idx, n_train, s->sq);
@@ -328,7 +371,8 @@ int mpap_surrogate_score(const mpap_surrogate *s, mpap_graph *g, void *stream, f
     if (!s || !g) return fail(MPAP_ERR_INVAL, "null argument");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int r;
-    if (!g->sdrift && g->symmetric_alias && (r = dalloc(&g->sdrift, std::max<long long>(g->e, 1))))
+    if (!g->sdrift && (r = dalloc(&g->sdrift, std::max<long long>(g->e, 1)))) return r;
+    if (!g->symmetric_alias && !g->srdrift && (r = dalloc(&g->srdrift, std::max<long long>(g->e, 1))))
         return r;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -360,7 +404,11 @@ int mpap_analytic_drift(mpap_graph *g, void *stream, float *ms) {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    if (g->n > 0) k_edge_drift<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->odrift);
+    if (g->n > 0 && g->dim == 6)
+        k_traj_drift<<<g->n, 64, sizeof(float) * 5 * (size_t)g->nblob, st>>>(
+            steer_view(g), g->optr, g->ocol, g->odrift, nullptr);
+    else if (g->n > 0)
+        k_edge_drift<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->odrift);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipEventSynchronize(e1));
@@ -444,24 +492,18 @@ int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *
 
 int sur_enqueue_score(const mpap_surrogate *s, mpap_graph *g, float *out, hipStream_t st) {
     if (!s || !g) return fail(MPAP_ERR_INVAL, "null argument");
-    if (!g->symmetric_alias) return fail(MPAP_ERR_INVAL, "graph is not a symmetric roadmap");
     if (!out) return fail(MPAP_ERR_INVAL, "no drift array to score into");
-    if (!g->pos) return fail(MPAP_ERR_INVAL, "graph has no environment (build it with mpap_build_graph)");
-    int r;
-    if (!g->feat && (r = dalloc(&g->feat, (size_t)std::max<long long>(g->e, 1) * kMlpIn))) return r;
-    {
-        // the inputs are part of the cost of scoring a roadmap: recompute them
-        BuildArgs a{};
-        a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu;
-        a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
-        a.reset_q = g->reset_q;
-        const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
-        if (g->n > 0)
-            k_edge_features<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->feat);
-    }
+    // the inputs are part of the cost of scoring a roadmap: recompute them
+    int r = enqueue_features(g, st);
+    if (r) return r;
     if (g->e > 0) {
         const int blocks = std::max(1, std::min(div_up(g->e, 128), 2048));
-        k_mlp_infer<<<blocks, 256, 0, st>>>(dev_view(s), g->feat, g->e, g->ocost, nullptr, out);
+        k_mlp_infer<<<blocks, 256, 0, st>>>(dev_view(s), g->feat, g->e, drift_length(g), g->sbase,
+                                            nullptr, out);
+        if (!g->symmetric_alias && out == g->sdrift) {
+            // in-edge order for the search of a directed roadmap
+            k_gather_f32<<<div_up(g->e, 256), 256, 0, st>>>(g->e, g->rperm, g->sdrift, g->srdrift);
+        }
     }
     HIP_TRY(hipGetLastError());
     return MPAP_OK;

@@ -38,12 +38,14 @@ class mpap_env(ctypes.Structure):
                 ("box_lo", ctypes.c_void_p), ("box_hi", ctypes.c_void_p),
                 ("n_blobs", ctypes.c_int32), ("blob_mu", ctypes.c_void_p),
                 ("blob_sigma", ctypes.c_void_p), ("blob_amp", ctypes.c_void_p),
-                ("goal", ctypes.c_float * 3), ("goal_radius", ctypes.c_float)]
+                ("goal", ctypes.c_float * 3), ("goal_radius", ctypes.c_float),
+                ("vel", ctypes.c_void_p)]
 
 
 class mpap_graph_params(ctypes.Structure):
     _fields_ = [("radius", ctypes.c_float), ("check_step", ctypes.c_float),
-                ("reset_q", ctypes.c_float)]
+                ("reset_q", ctypes.c_float), ("k_out", ctypes.c_int32),
+                ("horizon", ctypes.c_float), ("traj_steps", ctypes.c_int32)]
 
 
 class mpap_search_params(ctypes.Structure):
@@ -117,7 +119,7 @@ def load(path: str = LIB_PATH):
     lib.mpap_surrogate_set_params.argtypes = [P, P, I32]
     lib.mpap_surrogate_get_params.argtypes = [P, P, I32, P]
     lib.mpap_surrogate_init.argtypes = [P, ctypes.c_uint64]
-    lib.mpap_edge_features.argtypes = [P, P, P, I64]
+    lib.mpap_edge_features.argtypes = [P, P, P, I64, P]
     lib.mpap_surrogate_forward.argtypes = [P, P, I64, P]
     lib.mpap_surrogate_gradient.argtypes = [P, P, P, I32, P, P]
     lib.mpap_surrogate_train.argtypes = [P, P, P, I64, I32, I32, ctypes.c_float, P, P]
@@ -240,14 +242,21 @@ def mpap_build_graph(env, radius=None, check_step=None, reset_q=None, stream=Non
     e.blob_mu = _p(mu).value
     e.blob_sigma = _p(sg).value
     e.blob_amp = _p(am).value
+    wdim = 3 if env.dim == 6 else env.dim
     gl = np.zeros(3, np.float32)
-    gl[: env.dim] = env.goal
+    gl[:wdim] = env.goal
     for k in range(3):
         e.goal[k] = float(gl[k])
     e.goal_radius = float(env.goal_radius)
+    vel = None
+    if env.dim == 6:
+        vel = np.ascontiguousarray(env.vel, np.float32)
+        e.vel = _p(vel).value
     gp = mpap_graph_params(float(env.radius if radius is None else radius),
                            float(env.check_step if check_step is None else check_step),
-                           float(env.reset_q if reset_q is None else reset_q))
+                           float(env.reset_q if reset_q is None else reset_q),
+                           int(getattr(env, "k_out", 0)), float(getattr(env, "horizon", 0.0)),
+                           int(getattr(env, "traj_steps", 0)))
     h = ctypes.c_void_p()
     _check(lib.mpap_build_graph(ctypes.byref(e), ctypes.byref(gp), _stream(stream),
                                 ctypes.byref(h)))
@@ -492,11 +501,13 @@ class Surrogate:
             pass
 
 
-def mpap_edge_features(graph: Graph) -> np.ndarray:
+def mpap_edge_features(graph: Graph, with_base: bool = False):
+    """[e, 16] bfloat16 bit patterns (and, with_base, the float32 8-point base)."""
     e = graph.info()["e"]
     out = np.empty((e, 16), np.uint16)
-    _check(load().mpap_edge_features(graph.handle, None, _p(out), out.size))
-    return out
+    base = np.empty(e, np.float32)
+    _check(load().mpap_edge_features(graph.handle, None, _p(out), out.size, _p(base)))
+    return (out, base) if with_base else out
 
 
 def mpap_analytic_drift(graph: Graph, stream=None) -> float:

@@ -236,7 +236,7 @@ def plain6d(seed: int = 0, n: int = 50000) -> Env:
     vel = np.concatenate([np.zeros((1, 3), np.float32), _unit_ball(seed, n)], axis=0)
     return Env(dim=6, pos=pos.astype(np.float32), box_lo=lo, box_hi=hi, blob_mu=mu,
                blob_sigma=sig, blob_amp=amp, goal=goal, goal_radius=float(np.float32(0.05)),
-               radius=0.1, beta=float(np.float32(0.3)), n_obj=2, name=f"plain6d_n{n}_s{seed}",
+               radius=1.0, beta=float(np.float32(0.3)), n_obj=2, name=f"plain6d_n{n}_s{seed}",
                seed=seed, vel=vel, k_out=30, horizon=0.5, traj_steps=100)
 
 

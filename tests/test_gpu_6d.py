@@ -1,0 +1,107 @@
+"""Double-integrator (6D state) roadmaps: the device build against the oracle
+build, the search on the oracle's arrays (shared input) against the oracle
+search, and the learned drift surrogate on 6D edges."""
+import numpy as np
+import pytest
+
+from oracle import graph6d, mlp, search as osearch
+from paper_1705_02408_amd import synth
+from tests.test_gpu_search import bits, check_against_oracle
+
+pytestmark = pytest.mark.gpu
+mpap = pytest.importorskip("paper_1705_02408_amd.mpap")
+
+
+def env6(seed, n, goal_radius=0.15):
+    env = synth.plain6d(seed, n=n)
+    env.goal_radius = goal_radius
+    return env
+
+
+@pytest.fixture(scope="module")
+def built():
+    env = env6(0, 1500)
+    ref = graph6d.build_graph6d(env)
+    dg = mpap.mpap_build_graph(env)
+    print(f"6D roadmap: {dg.info()}", flush=True)
+    yield env, ref, dg
+    dg.close()
+
+
+def test_device_build_matches_oracle(built):
+    env, ref, dg = built
+    got = dg.export()
+    # neighbour selection (steering cost order, reachability): exact
+    assert np.array_equal(got["row_ptr"], ref["row_ptr"])
+    assert np.array_equal(got["col"], ref["col"])
+    assert np.array_equal(bits(got["cost"]), bits(ref["cost"]))
+    assert np.array_equal(got["goal"], ref["goal"])
+    # drift: float32 device sum of K chord terms vs float64
+    err = np.abs(got["drift"].astype(np.float64) - ref["drift"].astype(np.float64))
+    assert np.all(err <= 1e-5 * ref["drift"] + 1e-6), float(err.max())
+    clear = np.abs(ref["q"] - env.reset_q) > 1e-4
+    assert np.array_equal(got["reset"][clear], ref["reset"][clear])
+
+
+@pytest.mark.parametrize("seed,n", [(1, 1200), (2, 2000)])
+def test_search_on_oracle_arrays_matches_oracle(seed, n):
+    env = env6(seed, n)
+    g = graph6d.build_graph6d(env)
+    if g["goal"].sum() == 0:
+        pytest.skip("no goal sample")
+    ref = osearch.search(g, env.beta, env.n_obj)
+    dg = mpap.mpap_graph_from_csr(g["row_ptr"], g["col"], g["cost"], g["drift"], g["reset"],
+                                  g["goal"])
+    res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam)
+    print(f"6D n={n}: X={ref.X}, goal front {res.goal_front().vecs.shape[0]}", flush=True)
+    check_against_oracle(g, res, ref, env.beta, env.n_obj, all_nodes=False, node_stride=3)
+    res.close()
+    dg.close()
+
+
+def test_search_on_device_built_roadmap_matches_oracle_on_same_arrays(built):
+    env, _, dg = built
+    g = dg.export()
+    ref = osearch.search(g, env.beta, env.n_obj)
+    res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam)
+    check_against_oracle(g, res, ref, env.beta, env.n_obj, all_nodes=False, node_stride=4)
+    res.close()
+
+
+def test_features_match_oracle(built):
+    env, _, dg = built
+    g = dg.export()
+    X, base = mpap.mpap_edge_features(dg, with_base=True)
+    f, rbase, _ = graph6d.edge_features6d(env, g)
+    rb = mlp.bf16_bits(mlp.bf16_round(f))
+    assert np.array_equal(X[:, :6], rb[:, :6])
+    xv = (X[:, 6:].astype(np.uint32) << 16).view(np.float32)
+    rv = f[:, 6:]
+    assert np.all(np.abs(xv - rv) <= 2.0 ** -8 * np.abs(rv) + 2e-6)
+    assert np.all(np.abs(base - rbase) <= 1e-5 * np.abs(rbase) + 1e-6)
+
+
+def test_surrogate_on_6d_edges(built):
+    """Train on 70% of the edges, score all, search on the learned drift; the
+    analytic re-walk judges the front (and the analytic search stays exact)."""
+    env, _, dg = built
+    e = dg.info()["e"]
+    perm = np.random.default_rng(3).permutation(e)
+    n_tr = (int(0.7 * e) // 1024) * 1024
+    s = mpap.Surrogate(seed=6)
+    loss = s.train(dg, perm[:n_tr], epochs=12, batch=1024, lr=2e-3)
+    assert np.all(np.isfinite(loss)) and loss[-1] <= loss[0]
+    s.score(dg)
+    ana = mpap.mpap_graph_drift(dg, 0).astype(np.float64)
+    sur = mpap.mpap_graph_drift(dg, 1).astype(np.float64)
+    held = perm[n_tr:]
+    rel = np.abs(sur - ana)[held] / np.maximum(ana[held], 1e-3 * env.beta)
+    print(f"6D held-out median rel err {np.median(rel):.3g}, p90 {np.percentile(rel, 90):.3g}")
+    assert np.median(rel) < 0.02
+    res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam, heuristic=1)
+    ok = mpap.surrogate_front_ok(res, 0, env.beta)
+    rs = mpap.mpap_rescore_front(res, 0)
+    assert np.array_equal(bits(rs["cost"]), bits(res.goal_front().vecs[:, 0]))
+    print(f"6D surrogate front: {res.goal_front().vecs.shape[0]} labels, judge {ok}")
+    res.close()
+    s.close()
