@@ -154,7 +154,8 @@ typedef struct {
  * mpap_search - Alg. 3 (Explore) run until no plan is open, on the GPU.
  *   Labels (head, cost c, drift d [, max drift m], parent) are expanded in
  *   groups of open labels whose cost is at most the current threshold, which
- *   rises by lambda * radius per iteration (skipping empty groups).  A child
+ *   is i * lambda * radius at iteration i (float32; iterations whose group
+ *   would be empty are skipped).  A child
  *   along edge e = u->v has c + cost_e, d_pre = d + drift_e; it is dropped if
  *   d_pre > beta; its drift is 0 if reset[v] else d_pre; m = max(m, d_pre).
  *   RemoveDominated is weak Pareto dominance per head node (a label is removed
@@ -203,9 +204,11 @@ int mpap_graph_queries(const mpap_graph *g, int32_t *nq, int32_t *node_offset);
 
 /* mpap_search_batch - mpap_search over every query of g in one launch.  sp
  * holds one parameter set per query (n_params == nq) or one for all
- * (n_params == 1); init_node is relative to the query.  The group threshold
- * advances by the least lambda * radius of the set (the fronts do not depend
- * on it).  Errors as mpap_search. */
+ * (n_params == 1); init_node is relative to the query.  All queries share
+ * the iteration index i; query q's group holds its open labels of cost at
+ * most i * lambda_q * radius_q (float32), and an iteration with no group
+ * label in any query is skipped (the fronts do not depend on the steps).
+ * Errors as mpap_search. */
 int mpap_search_batch(const mpap_graph *g, const mpap_search_params *sp, int32_t n_params,
                       void *stream, mpap_result **out);
 

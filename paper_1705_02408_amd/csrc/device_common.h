@@ -93,6 +93,20 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *scratc
     return s;
 }
 
+__device__ __forceinline__ long long block_min_ll(long long v, long long *scratch) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (long long)__shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) scratch[w] = v;
+    __syncthreads();
+    long long s = scratch[0];
+    for (int i = 1; i < nw; ++i) s = min(s, scratch[i]);
+    __syncthreads();
+    return s;
+}
+
 __device__ __forceinline__ float block_min(float v, float *scratch) {
     v = wave_min(v);
     const int w = threadIdx.x >> 6;

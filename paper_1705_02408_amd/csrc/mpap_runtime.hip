@@ -526,7 +526,6 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
         return fail(MPAP_ERR_INVAL, "need one parameter set per query (or one for all)");
     p = SearchPrep{};
     p.nq = nq;
-    p.delta = __builtin_inff();
     for (int q = 0; q < nsp; ++q) {
         const mpap_search_params &x = sp[q];
         const int qn = g->qoff_h[(nsp == 1 ? 0 : q) + 1] - g->qoff_h[nsp == 1 ? 0 : q];
@@ -537,7 +536,6 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
         const float dq = x.lambda * x.radius;
         if (!(dq > 0.0f) || !std::isfinite(dq))
             return fail(MPAP_ERR_INVAL, "lambda * radius must be finite and > 0");
-        p.delta = std::min(p.delta, dq);
         p.max_waves = std::max(p.max_waves, x.max_waves);
         if (x.near_scan > 0) p.near_scan = x.near_scan;
         if (x.heuristic != 0 && x.heuristic != 1)
@@ -551,12 +549,14 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
                 return fail(MPAP_ERR_INVAL, "init_node out of range for a query");
     }
     p.beta.resize(nq);
+    p.delta.resize(nq);
     p.nobj.resize(nq);
     p.root.resize(nq);
     p.heur.resize(nq);
     for (int q = 0; q < nq; ++q) {
         const mpap_search_params &x = sp[nsp == 1 ? 0 : q];
         p.beta[q] = x.beta;
+        p.delta[q] = x.lambda * x.radius;
         p.nobj[q] = x.n_obj;
         p.root[q] = g->qoff_h[q] + x.init_node;
         p.heur[q] = x.heuristic;
@@ -595,6 +595,7 @@ int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s) {
     const size_t nq = p.nq;
     HIP_TRY(hipMemcpyAsync(w->qheur, p.heur.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w->qbeta, p.beta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qdelta, p.delta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w->qnobj, p.nobj.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w->qroot, p.root.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -609,13 +610,13 @@ SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
     a.sdrift = g->symmetric_alias ? g->sdrift : g->srdrift; a.qheur = w->qheur;
     a.nq = p.nq; a.qoff = g->qoff; a.qbeta = w->qbeta; a.qnobj = w->qnobj;
     a.qroot = w->qroot; a.qlast = w->qlast;
-    a.delta = p.delta; a.max_waves = p.max_waves; a.near_scan = p.near_scan;
+    a.qdelta = w->qdelta; a.max_waves = p.max_waves; a.near_scan = p.near_scan;
     a.capB = L.capB; a.capC = L.capC; a.nblocks = L.nblocks;
     a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
     a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
     a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
     a.arena = w->arena; a.arena_cap = std::min<long long>(w->arena_cap, 0x7ffffff0ll);
-    a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_min = w->part_min;
+    a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_step = w->part_step;
     a.bar = w->bar; a.err = w->err; a.out = w->out;
     a.wstat = w->wstat; a.wstat_cap = kTraceCap;
     a.spill = w->spill; a.spill_flags = w->spill_flags; a.capG = (int)w->spill_cap;

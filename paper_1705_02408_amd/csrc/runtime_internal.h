@@ -162,7 +162,7 @@ struct Workspace {
     float4 *F = nullptr;
     int2 *arena = nullptr;
     long long *part_cnt = nullptr, *part_open = nullptr;
-    float *part_min = nullptr;
+    long long *part_step = nullptr;
     unsigned *bar = nullptr;
     int *err = nullptr;
     long long *out = nullptr;
@@ -174,6 +174,7 @@ struct Workspace {
     int nq_cap = 0;
     float *qbeta = nullptr;
     int *qnobj = nullptr, *qroot = nullptr, *qlast = nullptr, *qheur = nullptr;
+    float *qdelta = nullptr;
     long long *g_laboff = nullptr;
     int *g_labcap = nullptr;
     int *g_overflow = nullptr;
@@ -189,11 +190,12 @@ struct Workspace {
     void free_all() {
         dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
         dfree(mark); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
-        dfree(part_open); dfree(part_min); dfree(bar); dfree(err); dfree(out); dfree(wstat);
+        dfree(part_open); dfree(part_step); dfree(bar); dfree(err); dfree(out); dfree(wstat);
         dfree(spill); dfree(spill_flags);
         dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count); dfree(g_total);
         dfree(p_lab); dfree(p_node);
-        dfree(qbeta); dfree(qnobj); dfree(qroot); dfree(qlast); dfree(qheur); dfree(g_laboff);
+        dfree(qbeta); dfree(qnobj); dfree(qroot); dfree(qlast); dfree(qheur); dfree(qdelta);
+        dfree(g_laboff);
         dfree(g_labcap); dfree(g_overflow);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -216,7 +218,7 @@ inline int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     if ((r = dalloc(&w->mcur, 2))) return r;
     if ((r = dalloc(&w->part_cnt, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->part_open, 2 * (size_t)nblocks))) return r;
-    if ((r = dalloc(&w->part_min, 2 * (size_t)nblocks))) return r;
+    if ((r = dalloc(&w->part_step, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->bar, 1))) return r;
     if ((r = dalloc(&w->err, 1))) return r;
     if ((r = dalloc(&w->out, kOutWords))) return r;
@@ -231,8 +233,9 @@ inline int ws_queries(Workspace *w, int nq) {
     if (nq <= w->nq_cap) return MPAP_OK;
     int r;
     dfree(w->qbeta); dfree(w->qnobj); dfree(w->qroot); dfree(w->qlast); dfree(w->g_laboff);
-    dfree(w->g_labcap); dfree(w->g_n); dfree(w->g_count); dfree(w->qheur);
+    dfree(w->g_labcap); dfree(w->g_n); dfree(w->g_count); dfree(w->qheur); dfree(w->qdelta);
     if ((r = dalloc(&w->qbeta, nq)) || (r = dalloc(&w->qnobj, nq)) || (r = dalloc(&w->qheur, nq)) ||
+        (r = dalloc(&w->qdelta, nq)) ||
         (r = dalloc(&w->qroot, nq)) || (r = dalloc(&w->qlast, nq)) ||
         (r = dalloc(&w->g_laboff, nq)) || (r = dalloc(&w->g_labcap, nq)) ||
         (r = dalloc(&w->g_n, nq)) || (r = dalloc(&w->g_count, nq)))
@@ -318,7 +321,7 @@ struct mpap_result {
 // Validated per-query parameters of one batched search.
 struct SearchPrep {
     int nq = 0;
-    float delta = 0.f;
+    std::vector<float> delta;  // per query lambda * radius
     int max_waves = 0, near_scan = 16, stage_cap = 0;
     std::vector<float> beta;
     std::vector<int> nobj, root, heur;

@@ -51,7 +51,8 @@ struct SearchArgs {
     const uint8_t *nflag; // bit 0: relocalise on arrival; bit 1: goal
     // queries: the roadmap is the disjoint union of nq query roadmaps, query q
     // owning nodes [qoff[q], qoff[q+1]); each has its own bound, objective
-    // count and root, and the same group-threshold step delta
+    // count, root and group-threshold step (query q's group of iteration i
+    // holds its open labels of cost <= i * qdelta[q])
     int nq;
     const int *qoff;     // [nq+1]
     const float *qbeta;  // [nq]
@@ -60,7 +61,7 @@ struct SearchArgs {
     const int *qheur;    // [nq] 1: drift from the learned surrogate (sdrift)
     const float *sdrift; // surrogate drift, in-edge order (the roadmap is symmetric)
     int *qlast;          // [nq] last wave with a group label of the query
-    float delta;         // lambda * r_n
+    const float *qdelta; // [nq] lambda * r_n of the query
     int max_waves;
     int near_scan;       // bucket labels tested per candidate before the full scan
     int capB;  // LDS staging capacity of a front (labels)
@@ -84,7 +85,7 @@ struct SearchArgs {
     long long arena_cap;
     long long *part_cnt;   // [2][nblocks]
     long long *part_open;  // [2][nblocks]
-    float *part_min;       // [2][nblocks]
+    long long *part_step;  // [2][nblocks] least iteration index with a non-empty group
     unsigned *bar;
     int *err;
     long long *out;    // [kOutWords]

@@ -40,26 +40,46 @@ __device__ __forceinline__ int query_of(const SearchArgs &a, int v) {
     return lo;
 }
 
+// group step of the query owning node v
+__device__ __forceinline__ float step_of(const SearchArgs &a, int v) {
+    return a.qdelta[a.nq > 1 ? query_of(a, v) : 0];
+}
+
+// threshold of iteration i for a query of step d: T = i * d (float32)
+__device__ __forceinline__ float threshold(long long i, float d) { return (float)i * d; }
+
+// least iteration index whose threshold reaches cost c (float32 exact)
+__device__ __forceinline__ long long first_step(float c, float d) {
+    const float r = ceilf(c / d);
+    long long i = r < 9.0e15f ? (long long)fmaxf(r, 0.0f) : (1ll << 53);
+    while (threshold(i, d) < c) ++i;
+    while (i > 0 && threshold(i - 1, d) >= c) --i;
+    return i;
+}
+
 // ------------------------------------------------------------------ P1
 // Nodes of the block's range are taken a tile (one per thread) at a time; the
 // nodes whose least open cost is within the threshold go to an LDS list and
 // the block's waves count their group labels in parallel, one node per wave.
-__device__ void phase_count(const SearchArgs &a, float T, int par, int lo, int hi,
-                            int *list, int *scan, long long *red_ll, float *red_f) {
+__device__ void phase_count(const SearchArgs &a, long long istep, int par, int lo, int hi,
+                            int *list, int *scan, long long *red_ll) {
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     long long grp = 0, open_nodes = 0;
-    float mn = MPAP_INF;
+    long long mn = 0x7fffffffffffffffll;
     for (int tb = lo; tb < hi; tb += blockDim.x) {
         const int v = tb + threadIdx.x;
         bool need = false;
         if (v < hi) {
             const float mo = a.minopen[v];
-            need = mo <= T;
+            if (mo < MPAP_INF) {
+                const float d = step_of(a, v);
+                need = mo <= threshold(istep, d);
+                open_nodes += 1;
+                mn = min(mn, first_step(mo, d));
+            }
             if (!need) a.gcnt[v] = 0;
-            if (mo < MPAP_INF) open_nodes += 1;
-            mn = fminf(mn, mo);
         }
         int nflag;
         const int ex = block_excl_scan(need ? 1 : 0, scan, &nflag);
@@ -68,6 +88,7 @@ __device__ void phase_count(const SearchArgs &a, float T, int par, int lo, int h
         for (int i = w; i < nflag; i += nw) {
             const int vv = list[i];
             const int4 nbv = a.nb[vv];
+            const float T = threshold(istep, step_of(a, vv));
             // open labels at or below T lie in the prefix of the sorted bucket
             int cnt = 0;
             for (int k = l; k < nbv.z; k += 64) {
@@ -85,11 +106,11 @@ __device__ void phase_count(const SearchArgs &a, float T, int par, int lo, int h
     }
     long long g = block_sum_ll(grp, red_ll);
     long long o = block_sum_ll(open_nodes, red_ll);
-    float bm = block_min(mn, red_f);
+    long long bm = block_min_ll(mn, red_ll);
     if (threadIdx.x == 0) {
         a.part_cnt[par * a.nblocks + blockIdx.x] = g;
         a.part_open[par * a.nblocks + blockIdx.x] = o;
-        a.part_min[par * a.nblocks + blockIdx.x] = bm;
+        a.part_step[par * a.nblocks + blockIdx.x] = bm;
     }
 }
 
@@ -98,7 +119,7 @@ __device__ void phase_count(const SearchArgs &a, float T, int par, int lo, int h
 // of the per-node counts on top of the block's offset); each flagged node is
 // then handled by one wave: its group labels are copied to the frontier,
 // closed and given their arena ids, and its out-neighbours are queued.
-__device__ void phase_select(const SearchArgs &a, float T, int wave, long long abase,
+__device__ void phase_select(const SearchArgs &a, long long istep, int wave, long long abase,
                              long long myoff, int lo, int hi, int *list, int *list_off,
                              int *scan) {
     const int l = lane_id();
@@ -122,6 +143,7 @@ __device__ void phase_select(const SearchArgs &a, float T, int wave, long long a
             const int vv = list[i];
             const int goff = list_off[i];
             const int4 nbv = a.nb[vv];
+            const float T = threshold(istep, step_of(a, vv));
             int run = 0;
             float rmin = MPAP_INF;
             // the bucket is sorted by cost: group labels lie below T; past T
@@ -619,7 +641,6 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
     carve_lds(lds, a, s);
 
     __shared__ long long red_ll[16];
-    __shared__ float red_f[16];
 
     const int G = (int)gridDim.x;
     const int b = (int)blockIdx.x;
@@ -627,8 +648,7 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
     const int hi = (int)((long long)(b + 1) * a.n / G);
 
     unsigned epoch = 0;
-    float T = 0.0f;        // group threshold of this iteration
-    long long i_step = 0;  // threshold index: T = i_step * delta (unless jumped)
+    long long i_step = 0;  // iteration index: query q's threshold is i_step * qdelta[q]
     int wave = 0;          // number of groups expanded so far
     long long abase = 0;   // arena ids handed out so far
     int it = 0;            // loop trips (parity of the partial sums)
@@ -644,20 +664,20 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
             a.acnt[wave_par(wave)] = 0;
             a.mcur[wave_par(wave)] = 0;
         }
-        phase_count(a, T, par, lo, hi, s.u_idx, s.scan, red_ll, red_f);
+        phase_count(a, i_step, par, lo, hi, s.u_idx, s.scan, red_ll);
         if (tr0 && tr) tr[kTrCountDone] = (long long)wall_clock64();
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) tr[kTrCounted] = (long long)wall_clock64();
 
         // every block derives the same decisions from the same partial sums
         long long total = 0, before = 0, open_nodes = 0;
-        float mn = MPAP_INF;
+        long long mstep = 0x7fffffffffffffffll;
         for (int q = 0; q < G; ++q) {
             const long long c = a.part_cnt[par * G + q];
             if (q < b) before += c;
             total += c;
             open_nodes += a.part_open[par * G + q];
-            mn = fminf(mn, a.part_min[par * G + q]);
+            mstep = min(mstep, a.part_step[par * G + q]);
         }
         const int errv = __hip_atomic_load(a.err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         if (errv != 0) {
@@ -666,14 +686,14 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
         }
         if (open_nodes == 0) break;  // P_open is empty
         ++it;
-        if (it > 2 * a.max_waves + 64 || (total == 0 && !(mn < MPAP_INF))) {
+        if (it > 2 * a.max_waves + 64 || (total == 0 && mstep == 0x7fffffffffffffffll)) {
             status = kStatusNoConverge;
             break;
         }
         if (total == 0) {
-            // empty group: move the threshold up to the cheapest open label
-            T = mn;
-            i_step = (long long)floorf(mn / a.delta);
+            // empty group: skip to the first iteration whose group is not
+            // empty (the least step that reaches some open label)
+            i_step = max(mstep, i_step + 1);
             continue;
         }
         if (wave >= a.max_waves) {
@@ -685,7 +705,7 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
             if (b == 0 && threadIdx.x == 0) a.out[kOutNeed] = total;
             break;
         }
-        phase_select(a, T, wave, abase, before, lo, hi, s.u_idx, s.u_end, s.scan);
+        phase_select(a, i_step, wave, abase, before, lo, hi, s.u_idx, s.u_end, s.scan);
         if (tr0 && tr) tr[kTrSelectDone] = (long long)wall_clock64();
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) {
@@ -720,7 +740,6 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
         abase += total;
         ++wave;
         ++i_step;
-        T = (float)i_step * a.delta;
     }
     if (threadIdx.x == 0) {
         atomicAdd((unsigned long long *)&a.out[kOutMerges], (unsigned long long)st_merges);

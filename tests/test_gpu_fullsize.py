@@ -140,3 +140,86 @@ def test_soundness_and_goal_front(full3d):
     assert is_pareto_min_of(fr.vecs, np.concatenate([fronts[v] for v in gidx]))
     st = res.stats()
     assert st["front_labels"] == sum(f.shape[0] for f in fronts)
+
+
+# ------------------------------------------------ 6D double integrator, full size
+@pytest.fixture(scope="module")
+def road6d():
+    from oracle import graph6d  # noqa: F401  (imported for the checks below)
+    env = synth.plain6d(0)  # 50,000 samples, 30 out-edges, 150 boxes, 100 blobs
+    print("building the 50,000-state 6D roadmap on the GPU", flush=True)
+    dg = mpap.mpap_build_graph(env)
+    print(f"6D roadmap {dg.info()}", flush=True)
+    yield env, dg
+    dg.close()
+
+
+def test_6d_rows_match_oracle_at_sampled_states(road6d):
+    """Each sampled state's out-edges (steering order, reachability), costs
+    and drifts against the oracle computed for that state alone."""
+    from oracle import graph6d
+    env, dg = road6d
+    g = dg.export()
+    assert g["row_ptr"][-1] >= 25 * env.n_nodes  # about 30 reachable targets each
+    rng = np.random.default_rng(0)
+    for u in [0] + rng.integers(1, env.n_nodes, 24).tolist():
+        tgt, J, c0, c1 = graph6d.out_edges(env.pos, env.vel, u, env.k_out, env.horizon,
+                                           env.traj_steps, env.box_lo, env.box_hi)
+        o = np.argsort(tgt, kind="stable")
+        row = slice(g["row_ptr"][u], g["row_ptr"][u + 1])
+        assert g["col"][row].tolist() == tgt[o].tolist(), u
+        assert np.array_equal(bits(g["cost"][row]), bits(J[o])), u
+        p, _ = graph6d.trajectory(np.repeat(env.pos[u][None], tgt.size, 0),
+                                  np.repeat(env.vel[u][None], tgt.size, 0), c0[o], c1[o],
+                                  env.horizon, env.traj_steps)
+        ref = graph6d.traj_drift(p, env.blob_mu, env.blob_sigma, env.blob_amp)
+        err = np.abs(g["drift"][row].astype(np.float64) - ref)
+        assert np.all(err <= 1e-5 * ref + 1e-6), u
+
+
+def test_6d_search_matches_oracle_on_same_arrays(road6d):
+    """The two-objective fronts of the 6D workload are small enough for the
+    whole oracle run: every sampled node front and the goal front, bit for
+    bit."""
+    env, dg = road6d
+    g = dg.export()
+    ref = osearch.search(g, env.beta, env.n_obj)
+    print(f"6D oracle: X={ref.X} in {ref.seconds:.1f}s", flush=True)
+    res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam)
+    st = res.stats()
+    assert st["front_labels"] == ref.X
+    for v in range(0, env.n_nodes, 97):
+        a = sort_lex(res.node_front(v))
+        assert np.array_equal(bits(a), bits(ref.node_front(v))), v
+    fr = res.goal_front()
+    rv, _, _ = osearch.goal_front(ref, g["goal"])
+    assert np.array_equal(bits(fr.vecs), bits(rv))
+    print(f"6D search: {st['waves']} waves, {st['gpu_ms']:.2f} ms, goal front {rv.shape[0]}",
+          flush=True)
+    res.close()
+
+
+def test_6d_surrogate_trained_on_a_million_edges(road6d):
+    """The learned drift on the 6D roadmap: trained on 2^20 edges, scored on
+    all, error on the held-out rest; the search on it is judged by the
+    analytic re-walk."""
+    env, dg = road6d
+    e = dg.info()["e"]
+    perm = np.random.default_rng(11).permutation(e)
+    n_tr = min(1 << 20, (e // 4096) * 4096)
+    s = mpap.Surrogate(seed=12)
+    loss = s.train(dg, perm[:n_tr], epochs=8, batch=4096, lr=2e-3)
+    ms = s.score(dg)
+    ana = mpap.mpap_analytic_drift(dg)
+    a = mpap.mpap_graph_drift(dg, 0).astype(np.float64)
+    sd = mpap.mpap_graph_drift(dg, 1).astype(np.float64)
+    held = perm[n_tr:]
+    rel = np.abs(sd - a)[held] / np.maximum(a[held], 1e-3 * env.beta)
+    print(f"6D surrogate: loss {loss[0]:.3g} -> {loss[-1]:.3g}; held-out ({held.size}) median "
+          f"rel err {np.median(rel):.3g}, p99 {np.percentile(rel, 99):.3g}; scoring {ms:.2f} ms "
+          f"vs analytic drift {ana:.2f} ms", flush=True)
+    assert np.median(rel) < 0.01
+    res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam, heuristic=1)
+    print(f"6D surrogate search judged {mpap.surrogate_front_ok(res, 0, env.beta)}", flush=True)
+    res.close()
+    s.close()
