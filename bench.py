@@ -35,6 +35,35 @@ def alg_bytes(X: int, R: int, n_obj: int) -> int:
     return 12 * R + s * X + (s + 4) * X
 
 
+def search_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the search kernel sources."""
+    import hashlib
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1705_02408_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("search_kernels.hip", "search_kernels.h", "device_common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_search launch on the benchmark workload from the
+    committed rocprofv3 counter summary, or None when the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "k_search_plain3d_n20000.md")
+    try:
+        with open(path) as f:
+            line = next(l for l in f if l.startswith("traffic:"))
+    except (OSError, StopIteration):
+        return None
+    kv = dict(t.split("=", 1) for t in line.split()[1:])
+    if kv.get("source_sha256_16") != search_source_hash():
+        return None
+    return int(1024 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                       float(kv["write_kib"]) * float(kv["write_scale"])))
+
+
 def cpu_count_used() -> int:
     return 1
 
@@ -46,7 +75,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["plain3d", "plain2d", "batch"], default="plain3d")
+    ap.add_argument("--workload", choices=["plain3d", "plain2d", "batch", "copy"],
+                    default="plain3d",
+                    help="copy: a plain 1 GiB device copy, the reference for the HBM "
+                         "traffic counters")
     ap.add_argument("--queries", type=int, default=256, help="batch workload: query count")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed batches")
     ap.add_argument("--no-batch", action="store_true",
@@ -75,6 +107,8 @@ def main():
 
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "copy":
+        return run_copy(args)
     env = (synth.plain3d(args.seed, n=args.n) if args.workload == "plain3d"
            else synth.plain2d(args.seed, n=args.n))
     n_obj = env.n_obj
@@ -189,7 +223,11 @@ def main():
                    "blocks": stats[-1]["blocks"], "lds_front_cap": stats[-1]["lds_front_cap"],
                    "max_front": stats[-1]["max_front"], "phases": phases},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.workload == "plain3d" and
+                     args.n == 20000 and args.seed == 0 else None,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a plain copy's counts)",
                      "kernel": "k_search", "alg_bytes_per_launch": B},
         "cpu_baseline": cpu,
     }
@@ -371,6 +409,26 @@ def measure_batch(args, log, with_surrogate: bool = True):
         for m in models.values():
             m["model"].close()
     return out
+
+
+def run_copy(args):
+    """A plain device copy of 1 GiB, K times: per launch 2^30 bytes read and
+    2^30 bytes written.  Profiled with the same counters as the search, it
+    gives the counters' bytes-per-unit scale on this device."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    print(json.dumps({"metric": "copy GB/s (read + write)", "value": 2 * nbytes / dt / 1e9,
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+                      "ms_per_step": 1e3 * dt, "bytes_read_per_launch": nbytes,
+                      "bytes_written_per_launch": nbytes}), flush=True)
 
 
 def run_batch(args):
