@@ -575,11 +575,12 @@ int search_shape(int stage_cap, SearchShape &L) {
                          128 + 32 + L.capC;
     // leave 1 KiB for the kernel's static LDS
     const size_t lds_budget = std::min<size_t>(di.max_lds, 160 * 1024) - 1024;
-    int capB = (int)((lds_budget - fixed) / 17);
+    // per staged label: 16 B + a flag byte; per 64 labels: two segment floats
+    int capB = (int)(((lds_budget - fixed - 16) * 64) / (17 * 64 + 8));
     capB = std::min(capB, 8 * L.threads);
     capB -= capB % 64;
     if (capB < 256) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
-    L.lds = fixed + 17 * (size_t)capB;
+    L.lds = fixed + 17 * (size_t)capB + 8 * (size_t)(capB / 64 + 2);
     if (stage_cap > 0) capB = std::min(capB, std::max(stage_cap, 1));
     L.capB = capB;
     int per_cu = 0;

@@ -241,6 +241,9 @@ struct MergeLds {
     int *u_end;     // [capC] per candidate: end of the bucket prefix left to scan
     int *scan;      // [32]
     int *misc;      // [8]
+    float *segd;    // [segcap] per 64-label segment: least d
+    float *segm;    // [segcap] per 64-label segment: least m
+    int segcap;
 };
 
 constexpr int kMaxBPerThread = 8;  // capB <= kMaxBPerThread * blockDim
@@ -301,54 +304,127 @@ __device__ void bitonic_sort(float4 *v, int n) {
     }
 }
 
+// Per 64-label segment of the sorted arr[0..n): the least d and the least m.
+// A segment whose least d exceeds q.d (or least m exceeds q.m) holds no label
+// that weakly dominates q, so dominance scans skip it.
+__device__ void seg_summary(const float4 *arr, int n, float *sd, float *sm) {
+    const int l = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int nseg = (n + 63) >> 6;
+    for (int sg = w; sg < nseg; sg += nw) {
+        const int i = sg * 64 + l;
+        float d = MPAP_INF, m = MPAP_INF;
+        if (i < n) {
+            const float4 v = arr[i];
+            d = v.y;
+            m = v.z;
+        }
+        d = wave_min(d);
+        m = wave_min(m);
+        if (l == 0) {
+            sd[sg] = d;
+            sm[sg] = m;
+        }
+    }
+    __syncthreads();
+}
+
+// does some label of the sorted arr[0..end) weakly dominate q (its cost is
+// known to be <= q's)?  Scanned from the top, segment by segment, by the gs
+// threads of a group (sub = rank in the group); flag is the group's shared
+// result, polled between segments.
+__device__ __forceinline__ bool any_dominates(const float4 *arr, int end, const float4 &q,
+                                              const float *sd, const float *sm, bool use_seg,
+                                              int gs, int sub, const uint8_t *flag) {
+    for (int sg = (end - 1) >> 6; sg >= 0; --sg) {
+        if (use_seg && !(sd[sg] <= q.y && sm[sg] <= q.z)) continue;
+        const int lo = sg << 6;
+        for (int j = min(end, lo + 64) - 1 - sub; j >= lo; j -= gs)
+            if (dm_le(arr[j], q)) return true;
+        if (flag && *(volatile const uint8_t *)flag) return false;
+    }
+    return false;
+}
+
+// block-wide exclusive prefix minimum of one float per thread (scratch: one
+// float per wave); every thread calls
+__device__ __forceinline__ float block_excl_min(float v, float *scratch) {
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    float incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float u = __shfl_up(incl, o, 64);
+        if (l >= o) incl = fminf(incl, u);
+    }
+    float ex = __shfl_up(incl, 1, 64);
+    if (l == 0) ex = MPAP_INF;
+    __syncthreads();
+    if (l == 63) scratch[w] = incl;
+    __syncthreads();
+    float before = MPAP_INF;
+    for (int i = 0; i < w; ++i) before = fminf(before, scratch[i]);
+    __syncthreads();
+    return fminf(before, ex);
+}
+
 // P(x) <- Min(P(x) U C): B[0..nB) sorted, C[0..nC) unsorted; result sorted in B.
-__device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan,
+// With two objectives (m = 0 everywhere) a Pareto front sorted by cost has
+// strictly falling drift, so the only possible dominator of a label among
+// the front's labels of cost <= its own is the last of them: every test is a
+// binary search.  With three objectives the tests scan cost prefixes,
+// skipping 64-label segments that cannot hold a dominator.
+__device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan, bool three,
                             int *err) {
     const int bd = blockDim.x;
-    // 1. near scan: the labels just below the candidate's cost
-    for (int i = threadIdx.x; i < nC; i += bd) {
-        const float4 q = s.C[i];
-        const int k = upper_c(s.B, nB, q.x);
-        const int stop = max(0, k - near_scan);
-        bool dead = false;
-        for (int j = k - 1; j >= stop && !dead; --j) dead = dm_le(s.B[j], q);
-        s.cdead[i] = dead ? 1 : 0;
-        s.u_end[i] = dead ? 0 : stop;
-    }
-    __syncthreads();
-    // 2. list the undecided candidates (bucket prefix left to scan)
-    int nU = 0;
-    for (int t0 = 0; t0 < nC; t0 += bd) {
-        const int i = t0 + threadIdx.x;
-        const bool und = i < nC && !s.cdead[i] && s.u_end[i] > 0;
-        int tot;
-        const int ex = block_excl_scan(und ? 1 : 0, s.scan, &tot);
-        if (und) s.u_idx[nU + ex] = i;
-        nU += tot;
-    }
-    __syncthreads();
-    // 3. full scan of the rest of the prefix, gs threads per candidate
-    if (nU > 0) {
-        int gs = 1;
-        while (gs < 64 && gs * 2 * nU <= bd) gs <<= 1;
-        const int per_round = bd / gs;
-        for (int base = 0; base < nU; base += per_round) {
-            const int u = base + (int)threadIdx.x / gs;
-            const int sub = (int)threadIdx.x % gs;
-            if (u < nU) {
-                const int i = s.u_idx[u];
-                const float4 q = s.C[i];
-                int n_it = 0;
-                for (int j = s.u_end[i] - 1 - sub; j >= 0; j -= gs) {
-                    if (dm_le(s.B[j], q)) {
-                        s.cdead[i] = 1;
-                        break;
-                    }
-                    if ((++n_it & 15) == 0 && *(volatile uint8_t *)&s.cdead[i]) break;
-                }
-            }
+    if (!three) {
+        // 1. the last bucket label of cost <= q.c decides
+        for (int i = threadIdx.x; i < nC; i += bd) {
+            const float4 q = s.C[i];
+            const int k = upper_c(s.B, nB, q.x);
+            s.cdead[i] = (k > 0 && s.B[k - 1].y <= q.y) ? 1 : 0;
         }
         __syncthreads();
+    } else {
+        // 1. near scan: the labels just below the candidate's cost
+        for (int i = threadIdx.x; i < nC; i += bd) {
+            const float4 q = s.C[i];
+            const int k = upper_c(s.B, nB, q.x);
+            const int stop = max(0, k - near_scan);
+            bool dead = false;
+            for (int j = k - 1; j >= stop && !dead; --j) dead = dm_le(s.B[j], q);
+            s.cdead[i] = dead ? 1 : 0;
+            s.u_end[i] = dead ? 0 : stop;
+        }
+        __syncthreads();
+        // 2. list the undecided candidates (bucket prefix left to scan)
+        int nU = 0;
+        for (int t0 = 0; t0 < nC; t0 += bd) {
+            const int i = t0 + threadIdx.x;
+            const bool und = i < nC && !s.cdead[i] && s.u_end[i] > 0;
+            int tot;
+            const int ex = block_excl_scan(und ? 1 : 0, s.scan, &tot);
+            if (und) s.u_idx[nU + ex] = i;
+            nU += tot;
+        }
+        __syncthreads();
+        // 3. the rest of the prefix, gs threads per candidate, by segments
+        if (nU > 0) {
+            const bool use_seg = nB <= 64 * s.segcap;
+            if (use_seg) seg_summary(s.B, nB, s.segd, s.segm);
+            int gs = 1;
+            while (gs < 64 && gs * 2 * nU <= bd) gs <<= 1;
+            const int per_round = bd / gs;
+            for (int base = 0; base < nU; base += per_round) {
+                const int u = base + (int)threadIdx.x / gs;
+                const int sub = (int)threadIdx.x % gs;
+                if (u < nU) {
+                    const int i = s.u_idx[u];
+                    if (any_dominates(s.B, s.u_end[i], s.C[i], s.segd, s.segm, use_seg, gs, sub,
+                                      &s.cdead[i]))
+                        s.cdead[i] = 1;
+                }
+            }
+            __syncthreads();
+        }
     }
     // 4. survivors of the bucket test, sorted
     const int nS = compact_alive(s.C, s.cdead, nC, s.scan);
@@ -359,22 +435,39 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         s.C[i] = make_float4(MPAP_INF, MPAP_INF, MPAP_INF, __uint_as_float(0xffffffffu));
     __syncthreads();
     bitonic_sort(s.C, P);
-    // 5. candidates among themselves: an earlier (cheaper) one may dominate
-    for (int i = threadIdx.x; i < nS; i += bd) {
-        const float4 q = s.C[i];
-        bool dead = false;
-        for (int j = 0; j < i && !dead; ++j) dead = dm_le(s.C[j], q);
-        s.cdead[i] = dead ? 1 : 0;
+    // 5. candidates among themselves: an earlier (lexicographically smaller)
+    // one may dominate
+    if (!three) {
+        float carry = MPAP_INF;
+        for (int t0 = 0; t0 < nS; t0 += bd) {
+            const int i = t0 + threadIdx.x;
+            const float d = i < nS ? s.C[i].y : MPAP_INF;
+            const float ex = fminf(carry, block_excl_min(d, reinterpret_cast<float *>(s.scan)));
+            if (i < nS) s.cdead[i] = ex <= d ? 1 : 0;
+            carry = fminf(carry, block_min(d, reinterpret_cast<float *>(s.scan)));
+        }
+        __syncthreads();
+    } else {
+        seg_summary(s.C, nS, s.segd, s.segm);
+        for (int i = threadIdx.x; i < nS; i += bd)
+            s.cdead[i] = any_dominates(s.C, i, s.C[i], s.segd, s.segm, true, 1, 0, nullptr) ? 1 : 0;
+        __syncthreads();
     }
-    __syncthreads();
     const int nS2 = compact_alive(s.C, s.cdead, nS, s.scan);
     // 6. bucket labels a surviving candidate dominates leave
-    for (int j = threadIdx.x; j < nB; j += bd) {
-        const float4 b = s.B[j];
-        const int kk = upper_c(s.C, nS2, b.x);
-        bool dead = false;
-        for (int i = 0; i < kk && !dead; ++i) dead = dm_le(s.C[i], b);
-        s.bdead[j] = dead ? 1 : 0;
+    if (!three) {
+        for (int j = threadIdx.x; j < nB; j += bd) {
+            const float4 b = s.B[j];
+            const int kk = upper_c(s.C, nS2, b.x);
+            s.bdead[j] = (kk > 0 && s.C[kk - 1].y <= b.y) ? 1 : 0;
+        }
+    } else {
+        seg_summary(s.C, nS2, s.segd, s.segm);
+        for (int j = threadIdx.x; j < nB; j += bd) {
+            const float4 b = s.B[j];
+            const int kk = upper_c(s.C, nS2, b.x);
+            s.bdead[j] = any_dominates(s.C, kk, b, s.segd, s.segm, true, 1, 0, nullptr) ? 1 : 0;
+        }
     }
     __syncthreads();
     const int nBs = compact_alive(s.B, s.bdead, nB, s.scan);
@@ -514,7 +607,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
             st_cand += nC;
             if (nC > 0) {
                 const int before = nB;
-                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.err);
+                merge_chunk(s, nB, nC, a.capB, a.near_scan, three, a.err);
                 changed = true;
                 (void)before;
             }
@@ -623,6 +716,11 @@ __device__ void carve_lds(unsigned char *lds, const SearchArgs &a, MergeLds &s) 
     p += sizeof(long long) * 16;
     s.misc = reinterpret_cast<int *>(p);
     p += sizeof(int) * 8;
+    s.segcap = a.capB / 64 + 2;
+    s.segd = reinterpret_cast<float *>(p);
+    p += sizeof(float) * s.segcap;
+    s.segm = reinterpret_cast<float *>(p);
+    p += sizeof(float) * s.segcap;
     s.bdeadl = p;
     p += a.capB;
     s.cdead = p;
@@ -797,7 +895,7 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
                 for (int i = threadIdx.x; i < nC; i += blockDim.x)
                     s.C[i] = a.pool[(size_t)(unsigned)nbv.x + c0 + i];
                 __syncthreads();
-                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.err);
+                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, a.err);
             }
         }
         const long long o = g.lab_off[q];
