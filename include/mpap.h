@@ -148,6 +148,9 @@ typedef struct {
                           Never changes the result. */
     int32_t heuristic; /* per-edge drift: 0 = the analytic values of the roadmap,
                           1 = the learned surrogate's (mpap_surrogate_score) */
+    int32_t block_threads; /* tuning: threads per workgroup of the persistent search,
+                              1024 (one per CU), 512 (two) or 256 (four); 0 = 1024.
+                              Never changes the result. */
 } mpap_search_params;
 
 /*

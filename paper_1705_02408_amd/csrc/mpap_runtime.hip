@@ -541,6 +541,10 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
         if (x.heuristic != 0 && x.heuristic != 1)
             return fail(MPAP_ERR_INVAL, "heuristic must be 0 (analytic) or 1 (surrogate)");
         if (x.stage_cap > 0) p.stage_cap = x.stage_cap;
+        if (x.block_threads != 0 && x.block_threads != 256 && x.block_threads != 512 &&
+            x.block_threads != 1024)
+            return fail(MPAP_ERR_INVAL, "block_threads must be 0, 256, 512 or 1024");
+        if (x.block_threads != 0) p.block_threads = x.block_threads;
     }
     if (p.max_waves <= 0) p.max_waves = 1 << 18;
     if (nsp == 1 && nq > 1) {
@@ -564,29 +568,35 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
     return MPAP_OK;
 }
 
-int search_shape(int stage_cap, SearchShape &L) {
+int search_shape(int stage_cap, int block_threads, SearchShape &L) {
     DeviceInfo di;
     int r = device_info(&di);
     if (r) return r;
-    // 1024-thread blocks, LDS staging sized from the device limit
-    L.threads = 1024;
-    L.capC = 1024;  // a power of two, a multiple of the block size
+    // 1024, 512 or 256-thread workgroups, one, two or four per CU; LDS staging
+    // sized from the device limit shared by the CU's workgroups
+    L.threads = block_threads;
+    const int per_cu_want = 1024 / L.threads;
+    L.capC = std::min(1024, 4 * L.threads);  // a power of two, a multiple of the block size
     const size_t fixed = 16 * (size_t)L.capC + 16 * (size_t)L.threads + 8 * (size_t)L.capC +
                          128 + 32 + L.capC;
-    // leave 1 KiB for the kernel's static LDS
-    const size_t lds_budget = std::min<size_t>(di.max_lds, 160 * 1024) - 1024;
-    // per staged label: 16 B + a flag byte; per 64 labels: two segment floats
-    int capB = (int)(((lds_budget - fixed - 16) * 64) / (17 * 64 + 8));
+    // leave 1 KiB per workgroup for the kernel's static LDS
+    const size_t lds_budget = std::min<size_t>(di.max_lds, 160 * 1024) / per_cu_want - 1024;
+    if (lds_budget < fixed + 17 * 256 + 64) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
+    // per staged label: 16 B + a flag byte; per 64 labels of the larger of the
+    // front stage and the candidate chunk: two segment floats
+    const size_t segc = 8 * ((size_t)L.capC / 64 + 2);
+    if (lds_budget < fixed + segc + 17 * 256 + 64) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
+    int capB = (int)(((lds_budget - fixed - segc - 16) * 64) / (17 * 64 + 8));
     capB = std::min(capB, 8 * L.threads);
     capB -= capB % 64;
     if (capB < 256) return fail(MPAP_ERR_DEVICE, "not enough LDS per block");
-    L.lds = fixed + 17 * (size_t)capB + 8 * (size_t)(capB / 64 + 2);
+    L.lds = fixed + 17 * (size_t)capB + 8 * (size_t)(std::max(capB, L.capC) / 64 + 2);
     if (stage_cap > 0) capB = std::min(capB, std::max(stage_cap, 1));
     L.capB = capB;
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search, L.threads, L.lds));
     if (per_cu < 1) return fail(MPAP_ERR_DEVICE, "search kernel does not fit on a CU");
-    L.nblocks = di.cus * std::min(per_cu, 2);
+    L.nblocks = di.cus * std::min(per_cu, per_cu_want);
     return MPAP_OK;
 }
 
@@ -803,7 +813,7 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
         if (p.heur[q] == 1 && !(g->symmetric_alias ? g->sdrift : g->srdrift))
             return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph (mpap_surrogate_score)");
     SearchShape L;
-    if ((r = search_shape(p.stage_cap, L))) return r;
+    if ((r = search_shape(p.stage_cap, p.block_threads, L))) return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     Workspace *w = nullptr;

@@ -224,7 +224,7 @@ int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
     mpap_plan *p = new mpap_plan();
     p->g = g;
     int r = search_prep(g, sp, nsp, p->prep);
-    if (!r) r = search_shape(p->prep.stage_cap, p->shape);
+    if (!r) r = search_shape(p->prep.stage_cap, p->prep.block_threads, p->shape);
     auto bail = [&](int st) {
         mpap_plan_free(p);
         return st;

@@ -322,7 +322,7 @@ struct mpap_result {
 struct SearchPrep {
     int nq = 0;
     std::vector<float> delta;  // per query lambda * radius
-    int max_waves = 0, near_scan = 16, stage_cap = 0;
+    int max_waves = 0, near_scan = 16, stage_cap = 0, block_threads = 1024;
     std::vector<float> beta;
     std::vector<int> nobj, root, heur;
 };
@@ -332,7 +332,7 @@ struct SearchShape {
     size_t lds = 0;
 };
 int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, SearchPrep &p);
-int search_shape(int stage_cap, SearchShape &L);
+int search_shape(int stage_cap, int block_threads, SearchShape &L);
 // Uploads the per-query parameters into w (synchronous).
 int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s);
 // The search with capacity growth and retries, goal fronts and statistics,

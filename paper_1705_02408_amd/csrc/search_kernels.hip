@@ -247,6 +247,7 @@ struct MergeLds {
 };
 
 constexpr int kMaxBPerThread = 8;  // capB <= kMaxBPerThread * blockDim
+constexpr int kMaxCPerThread = 4;  // capC <= kMaxCPerThread * blockDim
 
 // compact the alive entries of arr[0..n) to the front, stable.
 __device__ int compact_alive(float4 *arr, const uint8_t *dead, int n, int *scan) {
@@ -306,10 +307,12 @@ __device__ void bitonic_sort(float4 *v, int n) {
 
 // Per 64-label segment of the sorted arr[0..n): the least d and the least m.
 // A segment whose least d exceeds q.d (or least m exceeds q.m) holds no label
-// that weakly dominates q, so dominance scans skip it.
-__device__ void seg_summary(const float4 *arr, int n, float *sd, float *sm) {
+// that weakly dominates q, so dominance scans skip it.  Returns false (and
+// writes nothing) when the n labels need more than segcap segments.
+__device__ bool seg_summary(const float4 *arr, int n, float *sd, float *sm, int segcap) {
     const int l = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int nseg = (n + 63) >> 6;
+    if (nseg > segcap) return false;
     for (int sg = w; sg < nseg; sg += nw) {
         const int i = sg * 64 + l;
         float d = MPAP_INF, m = MPAP_INF;
@@ -325,7 +328,7 @@ __device__ void seg_summary(const float4 *arr, int n, float *sd, float *sm) {
             sm[sg] = m;
         }
     }
-    __syncthreads();
+    __syncthreads();    return true;
 }
 
 // does some label of the sorted arr[0..end) weakly dominate q (its cost is
@@ -408,8 +411,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         __syncthreads();
         // 3. the rest of the prefix, gs threads per candidate, by segments
         if (nU > 0) {
-            const bool use_seg = nB <= 64 * s.segcap;
-            if (use_seg) seg_summary(s.B, nB, s.segd, s.segm);
+            const bool use_seg = seg_summary(s.B, nB, s.segd, s.segm, s.segcap);
             int gs = 1;
             while (gs < 64 && gs * 2 * nU <= bd) gs <<= 1;
             const int per_round = bd / gs;
@@ -429,15 +431,47 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     // 4. survivors of the bucket test, sorted
     const int nS = compact_alive(s.C, s.cdead, nC, s.scan);
     if (nS == 0) return;
-    int P = 1;
-    while (P < nS) P <<= 1;
-    for (int i = nS + threadIdx.x; i < P; i += bd)
-        s.C[i] = make_float4(MPAP_INF, MPAP_INF, MPAP_INF, __uint_as_float(0xffffffffu));
-    __syncthreads();
-    bitonic_sort(s.C, P);
-    // 5. candidates among themselves: an earlier (lexicographically smaller)
-    // one may dominate
-    if (!three) {
+    int nS2;
+    if (nS <= 64) {
+        // 4-5 for a few survivors, by one wave without block barriers: each
+        // lane compares its survivor with all the others (broadcast LDS
+        // reads): it dies if a lexicographically smaller one dominates it,
+        // and its rank among the living ones is its place in the sorted run
+        if (threadIdx.x < 64) {
+            const int l = threadIdx.x;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            bool dead = l >= nS;
+            if (l < nS) v = s.C[l];
+            for (int j = 0; j < nS; ++j) {
+                const float4 o = s.C[j];
+                dead = dead || (lex_lt(o, v) && dm_le(o, v));
+            }
+            s.cdead[l] = dead ? 1 : 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int pos = 0;
+            for (int j = 0; j < nS; ++j) pos += (!s.cdead[j] && lex_lt(s.C[j], v)) ? 1 : 0;
+            const uint64_t am = ballot64(!dead);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (!dead) s.C[pos] = v;
+            if (l == 0) s.misc[3] = (int)__popcll(am);
+        }
+        __syncthreads();
+        nS2 = s.misc[3];
+        __syncthreads();
+    } else {
+        int P = 1;
+        while (P < nS) P <<= 1;
+        for (int i = nS + threadIdx.x; i < P; i += bd)
+            s.C[i] = make_float4(MPAP_INF, MPAP_INF, MPAP_INF, __uint_as_float(0xffffffffu));
+        __syncthreads();
+        bitonic_sort(s.C, P);
+        // 5. candidates among themselves: an earlier (lexicographically
+        // smaller) one may dominate
+        if (!three) {
         float carry = MPAP_INF;
         for (int t0 = 0; t0 < nS; t0 += bd) {
             const int i = t0 + threadIdx.x;
@@ -447,30 +481,36 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             carry = fminf(carry, block_min(d, reinterpret_cast<float *>(s.scan)));
         }
         __syncthreads();
-    } else {
-        seg_summary(s.C, nS, s.segd, s.segm);
-        for (int i = threadIdx.x; i < nS; i += bd)
-            s.cdead[i] = any_dominates(s.C, i, s.C[i], s.segd, s.segm, true, 1, 0, nullptr) ? 1 : 0;
-        __syncthreads();
+        } else {
+            const bool seg = seg_summary(s.C, nS, s.segd, s.segm, s.segcap);
+            for (int i = threadIdx.x; i < nS; i += bd)
+                s.cdead[i] =
+                    any_dominates(s.C, i, s.C[i], s.segd, s.segm, seg, 1, 0, nullptr) ? 1 : 0;
+            __syncthreads();
+        }
+        nS2 = compact_alive(s.C, s.cdead, nS, s.scan);
     }
-    const int nS2 = compact_alive(s.C, s.cdead, nS, s.scan);
     // 6. bucket labels a surviving candidate dominates leave
+    bool any_dead = false;
     if (!three) {
         for (int j = threadIdx.x; j < nB; j += bd) {
             const float4 b = s.B[j];
             const int kk = upper_c(s.C, nS2, b.x);
-            s.bdead[j] = (kk > 0 && s.C[kk - 1].y <= b.y) ? 1 : 0;
+            const bool dead = kk > 0 && s.C[kk - 1].y <= b.y;
+            s.bdead[j] = dead ? 1 : 0;
+            any_dead = any_dead || dead;
         }
     } else {
-        seg_summary(s.C, nS2, s.segd, s.segm);
+        const bool seg = nS2 > 64 && seg_summary(s.C, nS2, s.segd, s.segm, s.segcap);
         for (int j = threadIdx.x; j < nB; j += bd) {
             const float4 b = s.B[j];
             const int kk = upper_c(s.C, nS2, b.x);
-            s.bdead[j] = any_dominates(s.C, kk, b, s.segd, s.segm, true, 1, 0, nullptr) ? 1 : 0;
+            const bool dead = any_dominates(s.C, kk, b, s.segd, s.segm, seg, 1, 0, nullptr);
+            s.bdead[j] = dead ? 1 : 0;
+            any_dead = any_dead || dead;
         }
     }
-    __syncthreads();
-    const int nBs = compact_alive(s.B, s.bdead, nB, s.scan);
+    const int nBs = __syncthreads_or(any_dead) ? compact_alive(s.B, s.bdead, nB, s.scan) : nB;
     const int total = nBs + nS2;
     if (total > (s.spilled ? s.capG : capB) && (s.spilled || total > s.capG)) {
         if (threadIdx.x == 0) atomicOr(err, kErrBucket);
@@ -508,17 +548,24 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             pb[r] = k + lex_rank(s.C, nS2, rb[r]);
         }
     }
-    float4 rc = make_float4(0.f, 0.f, 0.f, 0.f);
-    int pc = -1;
-    if ((int)threadIdx.x < nS2) {
-        rc = s.C[threadIdx.x];
-        pc = (int)threadIdx.x + lex_rank(s.B, nBs, rc);
+    float4 rc[kMaxCPerThread];
+    int pc[kMaxCPerThread];
+#pragma unroll
+    for (int r = 0; r < kMaxCPerThread; ++r) {
+        const int i = (int)threadIdx.x + r * bd;
+        pc[r] = -1;
+        if (i < nS2) {
+            rc[r] = s.C[i];
+            pc[r] = i + lex_rank(s.B, nBs, rc[r]);
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kMaxBPerThread; ++r)
         if (pb[r] >= 0) s.B[pb[r]] = rb[r];
-    if (pc >= 0) s.B[pc] = rc;
+#pragma unroll
+    for (int r = 0; r < kMaxCPerThread; ++r)
+        if (pc[r] >= 0) s.B[pc[r]] = rc[r];
     nB = total;
     __syncthreads();
 }
@@ -716,7 +763,7 @@ __device__ void carve_lds(unsigned char *lds, const SearchArgs &a, MergeLds &s) 
     p += sizeof(long long) * 16;
     s.misc = reinterpret_cast<int *>(p);
     p += sizeof(int) * 8;
-    s.segcap = a.capB / 64 + 2;
+    s.segcap = max(a.capB, a.capC) / 64 + 2;
     s.segd = reinterpret_cast<float *>(p);
     p += sizeof(float) * s.segcap;
     s.segm = reinterpret_cast<float *>(p);

@@ -88,6 +88,20 @@ def test_cheap_end_of_every_front_matches_oracle(full3d):
     assert n_cmp > 100000
 
 
+@pytest.mark.parametrize("threads", [512, 256])
+def test_smaller_workgroups_give_the_same_fronts(full3d, threads):
+    """Two or four workgroups per CU stage less of each front in LDS (more
+    fronts spill) and merge larger candidate chunks per thread: every node
+    front must stay bit for bit the same at full size."""
+    env, g, dg, res, fronts = full3d
+    r2 = mpap.mpap_search(dg, env.beta, 3, env.radius, env.lam, block_threads=threads)
+    assert r2.stats()["front_labels"] == res.stats()["front_labels"]
+    assert np.array_equal(bits(r2.goal_front().vecs), bits(res.goal_front().vecs))
+    for v in range(0, len(fronts), 7):
+        assert np.array_equal(bits(sort_lex(r2.node_front(v))), bits(sort_lex(fronts[v]))), v
+    r2.close()
+
+
 def test_fixpoint_at_sampled_nodes(full3d):
     env, g, dg, res, fronts = full3d
     rp, col = g["row_ptr"], g["col"]

@@ -140,6 +140,21 @@ def test_plain3d_small_three_objectives():
     dg.close()
 
 
+@pytest.mark.parametrize("threads", [256, 512])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_workgroup_size_does_not_change_fronts(threads, dim):
+    """Two or four workgroups per CU (smaller LDS stages, more spills) give the
+    oracle's fronts bit for bit."""
+    env = synth.plain2d(5, n=2000) if dim == 2 else synth.plain3d(2, n=3000)
+    g = ograph.build_graph(env)
+    ref = osearch.search(g, env.beta, env.n_obj)
+    dg, res = run(g, env.beta, env.n_obj, radius=env.radius, block_threads=threads)
+    assert res.stats()["blocks"] == 256 * (1024 // threads)
+    check_against_oracle(g, res, ref, env.beta, env.n_obj, all_nodes=False, node_stride=2)
+    res.close()
+    dg.close()
+
+
 def test_deterministic(road2d):
     env, g = road2d[2]
     dg = upload(g)
