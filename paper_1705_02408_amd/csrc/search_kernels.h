@@ -74,7 +74,7 @@ struct SearchArgs {
     int4 *nb;          // per node {pool offset, capacity, count, 0}
     float *minopen;    // per node least cost of an open label (+inf: none)
     int *gcnt;         // per node group size of the current iteration
-    int4 *fo;          // per node {frontier offset, count, wave, 0}
+    int4 *fo;          // per node {frontier offset, count, wave, first open label index}
     int *mark;         // per node last wave it was queued as merge target
     int *alist;        // merge targets of the current wave [n]
     int *acnt;         // [2] target counts by wave parity

@@ -89,9 +89,10 @@ __device__ void phase_count(const SearchArgs &a, long long istep, int par, int l
             const int vv = list[i];
             const int4 nbv = a.nb[vv];
             const float T = threshold(istep, step_of(a, vv));
-            // open labels at or below T lie in the prefix of the sorted bucket
+            // open labels at or below T lie in the prefix of the sorted bucket,
+            // from its first open label on
             int cnt = 0;
-            for (int k = l; k < nbv.z; k += 64) {
+            for (int k = a.fo[vv].w + l; k < nbv.z; k += 64) {
                 const float4 L = a.pool[(size_t)(unsigned)nbv.x + k];
                 if (L.x > T) break;
                 cnt += lab_open(L) ? 1 : 0;
@@ -146,9 +147,11 @@ __device__ void phase_select(const SearchArgs &a, long long istep, int wave, lon
             const float T = threshold(istep, step_of(a, vv));
             int run = 0;
             float rmin = MPAP_INF;
-            // the bucket is sorted by cost: group labels lie below T; past T
-            // only the first open label (the least remaining open cost) matters
-            for (int k0 = 0; k0 < nbv.z; k0 += 64) {
+            int first_open = nbv.z;
+            // the bucket is sorted by cost: group labels lie below T from the
+            // first open label on; past T only the first open label (the least
+            // remaining open cost) matters, and it is the next first open one
+            for (int k0 = a.fo[vv].w; k0 < nbv.z; k0 += 64) {
                 const int k = k0 + l;
                 bool in = false, op = false, le = false;
                 float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -170,13 +173,15 @@ __device__ void phase_select(const SearchArgs &a, long long istep, int wave, lon
                 }
                 run += (int)__popcll(bm);
                 const bool past = ballot64(k < nbv.z && !le) != 0;
-                if (past && (ballot64(op && !le) != 0 || nbv.w - run == 0)) break;
+                const uint64_t beyond = ballot64(op && !le);
+                if (beyond) first_open = k0 + (int)__ffsll((unsigned long long)beyond) - 1;
+                if (past && (beyond != 0 || nbv.w - run == 0)) break;
             }
             rmin = wave_min(rmin);
             if (l == 0) {
                 a.nb[vv].w = nbv.w - run;
                 a.minopen[vv] = rmin;
-                a.fo[vv] = make_int4(goff, run, wave, 0);
+                a.fo[vv] = make_int4(goff, run, wave, first_open);
                 if (a.nq > 1) atomicMax(&a.qlast[query_of(a, vv)], wave);
                 else if (vv >= 0) a.qlast[0] = wave;
             }
@@ -246,8 +251,6 @@ struct MergeLds {
     int segcap;
 };
 
-constexpr int kMaxBPerThread = 8;  // capB <= kMaxBPerThread * blockDim
-constexpr int kMaxCPerThread = 4;  // capC <= kMaxCPerThread * blockDim
 
 // compact the alive entries of arr[0..n) to the front, stable.
 __device__ int compact_alive(float4 *arr, const uint8_t *dead, int n, int *scan) {
@@ -536,36 +539,26 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         __syncthreads();
         return;
     }
-    // 7b. merge the two sorted runs in place in LDS (positions by rank; read, then write)
-    float4 rb[kMaxBPerThread];
-    int pb[kMaxBPerThread];
-#pragma unroll
-    for (int r = 0; r < kMaxBPerThread; ++r) {
-        const int k = (int)threadIdx.x + r * bd;
-        pb[r] = -1;
-        if (k < nBs) {
-            rb[r] = s.B[k];
-            pb[r] = k + lex_rank(s.C, nS2, rb[r]);
-        }
-    }
-    float4 rc[kMaxCPerThread];
-    int pc[kMaxCPerThread];
-#pragma unroll
-    for (int r = 0; r < kMaxCPerThread; ++r) {
-        const int i = (int)threadIdx.x + r * bd;
-        pc[r] = -1;
-        if (i < nS2) {
-            rc[r] = s.C[i];
-            pc[r] = i + lex_rank(s.B, nBs, rc[r]);
-        }
-    }
+    // 7b. merge the two sorted runs in place in LDS.  Positions by rank: the
+    // survivors' places are found first (B still intact); B's labels only
+    // move up, so B is moved chunk by chunk from the top (each chunk read,
+    // then written, never over a label still to be read); the survivors go
+    // to their places last.
+    for (int i = threadIdx.x; i < nS2; i += bd) s.u_idx[i] = i + lex_rank(s.B, nBs, s.C[i]);
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kMaxBPerThread; ++r)
-        if (pb[r] >= 0) s.B[pb[r]] = rb[r];
-#pragma unroll
-    for (int r = 0; r < kMaxCPerThread; ++r)
-        if (pc[r] >= 0) s.B[pc[r]] = rc[r];
+    for (int top = nBs; top > 0; top -= bd) {
+        const int k = top - bd + (int)threadIdx.x;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        int pos = -1;
+        if (k >= 0) {
+            v = s.B[k];
+            pos = k + lex_rank(s.C, nS2, v);
+        }
+        __syncthreads();
+        if (pos >= 0) s.B[pos] = v;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nS2; i += bd) s.B[s.u_idx[i]] = s.C[i];
     nB = total;
     __syncthreads();
 }
@@ -685,19 +678,24 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
     }
     float mn = MPAP_INF;
     int nopen = 0;
+    long long first = nB;
     for (int i = threadIdx.x; i < nB; i += blockDim.x) {
         const float4 L = s.B[i];
         a.pool[(size_t)(unsigned)off + i] = L;
         if (lab_open(L)) {
             mn = fminf(mn, L.x);
             ++nopen;
+            first = min(first, (long long)i);
         }
     }
     mn = block_min(mn, reinterpret_cast<float *>(s.scan));
+    first = block_min_ll(first, reinterpret_cast<long long *>(s.scan));
     int tot_open;
     block_excl_scan(nopen, s.scan, &tot_open);
     if (threadIdx.x == 0) {
         a.nb[x] = make_int4(off, cap, nB, tot_open);
+        // first open label: the count and select of the next iteration start there
+        reinterpret_cast<int *>(&a.fo[x])[3] = (int)first;
         a.minopen[x] = mn;
     }
     __syncthreads();
@@ -815,15 +813,20 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
         if (tr0 && tr) tr[kTrCounted] = (long long)wall_clock64();
 
         // every block derives the same decisions from the same partial sums
+        // (read by all its threads at once, then reduced)
         long long total = 0, before = 0, open_nodes = 0;
         long long mstep = 0x7fffffffffffffffll;
-        for (int q = 0; q < G; ++q) {
+        for (int q = threadIdx.x; q < G; q += blockDim.x) {
             const long long c = a.part_cnt[par * G + q];
             if (q < b) before += c;
             total += c;
             open_nodes += a.part_open[par * G + q];
             mstep = min(mstep, a.part_step[par * G + q]);
         }
+        total = block_sum_ll(total, red_ll);
+        before = block_sum_ll(before, red_ll);
+        open_nodes = block_sum_ll(open_nodes, red_ll);
+        mstep = block_min_ll(mstep, red_ll);
         const int errv = __hip_atomic_load(a.err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         if (errv != 0) {
             status = kStatusError;
@@ -861,13 +864,17 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
         const int na = __hip_atomic_load(&a.acnt[wave_par(wave)], __ATOMIC_ACQUIRE,
                                          __HIP_MEMORY_SCOPE_AGENT);
         const long long m0 = (long long)wall_clock64();
+        // targets are taken dynamically (merges differ widely in cost); the
+        // next one is claimed while the current one merges
+        int next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(&a.mcur[wave_par(wave)], 1);
         for (;;) {
-            // targets are taken dynamically: merges differ widely in cost
-            if (threadIdx.x == 0) s.misc[2] = atomicAdd(&a.mcur[wave_par(wave)], 1);
+            if (threadIdx.x == 0) s.misc[2] = next;
             __syncthreads();
             const int k = s.misc[2];
             __syncthreads();
             if (k >= na) break;
+            if (threadIdx.x == 0) next = atomicAdd(&a.mcur[wave_par(wave)], 1);
             merge_node(a, a.alist[k], wave, s, st_cand);
             ++st_merges;
         }
