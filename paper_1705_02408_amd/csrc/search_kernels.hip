@@ -372,14 +372,18 @@ __device__ __forceinline__ float block_excl_min(float v, float *scratch) {
     return fminf(before, ex);
 }
 
+constexpr int kPairMax = 256;  // survivors handled by the all-pairs step
+
 // P(x) <- Min(P(x) U C): B[0..nB) sorted, C[0..nC) unsorted; result sorted in B.
 // With two objectives (m = 0 everywhere) a Pareto front sorted by cost has
 // strictly falling drift, so the only possible dominator of a label among
 // the front's labels of cost <= its own is the last of them: every test is a
 // binary search.  With three objectives the tests scan cost prefixes,
 // skipping 64-label segments that cannot hold a dominator.
+// lo: lowered to the first index of B this merge changes (labels below it
+// keep their places).
 __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan, bool three,
-                            int *err) {
+                            int &lo, int *err) {
     const int bd = blockDim.x;
     if (!three) {
         // 1. the last bucket label of cost <= q.c decides
@@ -435,35 +439,40 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     const int nS = compact_alive(s.C, s.cdead, nC, s.scan);
     if (nS == 0) return;
     int nS2;
-    if (nS <= 64) {
-        // 4-5 for a few survivors, by one wave without block barriers: each
-        // lane compares its survivor with all the others (broadcast LDS
-        // reads): it dies if a lexicographically smaller one dominates it,
-        // and its rank among the living ones is its place in the sorted run
-        if (threadIdx.x < 64) {
-            const int l = threadIdx.x;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            bool dead = l >= nS;
-            if (l < nS) v = s.C[l];
-            for (int j = 0; j < nS; ++j) {
+    if (nS <= kPairMax) {
+        // 4-5 for up to kPairMax survivors, all pairs at once: g threads per
+        // survivor, each over a slice of the others.  A survivor dies if a
+        // lexicographically smaller one dominates it; its rank among the
+        // living ones is its place in the sorted run.
+        int g = 1;
+        while (g < 64 && g * 2 * nS <= bd) g <<= 1;
+        const int i = (int)threadIdx.x / g, sub = (int)threadIdx.x % g;
+        const bool mine = i < nS;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        bool dead = false;
+        if (mine) {
+            v = s.C[i];
+            for (int j = sub; j < nS; j += g) {
                 const float4 o = s.C[j];
                 dead = dead || (lex_lt(o, v) && dm_le(o, v));
             }
-            s.cdead[l] = dead ? 1 : 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            int pos = 0;
-            for (int j = 0; j < nS; ++j) pos += (!s.cdead[j] && lex_lt(s.C[j], v)) ? 1 : 0;
-            const uint64_t am = ballot64(!dead);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (!dead) s.C[pos] = v;
-            if (l == 0) s.misc[3] = (int)__popcll(am);
         }
+        for (int o = 1; o < g; o <<= 1) dead = __shfl_xor((int)dead, o, 64) != 0 || dead;
+        if (mine && sub == 0) s.cdead[i] = dead ? 1 : 0;
         __syncthreads();
-        nS2 = s.misc[3];
+        int pos = 0;
+        if (mine && !dead)
+            for (int j = sub; j < nS; j += g) pos += (!s.cdead[j] && lex_lt(s.C[j], v)) ? 1 : 0;
+        for (int o = 1; o < g; o <<= 1) pos += __shfl_xor(pos, o, 64);
+        int alive = 0;
+        {
+            const bool lead = mine && sub == 0 && !dead;
+            int tot;
+            block_excl_scan(lead ? 1 : 0, s.scan, &tot);
+            alive = tot;
+        }
+        if (mine && sub == 0 && !dead) s.C[pos] = v;  // every read of C is done
+        nS2 = alive;
         __syncthreads();
     } else {
         int P = 1;
@@ -495,6 +504,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     }
     // 6. bucket labels a surviving candidate dominates leave
     bool any_dead = false;
+    long long first_dead = nB;
     if (!three) {
         for (int j = threadIdx.x; j < nB; j += bd) {
             const float4 b = s.B[j];
@@ -502,6 +512,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             const bool dead = kk > 0 && s.C[kk - 1].y <= b.y;
             s.bdead[j] = dead ? 1 : 0;
             any_dead = any_dead || dead;
+            if (dead) first_dead = min(first_dead, (long long)j);
         }
     } else {
         const bool seg = nS2 > 64 && seg_summary(s.C, nS2, s.segd, s.segm, s.segcap);
@@ -511,9 +522,17 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             const bool dead = any_dominates(s.C, kk, b, s.segd, s.segm, seg, 1, 0, nullptr);
             s.bdead[j] = dead ? 1 : 0;
             any_dead = any_dead || dead;
+            if (dead) first_dead = min(first_dead, (long long)j);
         }
     }
-    const int nBs = __syncthreads_or(any_dead) ? compact_alive(s.B, s.bdead, nB, s.scan) : nB;
+    int nBs = nB;
+    if (__syncthreads_or(any_dead)) {
+        lo = min(lo, (int)block_min_ll(first_dead, reinterpret_cast<long long *>(s.scan)));
+        nBs = compact_alive(s.B, s.bdead, nB, s.scan);
+    }
+    // the first survivor's place: labels below it and below the first
+    // removed one keep their places
+    lo = min(lo, lex_rank(s.B, nBs, s.C[0]));
     const int total = nBs + nS2;
     if (total > (s.spilled ? s.capG : capB) && (s.spilled || total > s.capG)) {
         if (threadIdx.x == 0) atomicOr(err, kErrBucket);
@@ -582,6 +601,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                            long long &st_cand) {
     const int4 nbx = a.nb[x];
     int nB = nbx.z;
+    int lo = nB;  // first index the merges change
     if (!stage_front(a, s, nbx)) return;
     const bool rst = (a.nflag[x] & 1u) != 0u;
     const int q = (a.nq > 1) ? query_of(a, x) : 0;
@@ -647,7 +667,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
             st_cand += nC;
             if (nC > 0) {
                 const int before = nB;
-                merge_chunk(s, nB, nC, a.capB, a.near_scan, three, a.err);
+                merge_chunk(s, nB, nC, a.capB, a.near_scan, three, lo, a.err);
                 changed = true;
                 (void)before;
             }
@@ -675,13 +695,14 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
         cap = s.misc[1];
         __syncthreads();
         if (off < 0) return;
+        lo = 0;  // a fresh region gets the whole front
     }
     float mn = MPAP_INF;
     int nopen = 0;
     long long first = nB;
     for (int i = threadIdx.x; i < nB; i += blockDim.x) {
         const float4 L = s.B[i];
-        a.pool[(size_t)(unsigned)off + i] = L;
+        if (i >= lo) a.pool[(size_t)(unsigned)off + i] = L;
         if (lab_open(L)) {
             mn = fminf(mn, L.x);
             ++nopen;
@@ -941,7 +962,7 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
         s.B = s.Bl;
         s.bdead = s.bdeadl;
         s.spilled = false;
-        int nB = 0;
+        int nB = 0, glo = 0;
         for (int gi = g.qgoff[q]; gi < g.qgoff[q + 1]; ++gi) {
             const int4 nbv = a.nb[g.goal_list[gi]];
             for (int c0 = 0; c0 < nbv.z; c0 += a.capC) {
@@ -949,7 +970,7 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
                 for (int i = threadIdx.x; i < nC; i += blockDim.x)
                     s.C[i] = a.pool[(size_t)(unsigned)nbv.x + c0 + i];
                 __syncthreads();
-                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, a.err);
+                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, glo, a.err);
             }
         }
         const long long o = g.lab_off[q];
