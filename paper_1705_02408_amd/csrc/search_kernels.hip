@@ -374,6 +374,16 @@ __device__ __forceinline__ float block_excl_min(float v, float *scratch) {
 
 constexpr int kPairMax = 256;  // survivors handled by the all-pairs step
 
+// claims a slot for each lane with keep set, at *counter (LDS), one atomic per
+// wave; the slots of one call are dense but in no particular order
+__device__ __forceinline__ void wave_append(bool keep, int *counter, int &slot) {
+    const uint64_t m = ballot64(keep);
+    int base = 0;
+    if (lane_id() == 0 && m) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, 0, 64);
+    slot = base + lanes_below(m);
+}
+
 // P(x) <- Min(P(x) U C): B[0..nB) sorted, C[0..nC) unsorted; result sorted in B.
 // With two objectives (m = 0 everywhere) a Pareto front sorted by cost has
 // strictly falling drift, so the only possible dominator of a label among
@@ -381,7 +391,8 @@ constexpr int kPairMax = 256;  // survivors handled by the all-pairs step
 // binary search.  With three objectives the tests scan cost prefixes,
 // skipping 64-label segments that cannot hold a dominator.
 // lo: lowered to the first index of B this merge changes (labels below it
-// keep their places).
+// keep their places).  The append counters misc[6] and misc[7] must be zero
+// on entry.
 __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan, bool three,
                             int &lo, int *err) {
     const int bd = blockDim.x;
@@ -394,28 +405,27 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         }
         __syncthreads();
     } else {
-        // 1. near scan: the labels just below the candidate's cost
-        for (int i = threadIdx.x; i < nC; i += bd) {
-            const float4 q = s.C[i];
-            const int k = upper_c(s.B, nB, q.x);
-            const int stop = max(0, k - near_scan);
-            bool dead = false;
-            for (int j = k - 1; j >= stop && !dead; --j) dead = dm_le(s.B[j], q);
-            s.cdead[i] = dead ? 1 : 0;
-            s.u_end[i] = dead ? 0 : stop;
-        }
-        __syncthreads();
-        // 2. list the undecided candidates (bucket prefix left to scan)
-        int nU = 0;
+        // 1. near scan: the labels just below the candidate's cost; 2. list
+        // the undecided candidates (bucket prefix left to scan)
         for (int t0 = 0; t0 < nC; t0 += bd) {
             const int i = t0 + threadIdx.x;
-            const bool und = i < nC && !s.cdead[i] && s.u_end[i] > 0;
-            int tot;
-            const int ex = block_excl_scan(und ? 1 : 0, s.scan, &tot);
-            if (und) s.u_idx[nU + ex] = i;
-            nU += tot;
+            bool und = false;
+            if (i < nC) {
+                const float4 q = s.C[i];
+                const int k = upper_c(s.B, nB, q.x);
+                const int stop = max(0, k - near_scan);
+                bool dead = false;
+                for (int j = k - 1; j >= stop && !dead; --j) dead = dm_le(s.B[j], q);
+                s.cdead[i] = dead ? 1 : 0;
+                s.u_end[i] = dead ? 0 : stop;
+                und = !dead && stop > 0;
+            }
+            int slot;
+            wave_append(und, &s.misc[6], slot);
+            if (und) s.u_idx[slot] = i;
         }
         __syncthreads();
+        const int nU = s.misc[6];
         // 3. the rest of the prefix, gs threads per candidate, by segments
         if (nU > 0) {
             const bool use_seg = seg_summary(s.B, nB, s.segd, s.segm, s.segcap);
@@ -435,8 +445,18 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             __syncthreads();
         }
     }
-    // 4. survivors of the bucket test, sorted
-    const int nS = compact_alive(s.C, s.cdead, nC, s.scan);
+    // 4. survivors of the bucket test, gathered (any order) into tmp (the
+    // undecided-scan space, free now) while they fit the all-pairs step
+    float4 *tmp = reinterpret_cast<float4 *>(s.u_end);  // capC / 4 >= kPairMax labels
+    for (int t0 = 0; t0 < nC; t0 += bd) {
+        const int i = t0 + threadIdx.x;
+        const bool alive = i < nC && !s.cdead[i];
+        int slot;
+        wave_append(alive, &s.misc[7], slot);
+        if (alive && slot < kPairMax) tmp[slot] = s.C[i];
+    }
+    __syncthreads();
+    const int nS = s.misc[7];
     if (nS == 0) return;
     int nS2;
     if (nS <= kPairMax) {
@@ -451,9 +471,9 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         bool dead = false;
         if (mine) {
-            v = s.C[i];
+            v = tmp[i];
             for (int j = sub; j < nS; j += g) {
-                const float4 o = s.C[j];
+                const float4 o = tmp[j];
                 dead = dead || (lex_lt(o, v) && dm_le(o, v));
             }
         }
@@ -462,19 +482,15 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         __syncthreads();
         int pos = 0;
         if (mine && !dead)
-            for (int j = sub; j < nS; j += g) pos += (!s.cdead[j] && lex_lt(s.C[j], v)) ? 1 : 0;
+            for (int j = sub; j < nS; j += g) pos += (!s.cdead[j] && lex_lt(tmp[j], v)) ? 1 : 0;
         for (int o = 1; o < g; o <<= 1) pos += __shfl_xor(pos, o, 64);
-        int alive = 0;
-        {
-            const bool lead = mine && sub == 0 && !dead;
-            int tot;
-            block_excl_scan(lead ? 1 : 0, s.scan, &tot);
-            alive = tot;
-        }
-        if (mine && sub == 0 && !dead) s.C[pos] = v;  // every read of C is done
-        nS2 = alive;
-        __syncthreads();
+        const bool lead = mine && sub == 0 && !dead;
+        if (lead) s.C[pos] = v;  // tmp is the input, C the sorted output
+        nS2 = __syncthreads_count(lead);
     } else {
+        // many survivors: compact them in place, sort, sweep
+        const int nSc = compact_alive(s.C, s.cdead, nC, s.scan);
+        (void)nSc;
         int P = 1;
         while (P < nS) P <<= 1;
         for (int i = nS + threadIdx.x; i < P; i += bd)
@@ -634,8 +650,14 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
         __syncthreads();
         const int ntile = min((int)blockDim.x, e1 - t0);
         for (int j0 = 0; j0 < tot; j0 += a.capC) {
-            // children j0 .. j0+capC-1 of this tile, those within the bound
-            int nC = 0;
+            // children j0 .. j0+capC-1 of this tile, those within the bound,
+            // appended in any order (every later step is order-free)
+            if (threadIdx.x == 0) {
+                s.misc[5] = 0;  // candidates
+                s.misc[6] = 0;  // undecided after the near scan
+                s.misc[7] = 0;  // survivors of the bucket test
+            }
+            __syncthreads();
             for (int jr = j0; jr < min(tot, j0 + a.capC); jr += blockDim.x) {
                 const int j = jr + threadIdx.x;
                 bool ok = false;
@@ -658,12 +680,12 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                     const unsigned meta = MPAP_OPEN_BIT | (unsigned)(__float_as_int(P.w) + 1);
                     ch = make_float4(c2, d2, m2, __uint_as_float(meta));
                 }
-                int t2;
-                const int ex2 = block_excl_scan(ok ? 1 : 0, s.scan, &t2);
-                if (ok) s.C[nC + ex2] = ch;
-                nC += t2;
+                int slot;
+                wave_append(ok, &s.misc[5], slot);
+                if (ok) s.C[slot] = ch;
             }
             __syncthreads();
+            const int nC = s.misc[5];
             st_cand += nC;
             if (nC > 0) {
                 const int before = nB;
@@ -698,25 +720,36 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
         lo = 0;  // a fresh region gets the whole front
     }
     float mn = MPAP_INF;
-    int nopen = 0;
-    long long first = nB;
+    int nopen = 0, first = nB;
     for (int i = threadIdx.x; i < nB; i += blockDim.x) {
         const float4 L = s.B[i];
         if (i >= lo) a.pool[(size_t)(unsigned)off + i] = L;
         if (lab_open(L)) {
             mn = fminf(mn, L.x);
             ++nopen;
-            first = min(first, (long long)i);
+            first = min(first, i);
         }
     }
-    mn = block_min(mn, reinterpret_cast<float *>(s.scan));
-    first = block_min_ll(first, reinterpret_cast<long long *>(s.scan));
-    int tot_open;
-    block_excl_scan(nopen, s.scan, &tot_open);
+    // least open cost, open count and first open index in one reduction
+    mn = wave_min(mn);
+    nopen = wave_sum(nopen);
+    first = -wave_max_i(-first);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane_id() == 0) {
+        s.e_c[w] = mn;
+        s.e_off[w] = nopen;
+        s.e_pre[w] = first;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        a.nb[x] = make_int4(off, cap, nB, tot_open);
+        for (int i = 1; i < nw; ++i) {
+            mn = fminf(mn, s.e_c[i]);
+            nopen += s.e_off[i];
+            first = min(first, s.e_pre[i]);
+        }
+        a.nb[x] = make_int4(off, cap, nB, nopen);
         // first open label: the count and select of the next iteration start there
-        reinterpret_cast<int *>(&a.fo[x])[3] = (int)first;
+        reinterpret_cast<int *>(&a.fo[x])[3] = first;
         a.minopen[x] = mn;
     }
     __syncthreads();
@@ -969,6 +1002,10 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
                 const int nC = min(a.capC, nbv.z - c0);
                 for (int i = threadIdx.x; i < nC; i += blockDim.x)
                     s.C[i] = a.pool[(size_t)(unsigned)nbv.x + c0 + i];
+                if (threadIdx.x == 0) {
+                    s.misc[6] = 0;  // merge_chunk's append counters start at zero
+                    s.misc[7] = 0;
+                }
                 __syncthreads();
                 merge_chunk(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, glo, a.err);
             }
