@@ -278,6 +278,15 @@ __device__ __forceinline__ int upper_c(const float4 *arr, int n, float c) {
     }
     return lo;
 }
+// first index j of the sorted arr[0..n) with arr[j].c >= c
+__device__ __forceinline__ int lower_c(const float4 *arr, int n, float c) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (arr[mid].x < c) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
 // number of entries of the sorted arr[0..n) lexicographically below v
 __device__ __forceinline__ int lex_rank(const float4 *arr, int n, const float4 &v) {
     int lo = 0, hi = n;
@@ -518,11 +527,13 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         }
         nS2 = compact_alive(s.C, s.cdead, nS, s.scan);
     }
-    // 6. bucket labels a surviving candidate dominates leave
+    // 6. bucket labels a surviving candidate dominates leave (only labels at
+    // least as costly as the cheapest survivor can be dominated)
     bool any_dead = false;
     long long first_dead = nB;
+    const int js = lower_c(s.B, nB, s.C[0].x);
     if (!three) {
-        for (int j = threadIdx.x; j < nB; j += bd) {
+        for (int j = js + threadIdx.x; j < nB; j += bd) {
             const float4 b = s.B[j];
             const int kk = upper_c(s.C, nS2, b.x);
             const bool dead = kk > 0 && s.C[kk - 1].y <= b.y;
@@ -532,7 +543,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         }
     } else {
         const bool seg = nS2 > 64 && seg_summary(s.C, nS2, s.segd, s.segm, s.segcap);
-        for (int j = threadIdx.x; j < nB; j += bd) {
+        for (int j = js + threadIdx.x; j < nB; j += bd) {
             const float4 b = s.B[j];
             const int kk = upper_c(s.C, nS2, b.x);
             const bool dead = any_dominates(s.C, kk, b, s.segd, s.segm, seg, 1, 0, nullptr);
@@ -543,12 +554,14 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     }
     int nBs = nB;
     if (__syncthreads_or(any_dead)) {
-        lo = min(lo, (int)block_min_ll(first_dead, reinterpret_cast<long long *>(s.scan)));
-        nBs = compact_alive(s.B, s.bdead, nB, s.scan);
+        // labels below the first removed one keep their places
+        const int fd = (int)block_min_ll(first_dead, reinterpret_cast<long long *>(s.scan));
+        lo = min(lo, fd);
+        nBs = fd + compact_alive(s.B + fd, s.bdead + fd, nB - fd, s.scan);
     }
-    // the first survivor's place: labels below it and below the first
-    // removed one keep their places
-    lo = min(lo, lex_rank(s.B, nBs, s.C[0]));
+    // the first survivor's place: labels below it keep their places
+    const int r0 = lex_rank(s.B, nBs, s.C[0]);
+    lo = min(lo, r0);
     const int total = nBs + nS2;
     if (total > (s.spilled ? s.capG : capB) && (s.spilled || total > s.capG)) {
         if (threadIdx.x == 0) atomicOr(err, kErrBucket);
@@ -581,11 +594,11 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     // to their places last.
     for (int i = threadIdx.x; i < nS2; i += bd) s.u_idx[i] = i + lex_rank(s.B, nBs, s.C[i]);
     __syncthreads();
-    for (int top = nBs; top > 0; top -= bd) {
+    for (int top = nBs; top > r0; top -= bd) {
         const int k = top - bd + (int)threadIdx.x;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         int pos = -1;
-        if (k >= 0) {
+        if (k >= r0) {
             v = s.B[k];
             pos = k + lex_rank(s.C, nS2, v);
         }
