@@ -151,6 +151,11 @@ typedef struct {
     int32_t block_threads; /* tuning: threads per workgroup of the persistent search,
                               1024 (one per CU), 512 (two) or 256 (four); 0 = 1024.
                               Never changes the result. */
+    int32_t wave_min_targets; /* tuning: an iteration with at least this many merge
+                                 targets of small front merges each of them with a
+                                 single wave (16 merges per CU at once); 0 = four times the
+                                 waves of the grid, < 0 = never.  Never changes the
+                                 result. */
 } mpap_search_params;
 
 /*

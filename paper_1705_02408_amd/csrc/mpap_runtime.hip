@@ -545,6 +545,7 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
             x.block_threads != 1024)
             return fail(MPAP_ERR_INVAL, "block_threads must be 0, 256, 512 or 1024");
         if (x.block_threads != 0) p.block_threads = x.block_threads;
+        if (x.wave_min_targets != 0) p.wave_min_targets = x.wave_min_targets;
     }
     if (p.max_waves <= 0) p.max_waves = 1 << 18;
     if (nsp == 1 && nq > 1) {
@@ -568,7 +569,7 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
     return MPAP_OK;
 }
 
-int search_shape(int stage_cap, int block_threads, SearchShape &L) {
+int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchShape &L) {
     DeviceInfo di;
     int r = device_info(&di);
     if (r) return r;
@@ -593,10 +594,25 @@ int search_shape(int stage_cap, int block_threads, SearchShape &L) {
     L.lds = fixed + 17 * (size_t)capB + 8 * (size_t)(std::max(capB, L.capC) / 64 + 2);
     if (stage_cap > 0) capB = std::min(capB, std::max(stage_cap, 1));
     L.capB = capB;
+    // single-wave merges: each wave's slice of the same LDS holds a front of
+    // wcap labels (16 B + a flag byte each, two floats per 64), 64 children
+    // and their flags
+    L.wslice = (int)((L.lds / (size_t)(L.threads / 64)) & ~(size_t)15);
+    {
+        const long long room = (long long)L.wslice - 16 * 64 - 64 - 64;
+        int wcap = room > 0 ? (int)((room * 64) / (17 * 64 + 8)) : 0;
+        wcap -= wcap % 64;
+        if (stage_cap > 0) wcap = std::min(wcap, stage_cap - stage_cap % 64);
+        L.wcap = wcap >= 64 ? wcap : 0;
+    }
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search, L.threads, L.lds));
     if (per_cu < 1) return fail(MPAP_ERR_DEVICE, "search kernel does not fit on a CU");
     L.nblocks = di.cus * std::min(per_cu, per_cu_want);
+    // by default a wave-per-target iteration needs four small targets per wave
+    if (wave_min_targets < 0) L.wcap = 0;
+    L.wmin = wave_min_targets > 0 ? wave_min_targets : 4 * L.nblocks * (L.threads / 64);
+    L.explicit_wmin = wave_min_targets > 0;
     return MPAP_OK;
 }
 
@@ -623,6 +639,7 @@ SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
     a.qroot = w->qroot; a.qlast = w->qlast;
     a.qdelta = w->qdelta; a.max_waves = p.max_waves; a.near_scan = p.near_scan;
     a.capB = L.capB; a.capC = L.capC; a.nblocks = L.nblocks;
+    a.wcap = L.wcap; a.wslice = L.wslice; a.wmin = L.wmin;
     a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
     a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
     a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
@@ -713,7 +730,7 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(w->ev0, s));
         void *kargs[] = {&a};
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search),
+        HIP_TRY(hipLaunchCooperativeKernel(search_kernel_for(L, g->n),
                                            dim3(L.nblocks), dim3(L.threads), kargs, L.lds, s));
         HIP_TRY(hipEventRecord(w->ev1, s));
         k_count_front<<<std::max(1, std::min(div_up(g->n, 256), 1024)), 256, 0, s>>>(a);
@@ -813,7 +830,7 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
         if (p.heur[q] == 1 && !(g->symmetric_alias ? g->sdrift : g->srdrift))
             return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph (mpap_surrogate_score)");
     SearchShape L;
-    if ((r = search_shape(p.stage_cap, p.block_threads, L))) return r;
+    if ((r = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L))) return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     Workspace *w = nullptr;

@@ -164,7 +164,7 @@ int plan_record(mpap_plan *p) {
     hipGraphNode_t n_pre = nullptr, n_e0 = nullptr, n_s = nullptr, n_e1 = nullptr, n_post = nullptr;
     void *kargs[] = {&p->args};
     hipKernelNodeParams kp{};
-    kp.func = reinterpret_cast<void *>(k_search);
+    kp.func = const_cast<void *>(search_kernel_for(p->shape, g->n));
     kp.gridDim = dim3(p->shape.nblocks);
     kp.blockDim = dim3(p->shape.threads);
     kp.sharedMemBytes = (unsigned)p->shape.lds;
@@ -224,7 +224,8 @@ int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
     mpap_plan *p = new mpap_plan();
     p->g = g;
     int r = search_prep(g, sp, nsp, p->prep);
-    if (!r) r = search_shape(p->prep.stage_cap, p->prep.block_threads, p->shape);
+    if (!r) r = search_shape(p->prep.stage_cap, p->prep.block_threads, p->prep.wave_min_targets,
+                             p->shape);
     auto bail = [&](int st) {
         mpap_plan_free(p);
         return st;

@@ -213,9 +213,9 @@ inline int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     if ((r = dalloc(&w->gcnt, n))) return r;
     if ((r = dalloc(&w->fo, n))) return r;
     if ((r = dalloc(&w->mark, n))) return r;
-    if ((r = dalloc(&w->alist, n))) return r;
-    if ((r = dalloc(&w->acnt, 2))) return r;
-    if ((r = dalloc(&w->mcur, 2))) return r;
+    if ((r = dalloc(&w->alist, 2 * (size_t)n))) return r;
+    if ((r = dalloc(&w->acnt, 4))) return r;
+    if ((r = dalloc(&w->mcur, 4))) return r;
     if ((r = dalloc(&w->part_cnt, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->part_open, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->part_step, 2 * (size_t)nblocks))) return r;
@@ -323,16 +323,20 @@ struct SearchPrep {
     int nq = 0;
     std::vector<float> delta;  // per query lambda * radius
     int max_waves = 0, near_scan = 16, stage_cap = 0, block_threads = 1024;
+    int wave_min_targets = 0;  // 0: default; < 0: never merge by single waves
     std::vector<float> beta;
     std::vector<int> nobj, root, heur;
 };
 // Launch shape of the persistent search kernel.
 struct SearchShape {
     int threads = 1024, capC = 1024, capB = 0, nblocks = 0;
+    int wcap = 0, wslice = 0;  // single-wave merges: front capacity, LDS slice bytes
+    int wmin = 0;              // and the least small-target count that uses them
+    bool explicit_wmin = false;
     size_t lds = 0;
 };
 int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, SearchPrep &p);
-int search_shape(int stage_cap, int block_threads, SearchShape &L);
+int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchShape &L);
 // Uploads the per-query parameters into w (synchronous).
 int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s);
 // The search with capacity growth and retries, goal fronts and statistics,
@@ -342,6 +346,14 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
 SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
                        const SearchShape &L);
 GoalArgs goal_args(const mpap_graph *g, Workspace *w);
+// The search kernel build for a launch on g: with single-wave merges only
+// when some iteration can have wmin targets (or the caller asked for them).
+inline const void *search_kernel_for(const SearchShape &L, int n) {
+    const bool wave = L.wcap > 0 && (L.explicit_wmin || n >= 4 * (long long)L.wmin);
+    return wave ? reinterpret_cast<const void *>(k_search_wave)
+                : reinterpret_cast<const void *>(k_search);
+}
+
 // Fills res's fronts, statistics, trace and latencies from host copies.
 void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_out,
                    const int *counts, const float4 *plab, const int *pnode, const int *qlast,

@@ -76,9 +76,13 @@ struct SearchArgs {
     int *gcnt;         // per node group size of the current iteration
     int4 *fo;          // per node {frontier offset, count, wave, first open label index}
     int *mark;         // per node last wave it was queued as merge target
-    int *alist;        // merge targets of the current wave [n]
-    int *acnt;         // [2] target counts by wave parity
-    int *mcur;         // [2] next target to merge, by wave parity
+    int *alist;        // merge targets of the current wave [2n]: fronts of at most wcap
+                       // labels at [0, n) (merged by one wave), larger ones at [n, 2n)
+    int *acnt;         // [4] target counts by wave parity: small [0..1], large [2..3]
+    int *mcur;         // [4] next target to merge, same layout
+    int wcap;          // largest front merged by a single wave (0: none)
+    int wmin;          // single-wave merges in iterations with at least wmin small targets
+    int wslice;        // LDS bytes of one wave's slice in single-wave merges
     float4 *F;         // frontier labels of the current wave
     long long F_cap;
     int2 *arena;       // per expanded label {node, parent id}
@@ -119,6 +123,7 @@ __global__ void k_rescore(const int2 *arena, const int *optr, const int *ocol,
                           int maxlen, float4 *out, int *err);
 __global__ void k_search_roots(SearchArgs a);
 __global__ void k_search(SearchArgs a);
+__global__ void k_search_wave(SearchArgs a);  // with single-wave merges
 __global__ void k_count_front(SearchArgs a);
 __global__ void k_goal_front(SearchArgs a, GoalArgs g);
 // per-query goal-front regions: lab_cap[q] = sum of the front sizes of the

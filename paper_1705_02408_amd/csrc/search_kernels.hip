@@ -120,6 +120,7 @@ __device__ void phase_count(const SearchArgs &a, long long istep, int par, int l
 // of the per-node counts on top of the block's offset); each flagged node is
 // then handled by one wave: its group labels are copied to the frontier,
 // closed and given their arena ids, and its out-neighbours are queued.
+template <bool kSplit>
 __device__ void phase_select(const SearchArgs &a, long long istep, int wave, long long abase,
                              long long myoff, int lo, int hi, int *list, int *list_off,
                              int *scan) {
@@ -185,22 +186,29 @@ __device__ void phase_select(const SearchArgs &a, long long istep, int wave, lon
                 if (a.nq > 1) atomicMax(&a.qlast[query_of(a, vv)], wave);
                 else if (vv >= 0) a.qlast[0] = wave;
             }
-            // queue out-neighbours as merge targets of this wave (one slot
-            // reservation per wave of 64 out-edges)
+            // queue out-neighbours as merge targets of this wave, by the size
+            // of their front (one slot reservation per wave of 64 out-edges)
             for (int e0 = a.optr[vv]; e0 < a.optr[vv + 1]; e0 += 64) {
                 const int e = e0 + l;
                 int x = -1;
-                bool fresh = false;
+                bool fresh = false, big = false;
                 if (e < a.optr[vv + 1]) {
                     x = a.ocol[e];
                     fresh = atomicExch(&a.mark[x], wave) != wave;
+                    if (kSplit && fresh) big = a.nb[x].z > a.wcap;
                 }
-                const uint64_t fm = ballot64(fresh);
-                if (fm) {
+                const uint64_t fs = ballot64(fresh && !big), fb = ballot64(fresh && big);
+                if (fs) {
                     int base = 0;
-                    if (l == 0) base = atomicAdd(&a.acnt[wp], (int)__popcll(fm));
+                    if (l == 0) base = atomicAdd(&a.acnt[wp], (int)__popcll(fs));
                     base = __shfl(base, 0, 64);
-                    if (fresh) a.alist[base + lanes_below(fm)] = x;
+                    if (fresh && !big) a.alist[base + lanes_below(fs)] = x;
+                }
+                if (fb) {
+                    int base = 0;
+                    if (l == 0) base = atomicAdd(&a.acnt[2 + wp], (int)__popcll(fb));
+                    base = __shfl(base, 0, 64);
+                    if (fresh && big) a.alist[a.n + base + lanes_below(fb)] = x;
                 }
             }
         }
@@ -611,6 +619,299 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     __syncthreads();
 }
 
+// ------------------------------------------------ single-wave merges (small fronts)
+// A target whose front holds at most wcap labels is merged by one wave in its
+// own LDS slice, without workgroup barriers, so the 16 waves of a workgroup
+// merge 16 targets at once.  The steps are those of merge_chunk, per chunk
+// of 64 children (one per lane).  A front that would outgrow the slice is
+// left untouched (nothing is written back) and handed to the workgroup path.
+struct WaveLds {
+    float4 *B;    // [wcap] the front, lexicographic order
+    float4 *C;    // [64] the chunk's children
+    float *sd;    // [wcap/64] per segment of B: least d
+    float *sm;    // [wcap/64] per segment of B: least m
+    uint8_t *bd;  // [wcap] flags of B
+    uint8_t *cd;  // [64] flags of C (1: dead)
+};
+
+__device__ void carve_wave(unsigned char *lds, const SearchArgs &a, WaveLds &w) {
+    unsigned char *p = lds + (size_t)(threadIdx.x >> 6) * a.wslice;
+    w.B = reinterpret_cast<float4 *>(p);
+    p += 16 * (size_t)a.wcap;
+    w.C = reinterpret_cast<float4 *>(p);
+    p += 16 * 64;
+    w.sd = reinterpret_cast<float *>(p);
+    p += 4 * (size_t)(a.wcap / 64);
+    w.sm = reinterpret_cast<float *>(p);
+    p += 4 * (size_t)(a.wcap / 64);
+    w.bd = p;
+    p += a.wcap;
+    w.cd = p;
+}
+
+// LDS writes of the wave's lanes visible to its other lanes
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_min_i(int v) { return -wave_max_i(-v); }
+
+// segment summaries of the wave's front B[0..n)
+__device__ void wave_seg_summary(const WaveLds &W, int n) {
+    const int l = lane_id();
+    for (int sg = 0; sg < ((n + 63) >> 6); ++sg) {
+        const int i = sg * 64 + l;
+        float d = MPAP_INF, m = MPAP_INF;
+        if (i < n) {
+            d = W.B[i].y;
+            m = W.B[i].z;
+        }
+        d = wave_min(d);
+        m = wave_min(m);
+        if (l == 0) {
+            W.sd[sg] = d;
+            W.sm[sg] = m;
+        }
+    }
+    wsync();
+}
+
+// Returns false when the front would outgrow the slice (the target then
+// goes to the workgroup path; nothing has been written).
+__device__ bool wave_merge_node(const SearchArgs &a, int x, int wave, const WaveLds &W,
+                                long long &cand_out) {
+    const int l = lane_id();
+    const int4 nbx = a.nb[x];
+    int nB = nbx.z;
+    if (nB > a.wcap) return false;
+    for (int i = l; i < nB; i += 64) W.B[i] = a.pool[(size_t)(unsigned)nbx.x + i];
+    wsync();
+    const bool rst = (a.nflag[x] & 1u) != 0u;
+    const int q = (a.nq > 1) ? query_of(a, x) : 0;
+    const float beta = a.qbeta[q];
+    const bool three = a.qnobj[q] >= 3;
+    const float *edrift = a.qheur[q] ? a.sdrift : a.rdrift;
+    if (three) wave_seg_summary(W, nB);
+    int lo = nB;
+    bool changed = false;
+    long long cand = 0;
+    const int e1 = a.rptr[x + 1];
+    for (int t0 = a.rptr[x]; t0 < e1; t0 += 64) {
+        // 64 in-edges at once: group sizes of their sources, packed by a prefix
+        const int e = t0 + l;
+        int cnt = 0, off = 0;
+        float ce = 0.f, de = 0.f;
+        if (e < e1) {
+            const int4 fu = a.fo[a.rsrc[e]];
+            if (fu.z == wave) {
+                cnt = fu.y;
+                off = fu.x;
+                ce = a.rcost[e];
+                de = edrift[e];
+            }
+        }
+        const int pre = wave_incl_scan_add(cnt);
+        const int tot = __shfl(pre, 63, 64);
+        for (int j0 = 0; j0 < tot; j0 += 64) {
+            // child j of the tile: in-edge t = first lane with prefix > j
+            const int j = j0 + l;
+            float4 ch = make_float4(0.f, 0.f, 0.f, 0.f);
+            bool alive = false;
+            {
+                int lo2 = 0, hi2 = 63;
+                while (lo2 < hi2) {
+                    const int mid = (lo2 + hi2) >> 1;
+                    if (__shfl(pre, mid, 64) > j) hi2 = mid; else lo2 = mid + 1;
+                }
+                const int t = lo2;
+                // every lane takes part in each shuffle (a lane not executing
+                // one would hand 0 to the lanes reading from it)
+                const int pb = __shfl(pre, t > 0 ? t - 1 : 0, 64);
+                const int before = t > 0 ? pb : 0;
+                const int o_t = __shfl(off, t, 64);
+                const float ce_t = __shfl(ce, t, 64), de_t = __shfl(de, t, 64);
+                if (j < tot) {
+                    const float4 P = a.F[o_t + (j - before)];
+                    const float c2 = P.x + ce_t;
+                    const float dpre = P.y + de_t;
+                    alive = dpre <= beta;
+                    const float d2 = rst ? 0.0f : dpre;
+                    const float m2 = three ? fmaxf(P.z, dpre) : 0.0f;
+                    const unsigned meta = MPAP_OPEN_BIT | (unsigned)(__float_as_int(P.w) + 1);
+                    ch = make_float4(c2, d2, m2, __uint_as_float(meta));
+                }
+            }
+            cand += alive ? 1 : 0;
+            // bucket test
+            if (!three) {
+                if (alive) {
+                    const int kk = upper_c(W.B, nB, ch.x);
+                    alive = !(kk > 0 && W.B[kk - 1].y <= ch.y);
+                }
+            } else {
+                // near scan per lane, then the rest of each undecided child's
+                // prefix by the whole wave, 64 labels a step
+                int stop = 0;
+                if (alive) {
+                    const int kk = upper_c(W.B, nB, ch.x);
+                    stop = max(0, kk - a.near_scan);
+                    for (int jj = kk - 1; jj >= stop && alive; --jj) alive = !dm_le(W.B[jj], ch);
+                }
+                uint64_t um = ballot64(alive && stop > 0);
+                while (um) {
+                    const int src = (int)__ffsll((unsigned long long)um) - 1;
+                    um &= um - 1;
+                    float4 qv;
+                    qv.x = __shfl(ch.x, src, 64);
+                    qv.y = __shfl(ch.y, src, 64);
+                    qv.z = __shfl(ch.z, src, 64);
+                    const int end = __shfl(stop, src, 64);
+                    bool dom = false;
+                    for (int sg = (end - 1) >> 6; sg >= 0 && !dom; --sg) {
+                        if (!(W.sd[sg] <= qv.y && W.sm[sg] <= qv.z)) continue;
+                        const int jj = (sg << 6) + l;
+                        dom = ballot64(jj < end && dm_le(W.B[jj], qv)) != 0;
+                    }
+                    if (l == src) alive = !dom;
+                }
+            }
+            const uint64_t am = ballot64(alive);
+            const int na = (int)__popcll(am);
+            if (na == 0) continue;
+            // children among themselves: a lexicographically smaller one may
+            // dominate; the survivors end up in W.C[0..ns)
+            if (alive) W.C[lanes_below(am)] = ch;
+            wsync();
+            bool dead = true;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (l < na) {
+                v = W.C[l];
+                dead = false;
+                for (int jj = 0; jj < na && !dead; ++jj) {
+                    const float4 o = W.C[jj];
+                    dead = lex_lt(o, v) && dm_le(o, v);
+                }
+            }
+            const uint64_t smask = ballot64(!dead);
+            const int ns = (int)__popcll(smask);
+            wsync();
+            if (!dead) W.C[lanes_below(smask)] = v;
+            wsync();
+            // front labels a survivor dominates leave (only those at least as
+            // costly as the cheapest survivor)
+            const float cmin = wave_min(dead ? MPAP_INF : v.x);
+            const int js = lower_c(W.B, nB, cmin);
+            int fd = nB;
+            for (int i = js + l; i < nB; i += 64) {
+                const float4 bl = W.B[i];
+                bool bdd = false;
+                for (int jj = 0; jj < ns && !bdd; ++jj) {
+                    const float4 o = W.C[jj];
+                    bdd = o.x <= bl.x && dm_le(o, bl);
+                }
+                W.bd[i] = bdd ? 1 : 0;
+                if (bdd) fd = min(fd, i);
+            }
+            fd = wave_min_i(fd);
+            wsync();
+            int nBs = nB;
+            if (fd < nB) {
+                // stable compaction from the first removed label; each chunk is
+                // read before it is written, and writes never pass the reads
+                int out = fd;
+                for (int c0 = fd; c0 < nB; c0 += 64) {
+                    const int i = c0 + l;
+                    const bool keep = i < nB && !W.bd[i];
+                    float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (keep) u = W.B[i];
+                    const uint64_t km = ballot64(keep);
+                    wsync();
+                    if (keep) W.B[out + lanes_below(km)] = u;
+                    out += (int)__popcll(km);
+                    wsync();
+                }
+                nBs = out;
+                lo = min(lo, fd);
+            }
+            if (nBs + ns > a.wcap) return false;
+            // the survivors' places, then B moved up from the top, then the survivors
+            int pos = -1, r = 0x7fffffff;
+            if (l < ns) {
+                const float4 sv = W.C[l];
+                int rs = 0;
+                for (int jj = 0; jj < ns; ++jj) rs += lex_lt(W.C[jj], sv) ? 1 : 0;
+                r = lex_rank(W.B, nBs, sv);
+                pos = r + rs;
+                v = sv;
+            }
+            const int r0 = wave_min_i(r);
+            for (int top = nBs; top > r0; top -= 64) {
+                const int i = top - 64 + l;
+                float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+                int np = -1;
+                if (i >= r0) {
+                    u = W.B[i];
+                    int c = 0;
+                    for (int jj = 0; jj < ns; ++jj) c += lex_lt(W.C[jj], u) ? 1 : 0;
+                    np = i + c;
+                }
+                wsync();
+                if (np >= 0) W.B[np] = u;
+                wsync();
+            }
+            if (l < ns) W.B[pos] = v;
+            wsync();
+            nB = nBs + ns;
+            lo = min(lo, r0);
+            changed = true;
+            if (three) wave_seg_summary(W, nB);
+        }
+    }
+    cand = wave_sum(cand);
+    if (l == 0) cand_out += cand;
+    if (!changed) return true;
+    // write back the changed suffix (a fresh region if the front outgrew its own)
+    int off = nbx.x, cap = nbx.y;
+    if (nB > cap) {
+        int o = 0, nc = 16;
+        while (nc < nB) nc <<= 1;
+        if (l == 0) {
+            o = (int)atomicAdd(a.pool_top, (unsigned)nc);
+            if ((unsigned long long)(unsigned)o + (unsigned)nc > a.pool_cap) {
+                atomicOr(a.err, kErrPool);
+                o = -1;
+            }
+        }
+        o = __shfl(o, 0, 64);
+        if (o < 0) return true;
+        off = o;
+        cap = nc;
+        lo = 0;
+    }
+    float mn = MPAP_INF;
+    int nopen = 0, first = nB;
+    for (int i = l; i < nB; i += 64) {
+        const float4 L = W.B[i];
+        if (i >= lo) a.pool[(size_t)(unsigned)off + i] = L;
+        if (lab_open(L)) {
+            mn = fminf(mn, L.x);
+            ++nopen;
+            first = min(first, i);
+        }
+    }
+    mn = wave_min(mn);
+    nopen = wave_sum(nopen);
+    first = wave_min_i(first);
+    if (l == 0) {
+        a.nb[x] = make_int4(off, cap, nB, nopen);
+        reinterpret_cast<int *>(&a.fo[x])[3] = first;
+        a.minopen[x] = mn;
+    }
+    return true;
+}
+
 // Stage P(x) (pool region nbv) for merging: LDS if it fits, else spill space.
 __device__ bool stage_front(const SearchArgs &a, MergeLds &s, const int4 &nbv) {
     s.spilled = nbv.z > a.capB;
@@ -781,10 +1082,10 @@ __global__ void __launch_bounds__(256) k_search_init(SearchArgs a) {
     }
     if (v == 0) {
         *a.pool_top = 16u * (unsigned)a.nq;
-        a.acnt[0] = 0;
-        a.acnt[1] = 0;
-        a.mcur[0] = 0;
-        a.mcur[1] = 0;
+        for (int i = 0; i < 4; ++i) {
+            a.acnt[i] = 0;
+            a.mcur[i] = 0;
+        }
         *a.bar = 0u;
         *a.err = 0;
         for (int i = 0; i < kOutWords; ++i) a.out[i] = 0;
@@ -845,7 +1146,8 @@ __device__ void carve_lds(unsigned char *lds, const SearchArgs &a, MergeLds &s) 
     s.spilled = false;
 }
 
-__global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
+template <bool kWaveMerges>
+__device__ __forceinline__ void search_body(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     MergeLds s;
     carve_lds(lds, a, s);
@@ -862,7 +1164,8 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
     int wave = 0;          // number of groups expanded so far
     long long abase = 0;   // arena ids handed out so far
     int it = 0;            // loop trips (parity of the partial sums)
-    long long st_merges = 0, st_cand = 0;
+    long long st_merges = 0, st_cand = 0;  // workgroup merges (thread 0 counts)
+    long long wv_merges = 0, wv_cand = 0;  // single-wave merges (lane 0 counts)
     int status = kStatusOk;
 
     const bool tr0 = (b == 0 && threadIdx.x == 0);
@@ -873,6 +1176,8 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
         if (threadIdx.x == 0 && b == 0) {
             a.acnt[wave_par(wave)] = 0;
             a.mcur[wave_par(wave)] = 0;
+            a.acnt[2 + wave_par(wave)] = 0;
+            a.mcur[2 + wave_par(wave)] = 0;
         }
         phase_count(a, i_step, par, lo, hi, s.u_idx, s.scan, red_ll);
         if (tr0 && tr) tr[kTrCountDone] = (long long)wall_clock64();
@@ -920,7 +1225,8 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
             if (b == 0 && threadIdx.x == 0) a.out[kOutNeed] = total;
             break;
         }
-        phase_select(a, i_step, wave, abase, before, lo, hi, s.u_idx, s.u_end, s.scan);
+        phase_select<kWaveMerges>(a, i_step, wave, abase, before, lo, hi, s.u_idx, s.u_end,
+                                  s.scan);
         if (tr0 && tr) tr[kTrSelectDone] = (long long)wall_clock64();
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) {
@@ -928,21 +1234,53 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
             tr[kTrGroup] = total;
         }
 
-        const int na = __hip_atomic_load(&a.acnt[wave_par(wave)], __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned wp = wave_par(wave);
+        const int na = __hip_atomic_load(&a.acnt[wp], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         const long long m0 = (long long)wall_clock64();
-        // targets are taken dynamically (merges differ widely in cost); the
-        // next one is claimed while the current one merges
+        // many small targets: one wave each; few: the workgroups share them
+        // (a single wave is slower per merge, so it pays only when the waves
+        // of the grid all have several targets)
+        const bool by_wave = kWaveMerges && a.wcap > 0 && na >= a.wmin;
+        if (by_wave) {
+            // small fronts: each wave takes targets itself and merges them in
+            // its LDS slice; fronts that outgrow it join the large list
+            WaveLds W;
+            carve_wave(lds, a, W);
+            for (;;) {
+                int k = 0;
+                if (lane_id() == 0) k = atomicAdd(&a.mcur[wp], 1);
+                k = __shfl(k, 0, 64);
+                if (k >= na) break;
+                const int x = a.alist[k];
+                if (wave_merge_node(a, x, wave, W, wv_cand)) {
+                    ++wv_merges;
+                } else if (lane_id() == 0) {
+                    const int kb = atomicAdd(&a.acnt[2 + wp], 1);
+                    a.alist[a.n + kb] = x;
+                }
+            }
+            __syncthreads();  // the slices are the workgroup's LDS again
+            grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+        }
+        // one workgroup per target: the large fronts (and the small ones when
+        // no wave took them), taken dynamically (merges differ widely in
+        // cost); the next one is claimed while the current one merges
+        int nbig = 0, nsmall = na;
+        if constexpr (kWaveMerges) {
+            nbig = __hip_atomic_load(&a.acnt[2 + wp], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (by_wave) nsmall = 0;
+        }
+        int *const cursor = &a.mcur[kWaveMerges ? 2 + wp : wp];
         int next = 0;
-        if (threadIdx.x == 0) next = atomicAdd(&a.mcur[wave_par(wave)], 1);
+        if (threadIdx.x == 0) next = atomicAdd(cursor, 1);
         for (;;) {
             if (threadIdx.x == 0) s.misc[2] = next;
             __syncthreads();
             const int k = s.misc[2];
             __syncthreads();
-            if (k >= na) break;
-            if (threadIdx.x == 0) next = atomicAdd(&a.mcur[wave_par(wave)], 1);
-            merge_node(a, a.alist[k], wave, s, st_cand);
+            if (k >= nsmall + nbig) break;
+            if (threadIdx.x == 0) next = atomicAdd(cursor, 1);
+            merge_node(a, k < nsmall ? a.alist[k] : a.alist[a.n + (k - nsmall)], wave, s, st_cand);
             ++st_merges;
         }
         if (threadIdx.x == 0 && tr) {
@@ -953,16 +1291,20 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) {
             tr[kTrMerged] = (long long)wall_clock64();
-            tr[kTrTargets] = na;
+            tr[kTrTargets] = na + nbig;
         }
 
         abase += total;
         ++wave;
         ++i_step;
     }
+    if (lane_id() == 0) {
+        atomicAdd((unsigned long long *)&a.out[kOutMerges],
+                  (unsigned long long)(wv_merges + (threadIdx.x == 0 ? st_merges : 0)));
+        atomicAdd((unsigned long long *)&a.out[kOutCandidates],
+                  (unsigned long long)(wv_cand + (threadIdx.x == 0 ? st_cand : 0)));
+    }
     if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&a.out[kOutMerges], (unsigned long long)st_merges);
-        atomicAdd((unsigned long long *)&a.out[kOutCandidates], (unsigned long long)st_cand);
         if (b == 0) {
             a.out[kOutWaves] = wave;
             a.out[kOutLabels] = abase;
@@ -970,6 +1312,12 @@ __global__ void __launch_bounds__(1024) k_search(SearchArgs a) {
         }
     }
 }
+
+// The two builds of the persistent search: with single-wave merges for
+// iterations with many small targets (large batches), and without (the
+// workgroup path only, which the compiler then schedules on its own).
+__global__ void __launch_bounds__(1024) k_search(SearchArgs a) { search_body<false>(a); }
+__global__ void __launch_bounds__(1024) k_search_wave(SearchArgs a) { search_body<true>(a); }
 
 __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
     // front labels X = sum_v |P(v)| and useful relaxations R = sum_v |P(v)| outdeg(v)

@@ -53,7 +53,8 @@ class mpap_search_params(ctypes.Structure):
                 ("radius", ctypes.c_float), ("n_obj", ctypes.c_int32),
                 ("init_node", ctypes.c_int32), ("max_waves", ctypes.c_int32),
                 ("near_scan", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
-                ("heuristic", ctypes.c_int32), ("block_threads", ctypes.c_int32)]
+                ("heuristic", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("wave_min_targets", ctypes.c_int32)]
 
 
 class mpap_stats(ctypes.Structure):
@@ -309,19 +310,20 @@ class Result:
 
 def search_params(beta: float, n_obj: int, radius: float, lam: float = 0.5,
                   init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
-                  stage_cap: int = 0, heuristic: int = 0, block_threads: int = 0):
+                  stage_cap: int = 0, heuristic: int = 0, block_threads: int = 0,
+                  wave_min_targets: int = 0):
     return mpap_search_params(float(beta), float(lam), float(radius), int(n_obj),
                               int(init_node), int(max_waves), int(near_scan), int(stage_cap),
-                              int(heuristic), int(block_threads))
+                              int(heuristic), int(block_threads), int(wave_min_targets))
 
 
 def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float = 0.5,
                 init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
                 stage_cap: int = 0, heuristic: int = 0, stream=None,
-                block_threads: int = 0) -> Result:
+                block_threads: int = 0, wave_min_targets: int = 0) -> Result:
     lib = load()
     sp = search_params(beta, n_obj, radius, lam, init_node, max_waves, near_scan, stage_cap,
-                       heuristic, block_threads)
+                       heuristic, block_threads, wave_min_targets)
     h = ctypes.c_void_p()
     _check(lib.mpap_search(graph.handle, ctypes.byref(sp), _stream(stream), ctypes.byref(h)))
     return Result(h, graph)

@@ -102,6 +102,18 @@ def test_smaller_workgroups_give_the_same_fronts(full3d, threads):
     r2.close()
 
 
+def test_single_wave_merges_full_size(full3d):
+    """Every iteration of the full-size search with single-wave merges for the
+    small fronts: the same fronts."""
+    env, g, dg, res, fronts = full3d
+    r2 = mpap.mpap_search(dg, env.beta, 3, env.radius, env.lam, wave_min_targets=1)
+    assert r2.stats()["front_labels"] == res.stats()["front_labels"]
+    assert np.array_equal(bits(r2.goal_front().vecs), bits(res.goal_front().vecs))
+    for v in range(0, len(fronts), 5):
+        assert np.array_equal(bits(sort_lex(r2.node_front(v))), bits(sort_lex(fronts[v]))), v
+    r2.close()
+
+
 def test_fixpoint_at_sampled_nodes(full3d):
     env, g, dg, res, fronts = full3d
     rp, col = g["row_ptr"], g["col"]

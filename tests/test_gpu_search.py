@@ -155,6 +155,26 @@ def test_workgroup_size_does_not_change_fronts(threads, dim):
     dg.close()
 
 
+@pytest.mark.parametrize("case,stage_cap", [("tiny3", 0), ("2d", 0), ("3d", 0), ("3d", 64),
+                                             ("2d", 128)])
+def test_single_wave_merges(case, stage_cap):
+    """Every iteration merged by single waves (small fronts) and workgroups
+    (large ones, and fronts that outgrow a wave's slice: stage_cap shrinks the
+    slice so that many do) gives the oracle's fronts bit for bit."""
+    if case == "tiny3":
+        g = synth.tiny_random_graph(13, n=200, p_reset=0.2, mean_degree=3.0, integer_costs=True)
+        beta, n_obj, radius = 1.0, 3, 0.25
+    else:
+        env = synth.plain2d(6, n=2000) if case == "2d" else synth.plain3d(3, n=3000)
+        g = ograph.build_graph(env)
+        beta, n_obj, radius = env.beta, env.n_obj, env.radius
+    ref = osearch.search(g, beta, n_obj)
+    dg, res = run(g, beta, n_obj, radius=radius, wave_min_targets=1, stage_cap=stage_cap)
+    check_against_oracle(g, res, ref, beta, n_obj, all_nodes=False, node_stride=2)
+    res.close()
+    dg.close()
+
+
 def test_deterministic(road2d):
     env, g = road2d[2]
     dg = upload(g)
