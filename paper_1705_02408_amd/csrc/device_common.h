@@ -124,26 +124,37 @@ __device__ __forceinline__ float block_min(float v, float *scratch) {
 // launch; every block must call it the same number of times.  The wait is
 // bounded: after `spin_limit` polls the block records `timeout_flag` in
 // *err and proceeds, so a broken launch still terminates.
+//
+// Cache maintenance is done once per workgroup, not once per wave: every wave
+// first waits until its own global stores and atomics are acknowledged by the
+// L2 of its XCD; after the workgroup barrier one thread writes that L2's dirty
+// lines back (agent-scope release), arrives, polls the counter with relaxed
+// loads (which leave the caches alone, so blocks still at work on the same
+// XCD keep their L2 contents) and, once all blocks have arrived, drops stale
+// lines (agent-scope acquire) before the workgroup goes on.  The waves of a
+// workgroup share one CU and its L1, so the one invalidation serves them all.
 __device__ __forceinline__ void grid_barrier(unsigned *counter, unsigned nblocks,
                                              unsigned &epoch, int *err, int timeout_flag,
                                              unsigned long long spin_limit) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt and lgkmcnt all zero
     __syncthreads();
     if (threadIdx.x == 0) {
         epoch += 1u;
         const unsigned target = epoch * nblocks;
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long spins = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > spin_limit) {
                 atomicOr(err, timeout_flag);
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __threadfence();
 }
 
 // float32 -> bfloat16 bits, round to nearest, ties to even (NaN stays NaN)

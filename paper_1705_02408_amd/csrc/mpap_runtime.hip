@@ -743,6 +743,8 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         if (status == kStatusOk && dev_err == 0) break;
         if (dev_err & kErrTimeout)
             return fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)");
+        if (dev_err & kErrTarget)
+            return fail(MPAP_ERR_HIP, "internal error: a queued merge target is not a node");
         if (status == kStatusNoConverge)
             return fail(MPAP_ERR_NOCONVERGE, "max_waves reached with open plans");
         if (++retries > 12) return fail(MPAP_ERR_OVERFLOW, "capacity retries exhausted");

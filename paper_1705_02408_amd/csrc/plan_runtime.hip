@@ -284,6 +284,8 @@ int mpap_plan_run(mpap_plan *p, void *stream, mpap_result **out) {
     const int err = *p->h_err;
     if (err & kErrTimeout)
         return fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)");
+    if (err & kErrTarget)
+        return fail(MPAP_ERR_HIP, "internal error: a queued merge target is not a node");
     if (status == kStatusNoConverge)
         return fail(MPAP_ERR_NOCONVERGE, "max_waves reached with open plans");
     if (status != kStatusOk || err != 0 || *p->h_ovf != 0) {

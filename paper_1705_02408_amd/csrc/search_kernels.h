@@ -13,6 +13,7 @@ constexpr int kStatusArena = 3;       // arena or frontier capacity too small
 constexpr int kErrBucket = 1;   // a front outgrew the LDS staging capacity
 constexpr int kErrPool = 2;     // bucket pool exhausted
 constexpr int kErrTimeout = 4;  // grid barrier wait exceeded its bound
+constexpr int kErrTarget = 8;   // a queued merge target is not a node (internal error)
 
 // device output words
 constexpr int kOutWaves = 0;

@@ -1199,7 +1199,8 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
         before = block_sum_ll(before, red_ll);
         open_nodes = block_sum_ll(open_nodes, red_ll);
         mstep = block_min_ll(mstep, red_ll);
-        const int errv = __hip_atomic_load(a.err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        // (the barrier made the other blocks' writes visible: relaxed loads)
+        const int errv = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (errv != 0) {
             status = kStatusError;
             break;
@@ -1235,7 +1236,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
         }
 
         const unsigned wp = wave_par(wave);
-        const int na = __hip_atomic_load(&a.acnt[wp], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int na = __hip_atomic_load(&a.acnt[wp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const long long m0 = (long long)wall_clock64();
         // many small targets: one wave each; few: the workgroups share them
         // (a single wave is slower per merge, so it pays only when the waves
@@ -1252,7 +1253,9 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                 k = __shfl(k, 0, 64);
                 if (k >= na) break;
                 const int x = a.alist[k];
-                if (wave_merge_node(a, x, wave, W, wv_cand)) {
+                if ((unsigned)x >= (unsigned)a.n) {
+                    if (lane_id() == 0) atomicOr(a.err, kErrTarget);
+                } else if (wave_merge_node(a, x, wave, W, wv_cand)) {
                     ++wv_merges;
                 } else if (lane_id() == 0) {
                     const int kb = atomicAdd(&a.acnt[2 + wp], 1);
@@ -1267,7 +1270,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
         // cost); the next one is claimed while the current one merges
         int nbig = 0, nsmall = na;
         if constexpr (kWaveMerges) {
-            nbig = __hip_atomic_load(&a.acnt[2 + wp], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            nbig = __hip_atomic_load(&a.acnt[2 + wp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (by_wave) nsmall = 0;
         }
         int *const cursor = &a.mcur[kWaveMerges ? 2 + wp : wp];
@@ -1280,8 +1283,13 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
             __syncthreads();
             if (k >= nsmall + nbig) break;
             if (threadIdx.x == 0) next = atomicAdd(cursor, 1);
-            merge_node(a, k < nsmall ? a.alist[k] : a.alist[a.n + (k - nsmall)], wave, s, st_cand);
-            ++st_merges;
+            const int x = k < nsmall ? a.alist[k] : a.alist[a.n + (k - nsmall)];
+            if ((unsigned)x < (unsigned)a.n) {
+                merge_node(a, x, wave, s, st_cand);
+                ++st_merges;
+            } else if (threadIdx.x == 0) {
+                atomicOr(a.err, kErrTarget);
+            }
         }
         if (threadIdx.x == 0 && tr) {
             const long long dm = (long long)wall_clock64() - m0;
