@@ -524,6 +524,9 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
     const int nq = g->nq;
     if (nsp != nq && nsp != 1)
         return fail(MPAP_ERR_INVAL, "need one parameter set per query (or one for all)");
+    // merge-target list regions are indexed in int32
+    if ((long long)g->n * kListRegions > 0x7fffffffll)
+        return fail(MPAP_ERR_INVAL, "graph too large for one search (nodes x 11 >= 2^31)");
     p = SearchPrep{};
     p.nq = nq;
     for (int q = 0; q < nsp; ++q) {
@@ -641,7 +644,7 @@ SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
     a.capB = L.capB; a.capC = L.capC; a.nblocks = L.nblocks;
     a.wcap = L.wcap; a.wslice = L.wslice; a.wmin = L.wmin;
     a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
-    a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark;
+    a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark; a.wt = w->wt;
     a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
     a.arena = w->arena; a.arena_cap = std::min<long long>(w->arena_cap, 0x7ffffff0ll);
     a.part_cnt = w->part_cnt; a.part_open = w->part_open; a.part_step = w->part_step;

@@ -156,6 +156,7 @@ struct Workspace {
     int *gcnt = nullptr;
     int4 *fo = nullptr;
     int *mark = nullptr;
+    int *wt = nullptr;
     int *alist = nullptr;
     int *acnt = nullptr;
     int *mcur = nullptr;
@@ -189,7 +190,7 @@ struct Workspace {
 
     void free_all() {
         dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
-        dfree(mark); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
+        dfree(mark); dfree(wt); dfree(alist); dfree(acnt); dfree(mcur); dfree(F); dfree(arena); dfree(part_cnt);
         dfree(part_open); dfree(part_step); dfree(bar); dfree(err); dfree(out); dfree(wstat);
         dfree(spill); dfree(spill_flags);
         dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count); dfree(g_total);
@@ -213,9 +214,10 @@ inline int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     if ((r = dalloc(&w->gcnt, n))) return r;
     if ((r = dalloc(&w->fo, n))) return r;
     if ((r = dalloc(&w->mark, n))) return r;
-    if ((r = dalloc(&w->alist, 2 * (size_t)n))) return r;
-    if ((r = dalloc(&w->acnt, 4))) return r;
-    if ((r = dalloc(&w->mcur, 4))) return r;
+    if ((r = dalloc(&w->wt, n))) return r;
+    if ((r = dalloc(&w->alist, (size_t)kListRegions * n))) return r;
+    if ((r = dalloc(&w->acnt, 2 * kListRegions))) return r;
+    if ((r = dalloc(&w->mcur, 2 * kListRegions))) return r;
     if ((r = dalloc(&w->part_cnt, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->part_open, 2 * (size_t)nblocks))) return r;
     if ((r = dalloc(&w->part_step, 2 * (size_t)nblocks))) return r;

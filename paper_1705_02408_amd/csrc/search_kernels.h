@@ -15,6 +15,14 @@ constexpr int kErrPool = 2;     // bucket pool exhausted
 constexpr int kErrTimeout = 4;  // grid barrier wait exceeded its bound
 constexpr int kErrTarget = 8;   // a queued merge target is not a node (internal error)
 
+// Merge targets of a workgroup-only launch are ordered by expected work (the
+// children queued to them): class 0 below kWeightClassBase children, class c
+// from kWeightClassBase * 2^(c-1) on, the last class open-ended.  Heavier
+// classes are merged first, so the longest merges of an iteration start early.
+constexpr int kWeightClasses = 10;
+constexpr int kWeightClassBase = 128;
+constexpr int kListRegions = 1 + kWeightClasses;  // target list regions of n entries each
+
 // device output words
 constexpr int kOutWaves = 0;
 constexpr int kOutLabels = 1;
@@ -76,11 +84,15 @@ struct SearchArgs {
     float *minopen;    // per node least cost of an open label (+inf: none)
     int *gcnt;         // per node group size of the current iteration
     int4 *fo;          // per node {frontier offset, count, wave, first open label index}
-    int *mark;         // per node last wave it was queued as merge target
-    int *alist;        // merge targets of the current wave [2n]: fronts of at most wcap
-                       // labels at [0, n) (merged by one wave), larger ones at [n, 2n)
-    int *acnt;         // [4] target counts by wave parity: small [0..1], large [2..3]
-    int *mcur;         // [4] next target to merge, same layout
+    int *mark;         // per node last wave it was queued as merge target (wave build)
+    int *wt;           // per node children queued to it this iteration (workgroup-only
+                       // build; zero between iterations)
+    int *alist;        // merge targets of the current wave, kListRegions regions of n:
+                       // wave build: fronts of at most wcap labels in region 0 (merged
+                       // by one wave), larger ones in region 1; workgroup-only build:
+                       // every target in region 0, then by weight class c in region 1+c
+    int *acnt;         // [2 kListRegions] target count of region r at [2 r + wave parity]
+    int *mcur;         // [2 kListRegions] next target to merge, same layout
     int wcap;          // largest front merged by a single wave (0: none)
     int wmin;          // single-wave merges in iterations with at least wmin small targets
     int wslice;        // LDS bytes of one wave's slice in single-wave merges

@@ -30,6 +30,14 @@ constexpr unsigned long long kSpinLimit = 1ull << 22;
 
 __device__ __forceinline__ unsigned wave_par(int w) { return (unsigned)w & 1u; }
 
+// weight class of a merge target with w children queued (see kWeightClasses)
+__device__ __forceinline__ int weight_class(int w) {
+    static_assert((kWeightClassBase & (kWeightClassBase - 1)) == 0, "power of two");
+    if (w < kWeightClassBase) return 0;
+    const int c = 1 + (31 - __clz(w)) - (31 - __clz(kWeightClassBase));
+    return min(c, kWeightClasses - 1);
+}
+
 // query owning global node v: last q with qoff[q] <= v
 __device__ __forceinline__ int query_of(const SearchArgs &a, int v) {
     int lo = 0, hi = a.nq - 1;
@@ -194,8 +202,13 @@ __device__ void phase_select(const SearchArgs &a, long long istep, int wave, lon
                 bool fresh = false, big = false;
                 if (e < a.optr[vv + 1]) {
                     x = a.ocol[e];
-                    fresh = atomicExch(&a.mark[x], wave) != wave;
-                    if (kSplit && fresh) big = a.nb[x].z > a.wcap;
+                    if constexpr (kSplit) {
+                        fresh = atomicExch(&a.mark[x], wave) != wave;
+                        if (fresh) big = a.nb[x].z > a.wcap;
+                    } else {
+                        // the weight (children queued) starts at zero each iteration
+                        fresh = atomicAdd(&a.wt[x], max(run, 1)) == 0;
+                    }
                 }
                 const uint64_t fs = ballot64(fresh && !big), fb = ballot64(fresh && big);
                 if (fs) {
@@ -1079,10 +1092,11 @@ __global__ void __launch_bounds__(256) k_search_init(SearchArgs a) {
         a.gcnt[v] = 0;
         a.fo[v] = make_int4(0, 0, -1, 0);
         a.mark[v] = -1;
+        a.wt[v] = 0;
     }
     if (v == 0) {
         *a.pool_top = 16u * (unsigned)a.nq;
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 2 * kListRegions; ++i) {
             a.acnt[i] = 0;
             a.mcur[i] = 0;
         }
@@ -1174,10 +1188,10 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
         long long* tr = (wave < a.wstat_cap) ? a.wstat + (size_t)wave * kTraceWords : nullptr;
         if (tr0 && tr) tr[kTrStart] = (long long)wall_clock64();
         if (threadIdx.x == 0 && b == 0) {
-            a.acnt[wave_par(wave)] = 0;
-            a.mcur[wave_par(wave)] = 0;
-            a.acnt[2 + wave_par(wave)] = 0;
-            a.mcur[2 + wave_par(wave)] = 0;
+            for (int r = 0; r < (kWaveMerges ? 2 : kListRegions); ++r) {
+                a.acnt[2 * r + wave_par(wave)] = 0;
+                a.mcur[2 * r + wave_par(wave)] = 0;
+            }
         }
         phase_count(a, i_step, par, lo, hi, s.u_idx, s.scan, red_ll);
         if (tr0 && tr) tr[kTrCountDone] = (long long)wall_clock64();
@@ -1265,25 +1279,79 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
             __syncthreads();  // the slices are the workgroup's LDS again
             grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         }
-        // one workgroup per target: the large fronts (and the small ones when
-        // no wave took them), taken dynamically (merges differ widely in
-        // cost); the next one is claimed while the current one merges
+        if constexpr (!kWaveMerges) {
+            // weight classes: every target once, by the children queued to it
+            // (final after the select barrier; cleared here for the next
+            // iteration), appended to its class region (one reservation per
+            // class present in a wave)
+            const int l = lane_id();
+            for (int k0 = b * (int)blockDim.x; k0 < na; k0 += (int)(G * blockDim.x)) {
+                const int k = k0 + threadIdx.x;
+                int c = -1, x = 0;
+                if (k < na) {
+                    x = a.alist[k];
+                    if ((unsigned)x < (unsigned)a.n) {
+                        c = weight_class(a.wt[x]);
+                        a.wt[x] = 0;
+                    } else {
+                        atomicOr(a.err, kErrTarget);
+                    }
+                }
+                uint64_t todo = ballot64(c >= 0);
+                while (todo) {
+                    const int lead = (int)__ffsll((unsigned long long)todo) - 1;
+                    const int cl = __shfl(c, lead, 64);
+                    const uint64_t same = ballot64(c == cl);
+                    int base = 0;
+                    if (l == lead) base = atomicAdd(&a.acnt[2 * (1 + cl) + wp], (int)__popcll(same));
+                    base = __shfl(base, lead, 64);
+                    if (c == cl) a.alist[(1 + cl) * a.n + base + lanes_below(same)] = x;
+                    todo &= ~same;
+                }
+            }
+            grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
+        }
+        // one workgroup per target, taken dynamically (merges differ widely in
+        // cost); the next one is claimed while the current one merges.  Wave
+        // build: the large fronts (and the small ones when no wave took them);
+        // workgroup-only build: the heaviest weight class first
         int nbig = 0, nsmall = na;
         if constexpr (kWaveMerges) {
             nbig = __hip_atomic_load(&a.acnt[2 + wp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (by_wave) nsmall = 0;
         }
         int *const cursor = &a.mcur[kWaveMerges ? 2 + wp : wp];
-        int next = 0;
-        if (threadIdx.x == 0) next = atomicAdd(cursor, 1);
+        // thread 0's walk over the class regions (claims only grow)
+        int cls = kWeightClasses - 1, cbase = 0, ccnt = 0;
+        if (!kWaveMerges && threadIdx.x == 0)
+            ccnt = __hip_atomic_load(&a.acnt[2 * (1 + cls) + wp], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        // list index of the k-th claim, -1 when none is left
+        auto locate = [&](int k) -> int {
+            if constexpr (kWaveMerges) {
+                return k;  // resolved below
+            } else {
+                if (k >= na) return -1;
+                while (cls > 0 && k >= cbase + ccnt) {
+                    cbase += ccnt;
+                    --cls;
+                    ccnt = __hip_atomic_load(&a.acnt[2 * (1 + cls) + wp], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+                }
+                return k < cbase + ccnt ? (1 + cls) * a.n + (k - cbase) : -1;
+            }
+        };
+        int next = -1;
+        if (threadIdx.x == 0) next = locate(atomicAdd(cursor, 1));
         for (;;) {
             if (threadIdx.x == 0) s.misc[2] = next;
             __syncthreads();
-            const int k = s.misc[2];
+            const int idx = s.misc[2];
             __syncthreads();
-            if (k >= nsmall + nbig) break;
-            if (threadIdx.x == 0) next = atomicAdd(cursor, 1);
-            const int x = k < nsmall ? a.alist[k] : a.alist[a.n + (k - nsmall)];
+            if (kWaveMerges ? idx >= nsmall + nbig : idx < 0) break;
+            if (threadIdx.x == 0) next = locate(atomicAdd(cursor, 1));
+            const int x = kWaveMerges ? (idx < nsmall ? a.alist[idx] : a.alist[a.n + (idx - nsmall)])
+                                      : a.alist[idx];
             if ((unsigned)x < (unsigned)a.n) {
                 merge_node(a, x, wave, s, st_cand);
                 ++st_merges;
