@@ -403,6 +403,7 @@ __device__ __forceinline__ float block_excl_min(float v, float *scratch) {
 }
 
 constexpr int kPairMax = 256;  // survivors handled by the all-pairs step
+constexpr int kChunkFill = 192; // candidates gathered before a chunk is merged
 
 // claims a slot for each lane with keep set, at *counter (LDS), one atomic per
 // wave; the slots of one call are dense but in no particular order
@@ -423,38 +424,46 @@ __device__ __forceinline__ void wave_append(bool keep, int *counter, int &slot) 
 // lo: lowered to the first index of B this merge changes (labels below it
 // keep their places).  The append counters misc[6] and misc[7] must be zero
 // on entry.
+// 1. First bucket test of candidate q against the front B[0..nB).  Two
+// objectives: the last label of cost <= q.c decides.  Three: the near_scan
+// labels just below q's cost are tested; `stop` is the end of the bucket
+// prefix still to scan (0: decided).
+__device__ __forceinline__ bool near_dead(const float4 *B, int nB, const float4 &q, int near_scan,
+                                          bool three, int &stop) {
+    const int k = upper_c(B, nB, q.x);
+    stop = 0;
+    if (!three) return k > 0 && B[k - 1].y <= q.y;
+    const int st = max(0, k - near_scan);
+    bool dead = false;
+    for (int j = k - 1; j >= st && !dead; --j) dead = dm_le(B[j], q);
+    if (!dead) stop = st;
+    return dead;
+}
+
+// `prescanned`: the candidates have passed the first test already (none
+// dead, the undecided ones listed in u_idx[0..misc[6]) with their u_end).
 __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan, bool three,
-                            int &lo, int *err) {
+                            int &lo, int *err, bool prescanned) {
     const int bd = blockDim.x;
-    if (!three) {
-        // 1. the last bucket label of cost <= q.c decides
-        for (int i = threadIdx.x; i < nC; i += bd) {
-            const float4 q = s.C[i];
-            const int k = upper_c(s.B, nB, q.x);
-            s.cdead[i] = (k > 0 && s.B[k - 1].y <= q.y) ? 1 : 0;
-        }
-        __syncthreads();
-    } else {
-        // 1. near scan: the labels just below the candidate's cost; 2. list
-        // the undecided candidates (bucket prefix left to scan)
+    if (!prescanned) {
+        // 1. first test; 2. list the undecided candidates
         for (int t0 = 0; t0 < nC; t0 += bd) {
             const int i = t0 + threadIdx.x;
             bool und = false;
             if (i < nC) {
-                const float4 q = s.C[i];
-                const int k = upper_c(s.B, nB, q.x);
-                const int stop = max(0, k - near_scan);
-                bool dead = false;
-                for (int j = k - 1; j >= stop && !dead; --j) dead = dm_le(s.B[j], q);
+                int stop;
+                const bool dead = near_dead(s.B, nB, s.C[i], near_scan, three, stop);
                 s.cdead[i] = dead ? 1 : 0;
-                s.u_end[i] = dead ? 0 : stop;
-                und = !dead && stop > 0;
+                s.u_end[i] = stop;
+                und = stop > 0;
             }
             int slot;
             wave_append(und, &s.misc[6], slot);
             if (und) s.u_idx[slot] = i;
         }
         __syncthreads();
+    }
+    if (three) {
         const int nU = s.misc[6];
         // 3. the rest of the prefix, gs threads per candidate, by segments
         if (nU > 0) {
@@ -953,6 +962,31 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
     const float *edrift = a.qheur[q] ? a.sdrift : a.rdrift;
     const int e0 = a.rptr[x], e1 = a.rptr[x + 1];
     bool changed = false;
+    // Children are made in rounds of up to one per thread and given the first
+    // bucket test at once; those it does not kill gather in C (any order)
+    // across rounds and in-edge tiles until C holds kChunkFill of them, then
+    // the chunk is merged.  Testing against the front as it was before the
+    // last chunk went in is sound: a label removed since is dominated by one
+    // that stayed, which then dominates the child too.
+    if (threadIdx.x == 0) {
+        s.misc[4] = 0;  // children within the bound
+        s.misc[5] = 0;  // candidates kept
+        s.misc[6] = 0;  // undecided after the first test
+        s.misc[7] = 0;  // survivors of the bucket test
+    }
+    __syncthreads();
+    int nC = 0;  // kept so far (from the barrier counts: the same in every thread)
+    auto flush = [&]() {
+        merge_chunk(s, nB, nC, a.capB, a.near_scan, three, lo, a.err, true);
+        changed = true;
+        nC = 0;
+        if (threadIdx.x == 0) {
+            s.misc[5] = 0;
+            s.misc[6] = 0;
+            s.misc[7] = 0;
+        }
+        __syncthreads();
+    };
     for (int t0 = e0; t0 < e1; t0 += blockDim.x) {
         // in-edge tile: frontier label counts of each in-neighbour
         const int e = t0 + threadIdx.x;
@@ -976,20 +1010,19 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
         s.e_d[threadIdx.x] = de;
         __syncthreads();
         const int ntile = min((int)blockDim.x, e1 - t0);
-        for (int j0 = 0; j0 < tot; j0 += a.capC) {
-            // children j0 .. j0+capC-1 of this tile, those within the bound,
-            // appended in any order (every later step is order-free)
-            if (threadIdx.x == 0) {
-                s.misc[5] = 0;  // candidates
-                s.misc[6] = 0;  // undecided after the near scan
-                s.misc[7] = 0;  // survivors of the bucket test
+        for (int j0 = 0; j0 < tot;) {
+            if (nC >= kChunkFill) {
+                flush();
+                continue;
             }
-            __syncthreads();
-            for (int jr = j0; jr < min(tot, j0 + a.capC); jr += blockDim.x) {
-                const int j = jr + threadIdx.x;
-                bool ok = false;
+            // children j0 .. j0+cnt-1 of this tile (C has room for all)
+            const int cnt = min(min((int)blockDim.x, a.capC - nC), tot - j0);
+            {
+                const int j = j0 + threadIdx.x;
+                bool ok = false, keep = false;
+                int stop = 0;
                 float4 ch = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (j < min(tot, j0 + a.capC)) {
+                if (j < j0 + cnt) {
                     // in-edge t: first with inclusive prefix > j
                     int lo2 = 0, hi2 = ntile - 1;
                     while (lo2 < hi2) {
@@ -1006,23 +1039,28 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                     const float m2 = three ? fmaxf(P.z, dpre) : 0.0f;
                     const unsigned meta = MPAP_OPEN_BIT | (unsigned)(__float_as_int(P.w) + 1);
                     ch = make_float4(c2, d2, m2, __uint_as_float(meta));
+                    if (ok) keep = !near_dead(s.B, nB, ch, a.near_scan, three, stop);
                 }
                 int slot;
-                wave_append(ok, &s.misc[5], slot);
-                if (ok) s.C[slot] = ch;
+                wave_append(keep, &s.misc[5], slot);
+                if (keep) {
+                    s.C[slot] = ch;
+                    s.cdead[slot] = 0;
+                    s.u_end[slot] = stop;
+                }
+                int us;
+                wave_append(stop > 0, &s.misc[6], us);
+                if (stop > 0) s.u_idx[us] = slot;
+                const uint64_t okm = ballot64(ok);
+                if (lane_id() == 0 && okm) atomicAdd(&s.misc[4], (int)__popcll(okm));
+                nC += __syncthreads_count(keep);
             }
-            __syncthreads();
-            const int nC = s.misc[5];
-            st_cand += nC;
-            if (nC > 0) {
-                const int before = nB;
-                merge_chunk(s, nB, nC, a.capB, a.near_scan, three, lo, a.err);
-                changed = true;
-                (void)before;
-            }
+            j0 += cnt;
         }
         __syncthreads();
     }
+    if (nC > 0) flush();
+    st_cand += s.misc[4];  // every append precedes the last barrier
     if (!changed) return;
     // write the merged front back (fresh region if it outgrew the old one)
     int off = nbx.x, cap = nbx.y;
@@ -1444,7 +1482,7 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
                     s.misc[7] = 0;
                 }
                 __syncthreads();
-                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, glo, a.err);
+                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, glo, a.err, false);
             }
         }
         const long long o = g.lab_off[q];
