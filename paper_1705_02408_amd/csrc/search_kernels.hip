@@ -270,6 +270,7 @@ struct MergeLds {
     float *segd;    // [segcap] per 64-label segment: least d
     float *segm;    // [segcap] per 64-label segment: least m
     int segcap;
+    int capC;
 };
 
 
@@ -402,7 +403,7 @@ __device__ __forceinline__ float block_excl_min(float v, float *scratch) {
     return fminf(before, ex);
 }
 
-constexpr int kPairMax = 256;  // survivors handled by the all-pairs step
+constexpr int kPairMax = 256;  // survivors handled by the all-pairs step (at most capC / 2)
 constexpr int kChunkFill = 192; // candidates gathered before a chunk is merged
 
 // claims a slot for each lane with keep set, at *counter (LDS), one atomic per
@@ -486,20 +487,22 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     }
     // 4. survivors of the bucket test, gathered (any order) into tmp (the
     // undecided-scan space, free now) while they fit the all-pairs step
-    float4 *tmp = reinterpret_cast<float4 *>(s.u_end);  // capC / 4 >= kPairMax labels
+    // (u_idx and u_end, adjacent: capC / 2 labels)
+    float4 *tmp = reinterpret_cast<float4 *>(s.u_idx);
+    const int pair_max = min(min(kPairMax, s.capC / 2), bd);  // one thread or more each
     for (int t0 = 0; t0 < nC; t0 += bd) {
         const int i = t0 + threadIdx.x;
         const bool alive = i < nC && !s.cdead[i];
         int slot;
         wave_append(alive, &s.misc[7], slot);
-        if (alive && slot < kPairMax) tmp[slot] = s.C[i];
+        if (alive && slot < pair_max) tmp[slot] = s.C[i];
     }
     __syncthreads();
     const int nS = s.misc[7];
     if (nS == 0) return;
     int nS2;
-    if (nS <= kPairMax) {
-        // 4-5 for up to kPairMax survivors, all pairs at once: g threads per
+    if (nS <= pair_max) {
+        // 4-5 for up to pair_max survivors, all pairs at once: g threads per
         // survivor, each over a slice of the others.  A survivor dies if a
         // lexicographically smaller one dominates it; its rank among the
         // living ones is its place in the sorted run.
@@ -509,19 +512,35 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         const bool mine = i < nS;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         bool dead = false;
+        // (four independent LDS reads in flight per step)
         if (mine) {
             v = tmp[i];
-            for (int j = sub; j < nS; j += g) {
+            int j = sub;
+            for (; j + 3 * g < nS; j += 4 * g) {
+                const float4 o0 = tmp[j], o1 = tmp[j + g], o2 = tmp[j + 2 * g], o3 = tmp[j + 3 * g];
+                dead |= (lex_lt(o0, v) && dm_le(o0, v)) | (lex_lt(o1, v) && dm_le(o1, v)) |
+                        (lex_lt(o2, v) && dm_le(o2, v)) | (lex_lt(o3, v) && dm_le(o3, v));
+            }
+            for (; j < nS; j += g) {
                 const float4 o = tmp[j];
-                dead = dead || (lex_lt(o, v) && dm_le(o, v));
+                dead |= lex_lt(o, v) && dm_le(o, v);
             }
         }
         for (int o = 1; o < g; o <<= 1) dead = __shfl_xor((int)dead, o, 64) != 0 || dead;
         if (mine && sub == 0) s.cdead[i] = dead ? 1 : 0;
         __syncthreads();
         int pos = 0;
-        if (mine && !dead)
-            for (int j = sub; j < nS; j += g) pos += (!s.cdead[j] && lex_lt(tmp[j], v)) ? 1 : 0;
+        if (mine && !dead) {
+            int j = sub;
+            for (; j + 3 * g < nS; j += 4 * g) {
+                const float4 o0 = tmp[j], o1 = tmp[j + g], o2 = tmp[j + 2 * g], o3 = tmp[j + 3 * g];
+                const int d0 = s.cdead[j], d1 = s.cdead[j + g], d2 = s.cdead[j + 2 * g],
+                          d3 = s.cdead[j + 3 * g];
+                pos += (!d0 && lex_lt(o0, v)) + (!d1 && lex_lt(o1, v)) + (!d2 && lex_lt(o2, v)) +
+                       (!d3 && lex_lt(o3, v));
+            }
+            for (; j < nS; j += g) pos += (!s.cdead[j] && lex_lt(tmp[j], v)) ? 1 : 0;
+        }
         for (int o = 1; o < g; o <<= 1) pos += __shfl_xor(pos, o, 64);
         const bool lead = mine && sub == 0 && !dead;
         if (lead) s.C[pos] = v;  // tmp is the input, C the sorted output
@@ -1182,6 +1201,7 @@ __device__ void carve_lds(unsigned char *lds, const SearchArgs &a, MergeLds &s) 
     s.misc = reinterpret_cast<int *>(p);
     p += sizeof(int) * 8;
     s.segcap = max(a.capB, a.capC) / 64 + 2;
+    s.capC = a.capC;
     s.segd = reinterpret_cast<float *>(p);
     p += sizeof(float) * s.segcap;
     s.segm = reinterpret_cast<float *>(p);
