@@ -9,7 +9,7 @@ import pytest
 
 from oracle import checks, graph as ograph, search as osearch
 from paper_1705_02408_amd import synth
-from tests.graphs import as_vecs, load_golden
+from tests.graphs import as_vecs, from_edges, load_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -310,5 +310,57 @@ def test_fronts_beyond_the_lds_stage_spill_exactly(road2d, stage_cap):
     res = mpap.mpap_search(dg, env.beta, 2, env.radius, env.lam, stage_cap=stage_cap)
     assert res.stats()["max_front"] > stage_cap
     check_against_oracle(g, res, ref, env.beta, 2, all_nodes=False, node_stride=2)
+    res.close()
+    dg.close()
+
+
+# ------------------------------------------------------------ high in-degree
+def hub_graph(seed, n_b=10, n_a=40, n_spoke=1500, fan=6, p_reset=0.1):
+    """root -> B layer -> A layer (all pairs) -> spokes (fan random A parents
+    each) -> one hub -> goal.  The hub's in-degree (n_spoke) spans several
+    in-edge tiles; with a huge group factor every spoke label reaches the hub
+    in one iteration (thousands of children: many candidate rounds and
+    chunks in one merge)."""
+    rng = np.random.default_rng(seed)
+    B = list(range(1, 1 + n_b))
+    A = list(range(1 + n_b, 1 + n_b + n_a))
+    S = list(range(1 + n_b + n_a, 1 + n_b + n_a + n_spoke))
+    hub = S[-1] + 1
+    goal = hub + 1
+    n = goal + 1
+    edges = []
+
+    def edge(u, v):
+        edges.append((u, v, float(rng.uniform(0.01, 1.0)), float(rng.uniform(0.0, 0.2))))
+
+    for b in B:
+        edge(0, b)
+    for b in B:
+        for a in A:
+            edge(b, a)
+    for s in S:
+        for a in rng.choice(A, fan, replace=False):
+            edge(int(a), s)
+    for s in S:
+        edge(s, hub)
+    edge(hub, goal)
+    reset = rng.random(n) < p_reset
+    reset[0] = False
+    goal_mask = np.zeros(n, dtype=np.uint8)
+    goal_mask[goal] = 1
+    return from_edges(n, edges, reset, goal_mask), hub
+
+
+@pytest.mark.parametrize("n_obj,threads,lam", [(3, 256, 1e6), (3, 1024, 1e6), (2, 256, 1e6),
+                                               (3, 1024, 0.5)])
+def test_hub_with_many_in_edge_tiles(n_obj, threads, lam):
+    g, hub = hub_graph(7)
+    assert g["col"].tolist().count(hub) > 1024
+    beta = 0.5
+    ref = osearch.search(g, beta, n_obj)
+    dg, res = run(g, beta, n_obj, radius=0.5, lam=lam, block_threads=threads)
+    st = check_against_oracle(g, res, ref, beta, n_obj)
+    print(f"hub n_obj {n_obj} threads {threads}: X {st['front_labels']}, hub front "
+          f"{res.node_front(hub).shape[0]}, candidates {st['candidates']}", flush=True)
     res.close()
     dg.close()
