@@ -443,6 +443,10 @@ __device__ __forceinline__ bool near_dead(const float4 *B, int nB, const float4 
 
 // `prescanned`: the candidates have passed the first test already (none
 // dead, the undecided ones listed in u_idx[0..misc[6]) with their u_end).
+// kWide: the all-pairs survivor step keeps four reads in flight (more
+// registers; the wave-first build, whose single-wave merges share the
+// kernel, keeps one).
+template <bool kWide>
 __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan, bool three,
                             int &lo, int *err, bool prescanned) {
     const int bd = blockDim.x;
@@ -516,6 +520,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         if (mine) {
             v = tmp[i];
             int j = sub;
+            if constexpr (kWide)
             for (; j + 3 * g < nS; j += 4 * g) {
                 const float4 o0 = tmp[j], o1 = tmp[j + g], o2 = tmp[j + 2 * g], o3 = tmp[j + 3 * g];
                 dead |= (lex_lt(o0, v) && dm_le(o0, v)) | (lex_lt(o1, v) && dm_le(o1, v)) |
@@ -532,6 +537,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         int pos = 0;
         if (mine && !dead) {
             int j = sub;
+            if constexpr (kWide)
             for (; j + 3 * g < nS; j += 4 * g) {
                 const float4 o0 = tmp[j], o1 = tmp[j + g], o2 = tmp[j + 2 * g], o3 = tmp[j + 3 * g];
                 const int d0 = s.cdead[j], d1 = s.cdead[j + g], d2 = s.cdead[j + 2 * g],
@@ -968,6 +974,7 @@ __device__ bool stage_front(const SearchArgs &a, MergeLds &s, const int4 &nbv) {
     return true;
 }
 
+template <bool kWide>
 __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                            long long &st_cand) {
     const int4 nbx = a.nb[x];
@@ -996,7 +1003,7 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
     __syncthreads();
     int nC = 0;  // kept so far (from the barrier counts: the same in every thread)
     auto flush = [&]() {
-        merge_chunk(s, nB, nC, a.capB, a.near_scan, three, lo, a.err, true);
+        merge_chunk<kWide>(s, nB, nC, a.capB, a.near_scan, three, lo, a.err, true);
         changed = true;
         nC = 0;
         if (threadIdx.x == 0) {
@@ -1411,7 +1418,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
             const int x = kWaveMerges ? (idx < nsmall ? a.alist[idx] : a.alist[a.n + (idx - nsmall)])
                                       : a.alist[idx];
             if ((unsigned)x < (unsigned)a.n) {
-                merge_node(a, x, wave, s, st_cand);
+                merge_node<!kWaveMerges>(a, x, wave, s, st_cand);
                 ++st_merges;
             } else if (threadIdx.x == 0) {
                 atomicOr(a.err, kErrTarget);
@@ -1502,7 +1509,8 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
                     s.misc[7] = 0;
                 }
                 __syncthreads();
-                merge_chunk(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, glo, a.err, false);
+                merge_chunk<false>(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, glo, a.err,
+                                   false);
             }
         }
         const long long o = g.lab_off[q];
