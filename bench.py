@@ -92,7 +92,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the search of one "
-                                   "roadmap is not sharded across GPUs (see DESIGN.md)",
+                                   "roadmap is not sharded across GPUs",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
