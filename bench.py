@@ -397,7 +397,8 @@ def measure_batch(args, log, with_surrogate: bool = True):
                    "waves": stats[-1]["waves"], "kernel_ms_mean": k_ms,
                    "max_front": stats[-1]["max_front"], "nodes": info["n"], "edges": info["e"]},
         "roofline": {"bound": "hbm", "achieved": B / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": B / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "unit": "GB/s", "frac": B / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "kernel": "k_search_wave" if stats[-1]["wave_build"] else "k_search"},
         "autotune": {"lambda": choice.lam, "near_scan": choice.near_scan},
         "plan": plan.info(),
     })
@@ -443,7 +444,7 @@ def run_batch(args):
         "config": {"workload": f"batch of {b['queries']} queries, 2D/3D even odds, sizes "
                                f"log-uniform 2000-50000 samples, two objectives",
                    "queries_per_step": b["queries"], "parallelism": "single GPU"},
-        "batched_serving": b, "roofline": dict(b["roofline"], traffic=None, kernel="k_search"),
+        "batched_serving": b, "roofline": dict(b["roofline"], traffic=None),
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

@@ -256,6 +256,8 @@ typedef struct {
     int32_t lds_front_cap;    /* largest per-node front the LDS merge stages */
     int32_t blocks;           /* workgroups of the persistent launch */
     int32_t max_front;        /* largest final per-node front */
+    int32_t wave_build;       /* 1: the wave-first kernel build ran (single-wave merges in
+                                 iterations with many small targets), 0: the weight-ordered one */
 } mpap_stats;
 
 int mpap_result_stats(const mpap_result *r, mpap_stats *out);

@@ -692,6 +692,7 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
     res->stats.lds_front_cap = L.capB;
     res->stats.max_front = (int32_t)dev_out[kOutMaxFront];
     res->stats.blocks = L.nblocks;
+    res->stats.wave_build = search_kernel_for(L, g->n) == reinterpret_cast<const void *>(k_search_wave);
     res->stats.gpu_ms = ms;
     // per-query latency from the per-wave device clock (100 MHz)
     const int tw = std::min<int>(res->stats.waves, kTraceCap);

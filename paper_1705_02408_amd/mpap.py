@@ -63,7 +63,7 @@ class mpap_stats(ctypes.Structure):
                 ("merges", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("relaxations", ctypes.c_int64), ("gpu_ms", ctypes.c_float),
                 ("lds_front_cap", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("max_front", ctypes.c_int32)]
+                ("max_front", ctypes.c_int32), ("wave_build", ctypes.c_int32)]
 
 
 SYMBOLS = [

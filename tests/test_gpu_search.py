@@ -150,6 +150,7 @@ def test_workgroup_size_does_not_change_fronts(threads, dim):
     ref = osearch.search(g, env.beta, env.n_obj)
     dg, res = run(g, env.beta, env.n_obj, radius=env.radius, block_threads=threads)
     assert res.stats()["blocks"] == 256 * (1024 // threads)
+    assert res.stats()["wave_build"] == 0
     check_against_oracle(g, res, ref, env.beta, env.n_obj, all_nodes=False, node_stride=2)
     res.close()
     dg.close()
@@ -170,6 +171,7 @@ def test_single_wave_merges(case, stage_cap):
         beta, n_obj, radius = env.beta, env.n_obj, env.radius
     ref = osearch.search(g, beta, n_obj)
     dg, res = run(g, beta, n_obj, radius=radius, wave_min_targets=1, stage_cap=stage_cap)
+    assert res.stats()["wave_build"] == 1
     check_against_oracle(g, res, ref, beta, n_obj, all_nodes=False, node_stride=2)
     res.close()
     dg.close()
