@@ -366,3 +366,69 @@ def test_hub_with_many_in_edge_tiles(n_obj, threads, lam):
           f"{res.node_front(hub).shape[0]}, candidates {st['candidates']}", flush=True)
     res.close()
     dg.close()
+
+
+# ------------------------------------------------------------ closed forms
+# The device search checked directly against closed forms (no oracle search):
+# Dijkstra on float32 sums is exact for the additive objectives.
+@pytest.fixture(scope="module")
+def road2d_small():
+    env = synth.plain2d(4, n=2000)
+    return env, ograph.build_graph(env)
+
+
+@pytest.mark.parametrize("n_obj", [2, 3])
+def test_relocalising_everywhere_leaves_one_label_per_node(road2d_small, n_obj):
+    """Zero drift and a reset at every node: each front is the single vector
+    (shortest-path cost, 0[, 0])."""
+    _, g = road2d_small
+    g1 = dict(g)
+    g1["drift"] = np.zeros_like(g["drift"])
+    g1["reset"] = np.ones_like(g["reset"])
+    dist = checks.dijkstra(g1, g1["cost"])
+    dg, res = run(g1, 0.3, n_obj, radius=0.05)
+    for v in range(0, g1["goal"].shape[0], 3):
+        f = res.node_front(v)
+        if not np.isfinite(dist[v]):
+            assert f.shape[0] == 0
+            continue
+        assert f.shape[0] == 1, v
+        assert bits(f[0]).tolist() == bits([dist[v], 0.0, 0.0]).tolist(), v
+    res.close()
+    dg.close()
+
+
+def test_drift_equal_to_cost_gives_diagonal_fronts(road2d_small):
+    """Drift = cost on every edge, no reset: each front is (dist, dist)."""
+    _, g = road2d_small
+    g1 = dict(g)
+    g1["drift"] = g["cost"].copy()
+    g1["reset"] = np.zeros_like(g["reset"])
+    dist = checks.dijkstra(g1, g1["cost"])
+    dg, res = run(g1, np.inf, 2, radius=0.05)
+    for v in range(0, g1["goal"].shape[0], 3):
+        f = res.node_front(v)
+        if np.isfinite(dist[v]):
+            assert f.shape[0] == 1, v
+            assert bits(f[0, :2]).tolist() == bits([dist[v], dist[v]]).tolist(), v
+    res.close()
+    dg.close()
+
+
+def test_front_ends_are_shortest_paths(road2d_small):
+    """With no bound and no resets, each front's least cost is the Dijkstra
+    distance on cost and its least drift the Dijkstra distance on drift."""
+    _, g = road2d_small
+    g0 = dict(g)
+    g0["reset"] = np.zeros_like(g["reset"])
+    dc = checks.dijkstra(g0, g0["cost"])
+    dd = checks.dijkstra(g0, g0["drift"])
+    dg, res = run(g0, np.inf, 2, radius=0.05)
+    for v in range(0, g0["goal"].shape[0], 3):
+        f = res.node_front(v)
+        if np.isfinite(dc[v]):
+            assert f.shape[0] >= 1
+            assert bits([f[:, 0].min()]).tolist() == bits([dc[v]]).tolist(), v
+            assert bits([f[:, 1].min()]).tolist() == bits([dd[v]]).tolist(), v
+    res.close()
+    dg.close()
