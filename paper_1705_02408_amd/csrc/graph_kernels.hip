@@ -280,9 +280,11 @@ __global__ void __launch_bounds__(256) k_zero_i32(int *p, long long n) {
 // Inputs of the learned drift surrogate for edge row u -> col[e], from the
 // id-ordered pair (a, b) so both directions agree: x_a (3), x_b (3, zero z in
 // 2D), the length, q at the 8 segment points (k + 1/2)/8, q(x_b); bfloat16.
-__global__ void __launch_bounds__(64) k_edge_features(BuildArgs g, int n, const int *row_ptr,
-                                                      const int *col, const float *cost,
-                                                      uint16_t *X, float *base) {
+// One thread per edge (its source found by a binary search of row_ptr), so
+// every lane has an edge whatever the node degrees.
+__global__ void __launch_bounds__(256) k_edge_features(BuildArgs g, int n, const int *row_ptr,
+                                                       const int *col, const float *cost,
+                                                       uint16_t *X, float *base) {
     extern __shared__ float blob[];
     for (int i = threadIdx.x; i < g.nblob * g.dim; i += blockDim.x) blob[i] = g.mu[i];
     for (int i = threadIdx.x; i < g.nblob; i += blockDim.x) {
@@ -294,9 +296,16 @@ __global__ void __launch_bounds__(64) k_edge_features(BuildArgs g, int n, const 
     gl.mu = blob;
     gl.sig = blob + g.nblob * g.dim;
     gl.amp = blob + g.nblob * g.dim + g.nblob;
-    const int u = blockIdx.x;
-    if (u >= n) return;
-    for (int e = row_ptr[u] + threadIdx.x; e < row_ptr[u + 1]; e += blockDim.x) {
+    const int m = row_ptr[n];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    int lo = 0, hi = n - 1;  // source u: last row with row_ptr[u] <= e
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int u = lo;
+    {
         const int v = col[e];
         const int a = min(u, v), b = max(u, v);
         float xa[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};

@@ -140,8 +140,9 @@ int enqueue_features(mpap_graph *g, hipStream_t st) {
         a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
         a.reset_q = g->reset_q;
         const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
-        k_edge_features<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->feat,
-                                               g->sbase);
+        if (g->e > 0)
+            k_edge_features<<<div_up(g->e, 256), 256, lds, st>>>(a, g->n, g->optr, g->ocol,
+                                                                 g->ocost, g->feat, g->sbase);
     }
     HIP_TRY(hipGetLastError());
     return MPAP_OK;
