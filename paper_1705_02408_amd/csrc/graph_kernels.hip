@@ -157,9 +157,17 @@ __global__ void __launch_bounds__(256) k_edge_drift(BuildArgs g, int n, const in
     gl.mu = blob;
     gl.sig = blob + g.nblob * g.dim;
     gl.amp = blob + g.nblob * g.dim + g.nblob;
-    const int u = blockIdx.x;  // one block per row, threads over the row's edges
-    if (u >= n) return;
-    for (int e = row_ptr[u] + threadIdx.x; e < row_ptr[u + 1]; e += blockDim.x) {
+    // one thread per edge; its source u: last row with row_ptr[u] <= e
+    const int m = row_ptr[n];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int u = lo;
+    {
         const int v = col[e];
         const int a = min(u, v), b = max(u, v);
         float xa[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};

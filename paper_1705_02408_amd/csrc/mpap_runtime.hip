@@ -358,7 +358,9 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
     k_row_ptr<<<div_up(n + 1, 256), 256, 0, s>>>(n, m, coff, kscan, keep, g->optr);
     {
         const size_t lds = sizeof(float) * (nf_ * dim + 2 * nf_);
-        if (n > 0) k_edge_drift<<<n, 64, lds, s>>>(a, n, g->optr, g->ocol, g->ocost, g->odrift);
+        if (n > 0 && g->e > 0)
+            k_edge_drift<<<div_up(g->e, 256), 256, lds, s>>>(a, n, g->optr, g->ocol, g->ocost,
+                                                             g->odrift);
     }
     k_node_flags<<<nblk, 256, 0, s>>>(a, g->nflag);
     k_flag_list<<<1, 1024, 0, s>>>(n, g->nflag, 2u, g->goal_list, ngoal);

@@ -413,9 +413,9 @@ __global__ void __launch_bounds__(64) k_traj_drift(SteerArgs a, const int *row_p
 // one thread per edge of the row: p_u (3), p_v (3), trajectory length,
 // 1 - q at t = (k + 1/2) T / 8, k = 0..7, and 1 - q(p_v); base = the
 // speed-weighted mean of the eight 1 - q values (arc-length weighting)
-__global__ void __launch_bounds__(64) k_traj_features(SteerArgs a, const int *row_ptr,
-                                                      const int *col, const float *elen,
-                                                      uint16_t *X, float *base) {
+__global__ void __launch_bounds__(256) k_traj_features(SteerArgs a, const int *row_ptr,
+                                                       const int *col, const float *elen,
+                                                       uint16_t *X, float *base) {
     extern __shared__ float blob[];
     for (int i = threadIdx.x; i < 3 * a.nblob; i += blockDim.x) blob[i] = a.mu[i];
     for (int i = threadIdx.x; i < a.nblob; i += blockDim.x) {
@@ -429,12 +429,20 @@ __global__ void __launch_bounds__(64) k_traj_features(SteerArgs a, const int *ro
     q.mu = blob;
     q.sig = blob + 3 * a.nblob;
     q.amp = blob + 4 * a.nblob;
-    const int u = blockIdx.x;
-    if (u >= a.n) return;
+    // one thread per edge; its source u: last row with row_ptr[u] <= e
+    const int m = row_ptr[a.n];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    int lo = 0, hi = a.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int u = lo;
     float p0[3], v0[3];
     load3(a.pos, u, p0);
     load3(a.vel, u, v0);
-    for (int e = row_ptr[u] + threadIdx.x; e < row_ptr[u + 1]; e += blockDim.x) {
+    {
         float p1[3], v1[3], c0[3], c1[3];
         load3(a.pos, col[e], p1);
         load3(a.vel, col[e], v1);

@@ -132,8 +132,9 @@ int enqueue_features(mpap_graph *g, hipStream_t st) {
     if (!g->sbase && (r = dalloc(&g->sbase, std::max<long long>(g->e, 1)))) return r;
     if (g->n == 0) return MPAP_OK;
     if (g->dim == 6) {
-        k_traj_features<<<g->n, 64, sizeof(float) * 5 * (size_t)g->nblob, st>>>(
-            steer_view(g), g->optr, g->ocol, g->elen, g->feat, g->sbase);
+        if (g->e > 0)
+            k_traj_features<<<div_up(g->e, 256), 256, sizeof(float) * 5 * (size_t)g->nblob,
+                              st>>>(steer_view(g), g->optr, g->ocol, g->elen, g->feat, g->sbase);
     } else {
         BuildArgs a{};
         a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu;
@@ -409,7 +410,9 @@ int mpap_analytic_drift(mpap_graph *g, void *stream, float *ms) {
         k_traj_drift<<<g->n, 64, sizeof(float) * 5 * (size_t)g->nblob, st>>>(
             steer_view(g), g->optr, g->ocol, g->odrift, nullptr);
     else if (g->n > 0)
-        k_edge_drift<<<g->n, 64, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost, g->odrift);
+        if (g->e > 0)
+            k_edge_drift<<<div_up(g->e, 256), 256, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost,
+                                                              g->odrift);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipEventSynchronize(e1));
