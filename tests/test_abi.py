@@ -56,3 +56,33 @@ def test_missing_library_fails_loudly(tmp_path):
             mpap.load(str(tmp_path / "nope.so"))
     finally:
         mpap._lib = saved
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every public struct of the header has the binding's size and field
+    offsets (a C program built with gcc prints them; a field the binding
+    names with a trailing underscore, a Python keyword, has it without in C)."""
+    import subprocess
+    from paper_1705_02408_amd import mpap
+    structs = [getattr(mpap, n) for n in ("mpap_env", "mpap_graph_params", "mpap_search_params",
+                                          "mpap_stats")]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpap.h"', 'int main(void) {']
+    for st in structs:
+        name = st.__name__
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in st._fields_:
+            cname = fname.rstrip("_")  # a Python keyword gets a trailing underscore
+            lines.append(f'    printf("{name} {fname} %zu\\n", offsetof({name}, {cname}));')
+    lines += ['    return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for st in structs:
+        name = st.__name__
+        assert got[(name, "size")] == ctypes.sizeof(st), name
+        for fname, _ in st._fields_:
+            assert got[(name, fname)] == getattr(st, fname).offset, (name, fname)
