@@ -20,7 +20,9 @@ this project fixes, applied identically by every consumer of a graph):
   the edge length times one minus the mean of q at the K sub-step midpoints
   (a continuous-rate reading of the per-time-step drift heuristic of
   Sec. 4.1), summed in float64 and rounded once to float32.
-* A node relocalises (its drift resets to zero on arrival) iff q(x_v) > 0.8.
+* A node relocalises (its drift resets to zero on arrival) iff q(x_v) > the
+  float32 threshold (0.8 as a float32 number, the value a float32 parameter
+  carries).
 * Goal membership: (dx*dx + dy*dy [+ dz*dz]) <= r_g*r_g in float32.
 """
 from __future__ import annotations
@@ -167,7 +169,7 @@ def build_graph(env):
     np.add.at(row_ptr, s2.astype(np.int64) + 1, 1)
     row_ptr = np.cumsum(row_ptr).astype(np.int32)
     q = quality(pos, env.blob_mu, env.blob_sigma, env.blob_amp)
-    reset = (q > float(env.reset_q)).astype(np.uint8)
+    reset = (q > float(np.float32(env.reset_q))).astype(np.uint8)
     goal = goal_mask(pos, env.goal, env.goal_radius)
     return dict(row_ptr=row_ptr, col=d2.astype(np.int32), cost=c2.astype(np.float32),
                 drift=r2.astype(np.float32), reset=reset, goal=goal, q=q)

@@ -28,8 +28,8 @@ are fixed for every consumer of a 6D roadmap):
   chord length times (1 - q(chord midpoint)), in float64 on the float32 check
   points, rounded once to float32 (the length-weighted midpoint rule of the
   2D/3D roadmaps along the trajectory).
-* Relocalisation and goal as in oracle.graph: q(p_v) > reset_q, and the
-  position in the goal ball (any velocity).
+* Relocalisation and goal as in oracle.graph: q(p_v) > the float32 reset_q,
+  and the position in the goal ball (any velocity).
 """
 from __future__ import annotations
 
@@ -185,7 +185,7 @@ def build_graph6d(env, block=32, width=64):
     return dict(row_ptr=row_ptr, col=np.concatenate(cols or empty),
                 cost=np.concatenate(costs or [np.zeros(0, F32)]),
                 drift=np.concatenate(drifts or [np.zeros(0, F32)]),
-                reset=(q > float(env.reset_q)).astype(np.uint8),
+                reset=(q > float(np.float32(env.reset_q))).astype(np.uint8),
                 goal=goal_mask(pos, env.goal, env.goal_radius), q=q)
 
 

@@ -74,13 +74,13 @@ def loss(y: np.ndarray, t: np.ndarray) -> float:
     return float(np.mean(d * d))
 
 
-def backward(p: dict, X: np.ndarray, t: np.ndarray, bf16_grads: bool = True):
+def backward(p: dict, X: np.ndarray, t: np.ndarray):
     """Gradients of the mean squared error with respect to the float32 master
-    parameters (straight through the bfloat16 rounding of the weights; the
-    rounding of h1 is treated as identity, ReLU' = [z > 0]).  With bf16_grads
-    the output gradients of both layers are rounded to bfloat16 before they
-    enter the matrix products (weight gradients and the backward of layer 2),
-    as the matrix-core kernels do; bias gradients use the unrounded values."""
+    parameters, exact (float64) for the model of ``forward``: straight through
+    the bfloat16 rounding of the weights, the rounding of h1 treated as the
+    identity, ReLU' = [z > 0].  No rounding is applied to the gradients; a
+    kernel that rounds the output gradients to bfloat16 before its matrix
+    products is compared with this within the rounding's error bound."""
     y, c = forward(p, X)
     n = X.shape[0]
     dy = 2.0 * (y - t.astype(np.float64)) / n
@@ -88,15 +88,29 @@ def backward(p: dict, X: np.ndarray, t: np.ndarray, bf16_grads: bool = True):
     g["w3"] = c["h2"].T @ dy
     g["b3"] = np.array([dy.sum()])
     dz2 = np.outer(dy, c["w3"]) * (c["z2"] > 0)
-    dz2m = bf16_round(dz2.astype(np.float32)).astype(np.float64) if bf16_grads else dz2
-    g["W2"] = c["h1"].T @ dz2m
+    g["W2"] = c["h1"].T @ dz2
     g["b2"] = dz2.sum(axis=0)
-    dh1 = dz2m @ c["W2"].T
-    dz1 = dh1 * (c["z1"] > 0)
-    dz1m = bf16_round(dz1.astype(np.float32)).astype(np.float64) if bf16_grads else dz1
-    g["W1"] = c["X"].T @ dz1m
+    dz1 = (dz2 @ c["W2"].T) * (c["z1"] > 0)
+    g["W1"] = c["X"].T @ dz1
     g["b1"] = dz1.sum(axis=0)
     return y, g
+
+
+def gradient_abs_terms(p: dict, X: np.ndarray, t: np.ndarray) -> dict:
+    """For every parameter, the sum of the absolute values of the terms its
+    gradient adds up (the same products as ``backward`` with every factor
+    replaced by its magnitude).  A perturbation of relative size u in each
+    factor moves a gradient entry by at most about k u times this sum, k the
+    number of perturbed factors on its path, so it scales the error bound of
+    a reduced-precision evaluation."""
+    y, c = forward(p, X)
+    n = X.shape[0]
+    ady = np.abs(2.0 * (y - t.astype(np.float64)) / n)
+    adz2 = np.outer(ady, np.abs(c["w3"])) * (c["z2"] > 0)
+    adz1 = (adz2 @ np.abs(c["W2"]).T) * (c["z1"] > 0)
+    return dict(w3=np.abs(c["h2"]).T @ ady, b3=np.array([ady.sum()]),
+                W2=np.abs(c["h1"]).T @ adz2, b2=adz2.sum(axis=0),
+                W1=np.abs(c["X"]).T @ adz1, b1=adz1.sum(axis=0))
 
 
 def adam_step(p: dict, g: dict, m: dict, v: dict, step: int, lr: float,

@@ -43,7 +43,7 @@ def test_model_backward_equals_rounding_free_one_on_the_bf16_grid():
              b3=np.array([0.25], np.float32))
     X = rng.choice([0.0, 0.25, 0.5, 1.0], (32, 16))
     t = rng.choice([0.0, 0.5, 1.0], 32)
-    _, gm = mlp.backward(p, X, t, bf16_grads=False)
+    _, gm = mlp.backward(p, X, t)
     gf = mlp.backward_f64(p, X, t)
     for k in gf:
         assert np.allclose(gm[k], gf[k], rtol=0, atol=1e-12), k
@@ -63,3 +63,65 @@ def test_flat_layout_roundtrip():
     q = mlp.unflat(v)
     for k in p:
         assert np.array_equal(p[k], q[k])
+
+
+def test_abs_terms_bound_every_gradient_and_are_tight_without_cancellation():
+    """gradient_abs_terms is the triangle-inequality bound of each gradient
+    entry, and equals |gradient| when every term has the same sign (positive
+    inputs and weights, outputs above their targets)."""
+    rng = np.random.default_rng(4)
+    p = mlp.init_params(6)
+    X = rng.uniform(0, 1, (48, 16))
+    t = rng.uniform(0, 1, 48)
+    _, g = mlp.backward(p, X, t)
+    a = mlp.gradient_abs_terms(p, X, t)
+    for k in g:
+        assert np.all(np.abs(g[k]) <= a[k] * (1 + 1e-12) + 1e-300), k
+    q = {k: np.abs(v).astype(np.float32) for k, v in p.items()}
+    q["b1"] = np.full(64, 0.1, np.float32)
+    q["b2"] = np.full(64, 0.1, np.float32)
+    t0 = np.full(48, -1.0)
+    _, g0 = mlp.backward(q, X, t0)
+    a0 = mlp.gradient_abs_terms(q, X, t0)
+    for k in g0:
+        assert np.allclose(np.abs(g0[k]), a0[k], rtol=1e-12, atol=0), k
+
+
+def rounded_backward(p, X, t):
+    """The backward with the two output gradients rounded to bfloat16 before
+    their matrix products (the placement the matrix-core kernels use), built
+    here from backward's own pieces for the bound check below."""
+    y, c = mlp.forward(p, X)
+    n = X.shape[0]
+    dy = 2.0 * (y - t) / n
+    dz2 = np.outer(dy, c["w3"]) * (c["z2"] > 0)
+    dz2m = mlp.bf16_round(dz2.astype(np.float32)).astype(np.float64)
+    dz1 = (dz2m @ c["W2"].T) * (c["z1"] > 0)
+    dz1m = mlp.bf16_round(dz1.astype(np.float32)).astype(np.float64)
+    return dict(w3=c["h2"].T @ dy, b3=np.array([dy.sum()]), W2=c["h1"].T @ dz2m,
+                b2=dz2.sum(0), W1=c["X"].T @ dz1m, b1=dz1.sum(0))
+
+
+def test_bf16_output_gradients_stay_within_the_stated_bound():
+    """Rounding the output gradients to bfloat16 (relative error at most
+    u = 2^-9 each, two roundings on the W1 path) moves every entry by at most
+    2 u times its absolute-term sum; the bound is not vacuous (the typical
+    entry moves by a tenth of it or less, and by more than zero)."""
+    rng = np.random.default_rng(5)
+    p = mlp.init_params(7)
+    p["b1"] = rng.normal(0, 0.2, 64).astype(np.float32)
+    p["b2"] = rng.normal(0, 0.2, 64).astype(np.float32)
+    X = rng.uniform(0, 1, (512, 16))
+    t = rng.uniform(0, 1, 512)
+    _, g = mlp.backward(p, X, t)
+    r = rounded_backward(p, X, t)
+    a = mlp.gradient_abs_terms(p, X, t)
+    u = 2.0 ** -9
+    moved = 0
+    for k in g:
+        err = np.abs(r[k] - g[k])
+        assert np.all(err <= (2 * u + u * u) * a[k] * (1 + 1e-9)), k
+        moved += int((err > 0).sum())
+    assert moved > 1000
+    ratio = np.abs(r["W1"] - g["W1"]) / np.maximum(2 * u * a["W1"], 1e-300)
+    assert np.median(ratio) < 0.1
