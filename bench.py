@@ -1,21 +1,29 @@
 """Benchmark: useful label expansions per second of the wavefront multiobjective
-search on one MI355X.
+search on one MI355X, plus queries per second of the batched serving load.
 
-A step is one whole search (Alg. 3 Explore to an empty open set, then the
-goal front) on a device-resident roadmap: the 3D workspace with 20,000 free
-samples, ~40 neighbours, 100 boxes, 80 feature blobs, three objectives (cost,
-drift, max drift so far), drift bound 0.25.  The roadmap is built on the GPU
-before timing.  `value` counts useful expansions X = sum over nodes of the
-final front size (an instance property) per second of step wall time.
+Headline step: one whole search (Alg. 3 Explore to an empty open set, then
+the goal front and its copy to the host) on a device-resident roadmap: the 3D
+workspace with 20,000 free samples, ~40 neighbours, 100 boxes, 80 feature
+blobs, three objectives (cost, drift, max drift so far), drift bound 0.25.
+The roadmap is built on the GPU before timing (it equals the oracle's
+roadmap bit for bit, and the search on it the whole oracle run, both checked
+by the GPU tests).  `value` = X / step wall time, X = sum over nodes of the
+final front size (an instance property).
 
-Prints one JSON line (rank 0).  Only one GPU is supported: --gpus N > 1 exits.
+Also measured: the 2D (2,000 samples) and 6D double-integrator (50,000
+states) single-query workloads, and the batched serving load (256 queries of
+uneven size in one recorded launch, on the learned drift judged by the
+library with the analytic fallback, against the same batch on the analytic
+drift recomputed inside the recorded launch and against one launch per
+query).
+
+Prints one JSON line.  Only one GPU is supported: --gpus N > 1 exits.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
-import platform
 import statistics
 import sys
 import time
@@ -24,6 +32,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TICK_MS = 1e-5         # the device's 100 MHz wall clock
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def alg_bytes(X: int, R: int, n_obj: int) -> int:
@@ -38,7 +51,7 @@ def alg_bytes(X: int, R: int, n_obj: int) -> int:
 def search_source_hash() -> str:
     """First 16 hex digits of the SHA-256 of the search kernel sources."""
     import hashlib
-    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1705_02408_amd", "csrc")
+    csrc = os.path.join(ROOT, "paper_1705_02408_amd", "csrc")
     h = hashlib.sha256()
     for f in ("search_kernels.hip", "search_kernels.h", "device_common.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
@@ -46,12 +59,11 @@ def search_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_search launch on the benchmark workload from the
-    committed rocprofv3 counter summary, or None when the kernel sources have
-    changed since the counters were taken."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        "k_search_plain3d_n20000.md")
+def measured_traffic(profile: str = "k_search_plain3d_n20000.md"):
+    """HBM bytes per search launch from a committed rocprofv3 counter summary
+    under profiles/, or None when the kernel sources have changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
     try:
         with open(path) as f:
             line = next(l for l in f if l.startswith("traffic:"))
@@ -64,79 +76,56 @@ def measured_traffic():
                        float(kv["write_kib"]) * float(kv["write_scale"])))
 
 
-def cpu_count_used() -> int:
-    return 1
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=20000)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["plain3d", "plain2d", "batch", "copy"],
-                    default="plain3d",
-                    help="copy: a plain 1 GiB device copy, the reference for the HBM "
-                         "traffic counters")
-    ap.add_argument("--queries", type=int, default=256, help="batch workload: query count")
-    ap.add_argument("--batch-steps", type=int, default=2, help="timed batches")
-    ap.add_argument("--no-batch", action="store_true",
-                    help="skip the batched serving measurement of the default run")
-    ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--cpu-labels", type=int, default=150000,
-                    help="labels the oracle makes permanent in the CPU baseline sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the search of one "
-                                   "roadmap is not sharded across GPUs",
-                          "n_gpus": args.gpus}), flush=True)
-        sys.exit(2)
 
+# ------------------------------------------------------------ single queries
+def measure_single(env, steps: int, warmup: int, with_trace: bool = True):
+    """Whole searches of one roadmap built on the GPU: returns a dict of the
+    step and kernel times, counts and per-phase device times."""
     import numpy as np
     import torch
-    from paper_1705_02408_amd import mpap, synth
-
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}), flush=True)
-        sys.exit(1)
-    torch.cuda.init()
-
-    if args.workload == "batch":
-        return run_batch(args)
-    if args.workload == "copy":
-        return run_copy(args)
-    env = (synth.plain3d(args.seed, n=args.n) if args.workload == "plain3d"
-           else synth.plain2d(args.seed, n=args.n))
-    n_obj = env.n_obj
+    from paper_1705_02408_amd import mpap
     t0 = time.perf_counter()
     dg = mpap.mpap_build_graph(env)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     ginfo = dg.info()
-    print(f"# graph built on GPU in {build_s:.3f}s: {ginfo}", file=sys.stderr, flush=True)
-
+    log(f"# {env.name}: graph built on GPU in {build_s:.3f}s: {ginfo}")
     trace = {}
 
     def step():
-        res = mpap.mpap_search(dg, env.beta, n_obj, env.radius, env.lam)
+        res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam)
         fr = res.goal_front()
         st = res.stats()
-        trace["t"] = res.wave_trace()
+        if with_trace:
+            trace["t"] = res.wave_trace()
         res.close()
         return fr, st
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         fr, st = step()
-        print(f"# warmup {i}: {st}", file=sys.stderr, flush=True)
-
+        log(f"# warmup {i}: {st}")
     torch.cuda.synchronize()
     times, kms, stats = [], [], []
     t_start = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ts = time.perf_counter()
         fr, st = step()
         times.append(time.perf_counter() - ts)
@@ -144,103 +133,100 @@ def main():
         stats.append(st)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    print(f"# timed {args.steps} steps in {total:.3f}s; last stats {stats[-1]}",
-          file=sys.stderr, flush=True)
-
-    X = stats[-1]["front_labels"]
-    R = stats[-1]["relaxations"]
-    ms_per_step = 1000.0 * total / args.steps
-    value = X * args.steps / total
-    k_ms = statistics.mean(kms)
-    B = alg_bytes(X, R, n_obj)
-    achieved = B / (k_ms * 1e-3) / 1e9
-
-    tr = trace["t"].astype(np.float64)
-    tick_ms = 1e-5  # 100 MHz device clock
-    phases = {
-        "count_ms": float(((tr[:, 1] - tr[:, 0]) * tick_ms).sum()),
-        "select_ms": float(((tr[:, 2] - tr[:, 1]) * tick_ms).sum()),
-        "merge_ms": float(((tr[:, 3] - tr[:, 2]) * tick_ms).sum()),
-        "count_work_block0_ms": float(((tr[:, 8] - tr[:, 0]) * tick_ms).sum()),
-        "select_work_block0_ms": float(((tr[:, 9] - tr[:, 1]) * tick_ms).sum()),
-        "merge_busiest_block_ms": float((tr[:, 6] * tick_ms).sum()),
-        "merge_mean_block_ms": float((tr[:, 7] * tick_ms).sum() / max(1, stats[-1]["blocks"])),
-        "max_group": int(tr[:, 4].max()) if tr.shape[0] else 0,
-        "max_targets": int(tr[:, 5].max()) if tr.shape[0] else 0,
-    }
-    print(f"# phases {phases}", file=sys.stderr, flush=True)
-    for w in range(0, tr.shape[0], max(1, tr.shape[0] // 12)):
-        r = tr[w]
-        print(f"# wave {w}: count {(r[1]-r[0])*tick_ms:.3f} select {(r[2]-r[1])*tick_ms:.3f} "
-              f"merge {(r[3]-r[2])*tick_ms:.3f} ms, group {int(r[4])}, targets {int(r[5])}, "
-              f"busiest block {r[6]*tick_ms:.3f} ms, mean block {r[7]*tick_ms/stats[-1]['blocks']:.3f} ms",
-              file=sys.stderr, flush=True)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import graph as ograph, search as osearch
-        t1 = time.perf_counter()
-        g = ograph.build_graph(env)
-        gb = time.perf_counter() - t1
-        labels, secs, finished = osearch.timed_sample(g, env.beta, n_obj, args.cpu_labels)
-        cpu = {"value": labels / secs, "unit": "labels/s", "cores": cpu_count_used(),
-               "kind": "oracle",
-               "sample": (f"sequential label-setting oracle on the same workload, first "
-                          f"{labels} labels made permanent ({'whole search' if finished else 'bounded sample'}), "
-                          f"{secs:.2f}s on one core of {platform.processor() or platform.machine()}; "
-                          f"oracle graph build {gb:.1f}s not counted"),
-               "host_cpus": os.cpu_count()}
-
-    out = {
-        "metric": "label expansions/s (useful, oracle-exact front)",
-        "value": value,
-        "unit": "labels/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded generator), graph built on the GPU",
-        "config": {
-            "workload": f"{env.name}: {env.dim}D r-disc roadmap, {ginfo['n']} nodes, "
-                        f"{ginfo['e']} directed edges, {env.box_lo.shape[0]} boxes, "
-                        f"{env.blob_mu.shape[0]} blobs, {n_obj} objectives, beta {env.beta}, "
-                        f"lambda {env.lam}",
-            "queries_per_step": 1,
-            "parallelism": "single GPU",
-        },
-        "queries_per_s": args.steps / total,
-        "search": {"X_front_labels": X, "R_relaxations": R,
-                   "labels_expanded_gpu": stats[-1]["labels_expanded"],
-                   "waves": stats[-1]["waves"], "merges": stats[-1]["merges"],
-                   "candidates": stats[-1]["candidates"],
-                   "goal_front": int(fr.vecs.shape[0]),
-                   "kernel_ms_mean": k_ms, "kernel_ms_min": min(kms),
-                   "step_ms_median": 1000 * statistics.median(times),
-                   "blocks": stats[-1]["blocks"], "lds_front_cap": stats[-1]["lds_front_cap"],
-                   "max_front": stats[-1]["max_front"], "phases": phases},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.workload == "plain3d" and
-                     args.n == 20000 and args.seed == 0 else None,
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                     "scaled by a plain copy's counts)",
-                     "kernel": "k_search", "alg_bytes_per_launch": B},
-        "cpu_baseline": cpu,
-    }
     dg.close()
-    if not args.no_batch:
-        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-        out["batched_serving"] = measure_batch(args, log, with_surrogate=not args.no_surrogate)
-    print(json.dumps(out), flush=True)
+    st = stats[-1]
+    X, R = st["front_labels"], st["relaxations"]
+    k_ms = statistics.mean(kms)
+    B = alg_bytes(X, R, env.n_obj)
+    out = {
+        "workload": f"{env.name}: {env.dim}D roadmap, {ginfo['n']} nodes, {ginfo['e']} directed "
+                    f"edges, {env.box_lo.shape[0]} boxes, {env.blob_mu.shape[0]} blobs, "
+                    f"{env.n_obj} objectives, beta {env.beta}, lambda {env.lam}",
+        "nodes": ginfo["n"], "edges": ginfo["e"], "graph_build_s": build_s,
+        "steps": steps, "total_s": total, "ms_per_step": 1000.0 * total / steps,
+        "labels_per_s": X * steps / total, "queries_per_s": steps / total,
+        "X_front_labels": X, "R_relaxations": R, "labels_expanded_gpu": st["labels_expanded"],
+        "waves": st["waves"], "merges": st["merges"], "candidates": st["candidates"],
+        "goal_front": int(fr.vecs.shape[0]), "kernel_ms_mean": k_ms, "kernel_ms_min": min(kms),
+        "step_ms_median": 1000 * statistics.median(times), "blocks": st["blocks"],
+        "lds_front_cap": st["lds_front_cap"], "max_front": st["max_front"],
+        "wave_build": st["wave_build"], "alg_bytes_per_launch": B,
+        "achieved_GBps": B / (k_ms * 1e-3) / 1e9,
+    }
+    if with_trace and "t" in trace:
+        tr = trace["t"].astype(np.float64)
+        out["phases"] = {
+            "count_ms": float(((tr[:, 1] - tr[:, 0]) * TICK_MS).sum()),
+            "select_ms": float(((tr[:, 2] - tr[:, 1]) * TICK_MS).sum()),
+            "merge_ms": float(((tr[:, 3] - tr[:, 2]) * TICK_MS).sum()),
+            "merge_busiest_block_ms": float((tr[:, 6] * TICK_MS).sum()),
+            "merge_mean_block_ms": float((tr[:, 7] * TICK_MS).sum() / max(1, st["blocks"])),
+            "max_group": int(tr[:, 4].max()) if tr.shape[0] else 0,
+            "max_targets": int(tr[:, 5].max()) if tr.shape[0] else 0,
+        }
+    return out
 
 
-def train_surrogates(seed: int, log):
+def golden_whole_search():
+    """The stored whole-oracle run of the 3D workload (written by
+    tests/golden/make_plain3d_golden.py): its own wall time and CPU."""
+    path = os.path.join(ROOT, "tests", "golden", "plain3d_s0_front.json")
+    try:
+        with open(path) as f:
+            s = json.load(f)
+    except OSError:
+        return None
+    return {"value": s["oracle_labels_per_s"], "unit": "labels/s", "cores": s["oracle_cores"],
+            "seconds": s["oracle_seconds"], "X": s["X"], "cpu": s["oracle_cpu"],
+            "source": "tests/golden/plain3d_s0_front.json (whole search, timed by the script "
+                      "that wrote it)"}
+
+
+def cpu_prefix_baseline(env, seconds: float):
+    """The oracle on a bounded sample of the headline search: labels are made
+    permanent in ascending cost order, so the sample is the cheap start of
+    the search (small fronts), which makes its rate an upper bound of the
+    whole search's rate."""
+    from oracle import graph as ograph, search as osearch
+    t1 = time.perf_counter()
+    g = ograph.build_graph(env)
+    gb = time.perf_counter() - t1
+    labels, secs, finished = osearch.timed_sample(g, env.beta, env.n_obj, 150000)
+    target = int(150000 * max(1.0, seconds / max(secs, 1e-3)) ** 0.5)
+    if not finished and target > labels:
+        labels, secs, finished = osearch.timed_sample(g, env.beta, env.n_obj, target)
+    return {"value": labels / secs, "unit": "labels/s", "cores": 1, "kind": "oracle",
+            "sample": (f"sequential label-setting oracle (one thread) on the headline workload's "
+                       f"own roadmap, the first {labels} labels it makes permanent "
+                       f"({'the whole search' if finished else 'a prefix: the cheapest labels, small fronts; an upper bound of the whole-search rate'}), "
+                       f"{secs:.2f}s; oracle roadmap build {gb:.1f}s not counted"),
+            "cpu": cpu_model(), "host_cores": host_cores(),
+            "whole_search_reference": golden_whole_search()}
+
+
+def cpu_whole_search(env):
+    """The oracle's whole search of a small workload (one thread)."""
+    from oracle import graph as ograph, search as osearch
+    g = ograph.build_graph(env)
+    res = osearch.search(g, env.beta, env.n_obj)
+    return {"value": res.X / res.seconds, "unit": "labels/s", "cores": 1, "kind": "oracle",
+            "seconds": res.seconds, "X": res.X,
+            "sample": "the whole search of the same workload (oracle roadmap, one thread)"}
+
+
+# ------------------------------------------------------------------- batch
+def surrogate_error_stats(ana, sur, held, beta):
+    import numpy as np
+    floor = 1e-3 * beta
+    rel = np.abs(sur[held] - ana[held]).astype(np.float64) / np.maximum(ana[held], floor)
+    return {"heldout_edges": int(held.size), "p50": float(np.percentile(rel, 50)),
+            "p90": float(np.percentile(rel, 90)), "p99": float(np.percentile(rel, 99)),
+            "max": float(rel.max())}
+
+
+def train_surrogates(seed: int):
     """One surrogate per dimension, trained on roadmaps that are not part of
-    the measured batch (the largest query sizes, other seeds)."""
+    the measured batch (other seeds)."""
     import numpy as np
     from paper_1705_02408_amd import mpap, synth
     models = {}
@@ -251,7 +237,8 @@ def train_surrogates(seed: int, log):
         g = mpap.mpap_build_graph(env)
         e = g.info()["e"]
         n_train = min(1 << 20, (e // 4096) * 4096)
-        edges = np.random.default_rng(seed + dim).permutation(e)[:n_train]
+        perm = np.random.default_rng(seed + dim).permutation(e)
+        edges = perm[:n_train]
         s = mpap.Surrogate(seed=seed * 10 + dim)
         t0 = time.perf_counter()
         loss = s.train(g, edges, epochs=8, batch=4096, lr=2e-3)
@@ -259,22 +246,85 @@ def train_surrogates(seed: int, log):
         s.score(g)
         ana = mpap.mpap_graph_drift(g, 0)
         sur = mpap.mpap_graph_drift(g, 1)
-        held = np.setdiff1d(np.arange(e), edges)
-        rel = np.abs(sur[held] - ana[held]) / np.maximum(ana[held], 1e-3)
+        _, base = mpap.mpap_edge_features(g, with_base=True)
+        cost = g.export()["cost"]
+        only_base = (cost.astype(np.float64) * np.clip(base, 0, 1)).astype(np.float32)
+        held = perm[n_train:]
+        err = surrogate_error_stats(ana, sur, held, env.beta)
+        err_base = surrogate_error_stats(ana, only_base, held, env.beta)
         log(f"# surrogate {dim}D: {n_train} edges, {dt:.2f}s, loss {loss[0]:.4g} -> "
-            f"{loss[-1]:.4g}, held-out median rel err {np.median(rel):.4f} (n={held.size})")
+            f"{loss[-1]:.4g}; held-out rel err p50 {err['p50']:.3g} p99 {err['p99']:.3g} "
+            f"(8-point base alone p50 {err_base['p50']:.3g} p99 {err_base['p99']:.3g})")
         models[dim] = dict(model=s, train_s=dt, loss_first=float(loss[0]),
-                           loss_last=float(loss[-1]), heldout_median_rel=float(np.median(rel)),
-                           n_train=int(n_train))
+                           loss_last=float(loss[-1]), n_train=int(n_train),
+                           heldout_rel_err=err, heldout_rel_err_base_only=err_base)
         g.close()
     return models
 
 
-def measure_batch(args, log, with_surrogate: bool = True):
+def _cpu_batch_worker(args):
+    env, = args
+    from oracle import graph as ograph, search as osearch
+    g = ograph.build_graph(env)
+    if g["goal"].sum() == 0:
+        return None
+    res = osearch.search(g, env.beta, env.n_obj)
+    return res.X, res.seconds
+
+
+def cpu_batch_baseline(envs, X_batch: int, seconds: float):
+    """The oracle over whole queries of the batch on every host core (one
+    query per process): a seeded sample of the batch's queries below 4,000
+    samples, as many as finish in about `seconds` of wall time.  The label
+    rate over the sample (aggregate over the cores) is scaled to queries/s
+    with the batch's own mean labels per query; the sample's small fronts
+    make it an upper bound of the rate on the whole batch."""
+    import multiprocessing as mp
+
+    import numpy as np
+    cores = min(host_cores(), 16)  # a one-GPU box's share of the host
+    small = [k for k, e in enumerate(envs) if e.n_nodes <= 4000]
+    order = [small[i] for i in np.random.default_rng(0).permutation(len(small))]
+    done_labels, done_q, cpu_s = 0, 0, 0.0
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")  # fresh interpreters: nothing of the GPU state
+    with ctx.Pool(cores) as pool:
+        pending = [pool.apply_async(_cpu_batch_worker, ((envs[k],),)) for k in order]
+        for r in pending:
+            left = seconds - (time.perf_counter() - t0)
+            if left <= 0:
+                break
+            try:
+                out = r.get(timeout=left)
+            except mp.TimeoutError:
+                break
+            if out is None:
+                continue
+            done_labels += out[0]
+            cpu_s += out[1]
+            done_q += 1
+        pool.terminate()
+    wall = time.perf_counter() - t0
+    if done_q == 0 or cpu_s <= 0:
+        return None
+    rate = done_labels / cpu_s * cores  # labels/s over all cores (search time only)
+    mean_x = X_batch / max(len(envs), 1)
+    return {"value": rate / mean_x, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "labels_per_s": rate,
+            "sample": (f"whole oracle searches of {done_q} queries of the batch (seeded sample of "
+                       f"the queries below 4,000 samples), one per process on {cores} cores, "
+                       f"{done_labels} labels in {cpu_s:.1f} s of search time ({wall:.1f} s wall "
+                       f"with the oracle roadmap builds); labels/s x cores scaled by the batch's "
+                       f"mean {mean_x:.0f} labels per query (small queries: an upper bound)"),
+            "cpu": cpu_model()}
+
+
+def measure_batch(args, with_surrogate: bool = True):
     """Serving-style load: args.queries independent queries of uneven size in
-    one persistent launch, on the learned drift (judged by the analytic
-    re-walk, failing queries searched again on the analytic drift), against
-    the same queries searched one launch each on the analytic drift."""
+    one persistent launch recorded as a HIP graph (a) on the learned drift,
+    judged by the library with the analytic fallback, (b) on the analytic
+    drift recomputed inside the recorded launch, (c) one launch per query on
+    the precomputed analytic drift."""
     import numpy as np
     import torch
     from paper_1705_02408_amd import autotune, mpap, synth
@@ -294,115 +344,119 @@ def measure_batch(args, log, with_surrogate: bool = True):
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     nq = len(envs)
-    # analytic precompute time (the drift the plain path uses)
     ana_ms = sum(mpap.mpap_analytic_drift(p) for p in parts)
     out = {"queries": nq, "build_s": build_s, "analytic_drift_ms": ana_ms}
     models = None
-    sur_ms = 0.0
     if with_surrogate:
-        models = train_surrogates(args.seed, log)
+        models = train_surrogates(args.seed)
         sur_ms = sum(models[e.dim]["model"].score(p) for e, p in zip(envs, parts))
         out["surrogate"] = {f"{d}d": {k: v for k, v in m.items() if k != "model"}
                             for d, m in models.items()}
         out["surrogate_score_ms"] = sur_ms
     union = mpap.mpap_graph_concat(parts)
     info = union.info()
-    log(f"# {nq} roadmaps ({info}) built in {build_s:.2f}s; analytic drift {ana_ms:.1f} ms, "
-        f"surrogate scoring {sur_ms:.1f} ms")
-    heur = 1 if with_surrogate else 0
-    params = [mpap.search_params(e.beta, e.n_obj, e.radius, e.lam, heuristic=heur) for e in envs]
-    # tune on the first 32 queries (the choice never changes a result)
+    log(f"# {nq} roadmaps ({info}) built in {build_s:.2f}s; analytic drift {ana_ms:.1f} ms")
+    base = [mpap.search_params(e.beta, e.n_obj, e.radius, e.lam) for e in envs]
     sub = mpap.mpap_graph_concat(parts[:32])
     t0 = time.perf_counter()
-    choice = autotune.tune(sub, params[:32], sorted({e.dim for e in envs}), 2, repeats=1,
-                           lambdas=(0.5, 1.0, 2.0), near_scans=(8, 16, 32), log=log)
+    choice = autotune.tune(sub, base[:32], sorted({e.dim for e in envs}), 2, repeats=1,
+                           lambdas=(0.5, 1.0, 2.0), log=log)
     sub.close()
-    log(f"# autotune {time.perf_counter() - t0:.1f}s")
-    params = autotune.apply(params, choice)
-    log(f"# autotuned: lambda {choice.lam}, near_scan {choice.near_scan} ({choice.tried})")
+    out["autotune"] = {"s": time.perf_counter() - t0, **{k.rstrip("_"): v for k, v in
+                                                         choice.fields().items()}}
+    log(f"# autotuned {choice.fields()} in {out['autotune']['s']:.1f}s")
 
-    # the batch recorded once as a HIP graph: scoring of every roadmap by its
-    # surrogate, the persistent search, the goal fronts
-    t0 = time.perf_counter()
-    plan = mpap.Plan(union, params, parts=parts if with_surrogate else None,
-                     models=[models[e.dim]["model"] for e in envs] if with_surrogate else None)
-    log(f"# plan recorded in {time.perf_counter() - t0:.2f}s")
+    def params(heur):
+        return autotune.apply([mpap.search_params(e.beta, e.n_obj, e.radius, e.lam,
+                                                  heuristic=heur) for e in envs], choice)
 
-    def one_batch():
-        ts = time.perf_counter()
-        res = plan.run()
-        st = res.stats()
-        ok = [True] * nq
-        if with_surrogate:
-            ok = mpap.surrogate_judge(res, [e.beta for e in envs])
-        lat = [res.query_info(k)["latency_ms"] for k in range(nq)]
-        res.close()
-        log(f"# batch: {time.perf_counter() - ts:.2f}s, kernel {st['gpu_ms']:.1f} ms, "
-            f"judge passed {sum(ok)}/{nq}")
-        fb_ms = 0.0
-        for k in [k for k in range(nq) if not ok[k]]:
-            # the judge rejected this front: search the query again on the
-            # analytic drift of its own roadmap
-            r2 = mpap.mpap_search(parts[k], envs[k].beta, envs[k].n_obj, envs[k].radius,
-                                  choice.lam)
-            fb_ms += r2.stats()["gpu_ms"]
-            lat[k] = st["gpu_ms"] + fb_ms  # answered after the batch and the re-search
-            r2.goal_front()
-            r2.close()
-        return time.perf_counter() - ts, st, lat, ok, fb_ms
+    def timed_plan(plan, judge: bool, label: str):
+        for _ in range(min(args.warmup, 1)):
+            r = plan.run()
+            if judge:
+                r.judge(1e-2, fallback=True)
+            r.close()
+        torch.cuda.synchronize()
+        walls, stats, lats = [], [], []
+        for _ in range(args.batch_steps):
+            ts = time.perf_counter()
+            res = plan.run()
+            if judge:
+                res.judge(1e-2, fallback=True)
+            for k in range(nq):
+                res.goal_front(k)
+            walls.append(time.perf_counter() - ts)
+            st = res.stats()
+            stats.append(st)
+            lats.append([res.query_info(k)["latency_ms"] for k in range(nq)])
+            res.close()
+            log(f"# {label}: {walls[-1]:.3f}s, kernel {st['gpu_ms']:.1f} ms, rejected "
+                f"{st['judged_failed']}, fallback {st['fallback_ms']:.1f} ms")
+        wall = statistics.mean(walls)
+        lat = np.array(lats[-1])
+        st = stats[-1]
+        return {"queries_per_s": nq / wall, "step_wall_s": wall,
+                "label_expansions_per_s": st["front_labels"] / wall,
+                "kernel_ms_mean": statistics.mean(s_["gpu_ms"] for s_ in stats),
+                "judge_rejected": st["judged_failed"], "fallback_ms": st["fallback_ms"],
+                "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                               "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
+                "X_front_labels": st["front_labels"], "R_relaxations": st["relaxations"],
+                "waves": st["waves"], "wave_build": st["wave_build"]}
 
-    for i in range(min(args.warmup, 1)):
-        one_batch()
-    torch.cuda.synchronize()
-    walls, stats, lats, oks, fbs = [], [], [], [], []
-    for i in range(args.batch_steps):
-        w, st, lat, ok, fb = one_batch()
-        walls.append(w)
-        stats.append(st)
-        lats.append(lat)
-        oks.append(ok)
-        fbs.append(fb)
-    torch.cuda.synchronize()
-    wall = statistics.mean(walls)
-    X = stats[-1]["front_labels"]
-    lat = np.array(lats[-1])
-    # plain: one launch per query, analytic drift
+    res_sur = None
+    if with_surrogate:
+        t0 = time.perf_counter()
+        plan = mpap.Plan(union, params(1), parts=parts,
+                         models=[models[e.dim]["model"] for e in envs])
+        log(f"# surrogate plan recorded in {time.perf_counter() - t0:.2f}s")
+        res_sur = timed_plan(plan, True, "batched+surrogate")
+        res_sur["plan"] = plan.info()
+        plan.close()
+    plan = mpap.Plan(union, params(0), parts=parts, analytic=True)
+    res_ana = timed_plan(plan, False, "batched+analytic")
+    res_ana["plan"] = plan.info()
+    plan.close()
+
     log("# plain: one launch per query")
-    seq = 0.0
-    Xp = 0
+    seq, Xp, per_q = 0.0, 0, []
     for k, (p, e) in enumerate(zip(parts, envs)):
         ts = time.perf_counter()
         r1 = mpap.mpap_search(p, e.beta, e.n_obj, e.radius, e.lam)
         r1.goal_front()
         Xp += r1.stats()["front_labels"]
         r1.close()
-        seq += time.perf_counter() - ts
+        dt = time.perf_counter() - ts
+        per_q.append(dt)
+        seq += dt
         if (k + 1) % 64 == 0:
             log(f"# plain: {k + 1}/{nq} queries, {seq:.1f}s")
-    k_ms = statistics.mean(s_["gpu_ms"] for s_ in stats)
-    B = alg_bytes(X, stats[-1]["relaxations"], 2)
+    head = res_sur if res_sur is not None else res_ana
+    X = res_ana["X_front_labels"]
+    B = alg_bytes(X, res_ana["R_relaxations"], 2)
+    k_ms = res_ana["kernel_ms_mean"]
     out.update({
-        "queries_per_s": nq / wall,
-        "label_expansions_per_s": X / wall,
-        "step_wall_s": wall,
-        "judge_pass_fraction": float(np.mean(oks[-1])),
-        "fallback_ms": fbs[-1],
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max())},
-        "plain_one_launch_per_query": {"queries_per_s": nq / seq,
+        "queries_per_s": head["queries_per_s"],
+        "batched_surrogate": res_sur,
+        "batched_analytic": res_ana,
+        "plain_one_launch_per_query": {"queries_per_s": nq / seq, "wall_s": seq,
                                        "label_expansions_per_s": Xp / seq,
-                                       "wall_s": seq},
-        "speedup_vs_plain": (nq / wall) / (nq / seq),
-        "search": {"X_front_labels": X, "R_relaxations": stats[-1]["relaxations"],
-                   "waves": stats[-1]["waves"], "kernel_ms_mean": k_ms,
-                   "max_front": stats[-1]["max_front"], "nodes": info["n"], "edges": info["e"]},
+                                       "latency_ms_p50": 1e3 * float(np.percentile(per_q, 50)),
+                                       "latency_ms_p99": 1e3 * float(np.percentile(per_q, 99))},
+        "speedup_surrogate_vs_analytic_batched": (res_sur["queries_per_s"] /
+                                                  res_ana["queries_per_s"]) if res_sur else None,
+        "speedup_batched_vs_plain": head["queries_per_s"] / (nq / seq),
+        "nodes": info["n"], "edges": info["e"],
         "roofline": {"bound": "hbm", "achieved": B / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": B / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "kernel": "k_search_wave" if stats[-1]["wave_build"] else "k_search"},
-        "autotune": {"lambda": choice.lam, "near_scan": choice.near_scan},
-        "plan": plan.info(),
+                     "kernel": "k_search_wave" if res_ana["wave_build"] else "k_search",
+                     "alg_bytes_per_launch": B,
+                     "traffic": measured_traffic("k_search_wave_batch256.md")
+                     if args.queries == 256 and args.seed == 0 else None},
     })
-    plan.close()
+    if not args.no_cpu_baseline:
+        log("# batch CPU baseline (oracle, all cores)")
+        out["cpu_baseline"] = cpu_batch_baseline(envs, X, args.cpu_seconds)
     union.close()
     for p in parts:
         p.close()
@@ -433,20 +487,112 @@ def run_copy(args):
 
 
 def run_batch(args):
-    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    b = measure_batch(args, log, with_surrogate=not args.no_surrogate)
+    b = measure_batch(args, with_surrogate=not args.no_surrogate)
     out = {
-        "metric": "queries/s (batched, oracle-exact fronts)",
+        "metric": "queries/s (batched, learned drift judged per query, exact fallback)",
         "value": b["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
         "steps": args.batch_steps, "warmup": args.warmup,
-        "ms_per_step": 1000.0 * b["step_wall_s"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded generator)",
+        "ms_per_step": 1000.0 * (b["batched_surrogate"] or b["batched_analytic"])["step_wall_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded generator)",
         "config": {"workload": f"batch of {b['queries']} queries, 2D/3D even odds, sizes "
                                f"log-uniform 2000-50000 samples, two objectives",
                    "queries_per_step": b["queries"], "parallelism": "single GPU"},
-        "batched_serving": b, "roofline": dict(b["roofline"], traffic=None),
-        "cpu_baseline": None,
+        "batched_serving": b, "roofline": b["roofline"],
+        "cpu_baseline": b.get("cpu_baseline"),
     }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=20000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", choices=["plain3d", "plain2d", "plain6d", "batch", "copy"],
+                    default="plain3d",
+                    help="copy: a plain 1 GiB device copy, the reference for the HBM "
+                         "traffic counters")
+    ap.add_argument("--queries", type=int, default=256, help="batch workload: query count")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed batches")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched serving measurement of the default run")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 2D and 6D single-query rows of the default run")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="time budget of each CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the search of one "
+                                   "roadmap is not sharded across GPUs",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_1705_02408_amd import mpap, synth  # noqa: F401  (fails loudly if not built)
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    torch.cuda.init()
+
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "copy":
+        return run_copy(args)
+    env = {"plain3d": lambda: synth.plain3d(args.seed, n=args.n),
+           "plain2d": lambda: synth.plain2d(args.seed, n=args.n),
+           "plain6d": lambda: synth.plain6d(args.seed, n=args.n)}[args.workload]()
+    head = measure_single(env, args.steps, args.warmup)
+    for k in ("phases",):
+        log(f"# {k} {head.get(k)}")
+    headline_3d = args.workload == "plain3d" and args.n == 20000 and args.seed == 0
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_prefix_baseline(env, args.cpu_seconds)
+    out = {
+        "metric": "label expansions/s (useful, oracle-exact front)",
+        "value": head["labels_per_s"],
+        "unit": "labels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator), roadmap built on the GPU",
+        "config": {"workload": head["workload"], "queries_per_step": 1,
+                   "parallelism": "single GPU"},
+        "queries_per_s": head["queries_per_s"],
+        "search": {k: v for k, v in head.items() if k not in ("workload",)},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["achieved_GBps"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if headline_3d else None,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a plain copy's counts)",
+                     "kernel": "k_search_wave" if head["wave_build"] else "k_search",
+                     "alg_bytes_per_launch": head["alg_bytes_per_launch"]},
+        "cpu_baseline": cpu,
+    }
+    if headline_3d and not args.no_configs:
+        rows = {}
+        for name, env2 in (("plain2d_n2000", synth.plain2d(0)), ("plain6d_n50000",
+                                                                synth.plain6d(0))):
+            r = measure_single(env2, args.steps, args.warmup, with_trace=False)
+            if not args.no_cpu_baseline and env2.dim == 2:
+                r["cpu_baseline"] = cpu_whole_search(env2)
+            rows[name] = r
+        out["configs"] = rows
+    if not args.no_batch and headline_3d:
+        out["batched_serving"] = measure_batch(args, with_surrogate=not args.no_surrogate)
     print(json.dumps(out), flush=True)
 
 

@@ -88,8 +88,11 @@ typedef struct {
  *   drift = Cost * (1 - mean q over the K sub-step midpoints).  Per node:
  *   reset = q(x) > reset_q, goal = |x - goal|^2 <= goal_radius^2.
  *   q(x) = clamp(sum_j amp_j exp(-|x - mu_j|^2 / (2 sigma_j^2)), 0, 1),
- *   evaluated in float32 with the device expf (not bit-identical to a host
- *   libm; drift and reset agree with a float64 evaluation within a few ulp).
+ *   evaluated in float64 from the float32 inputs (blob order); the drift is
+ *   the float64 sum over the midpoints in order, (Cost/K)(1 - q), rounded
+ *   once to float32, and reset compares the float64 q with the float32
+ *   reset_q.  (The float64 exp may differ from another libm's in the last
+ *   bit, which changes a float32 result only in rare ties.)
  * dim 6 (double integrator; the dynamics class of Sec. 4.1 and Sec. 5):
  *   steering u -> v is the minimum-energy control of p'' = a over the fixed
  *   time T = horizon; per axis, with a = (p_v - p_u) - v_u T, b = v_v - v_u,
@@ -97,8 +100,10 @@ typedef struct {
  *   The trajectory is checked at t_k = (k T)/K, k = 0..K: inside the closed
  *   unit cube, in no closed box, speed <= 1.  Each node keeps the k_out
  *   reachable targets of least (J, id) (a directed roadmap).  drift = sum
- *   over the K chords of |chord| (1 - q(chord midpoint)).  All float32 with
- *   separately rounded operations.
+ *   over the K chords of |chord| (1 - q(chord midpoint)), float64 terms from
+ *   the float32 check points summed in chord order and rounded once to
+ *   float32.  Steering, checks and costs are float32 with separately rounded
+ *   operations.
  * Errors: MPAP_ERR_INVAL (null, dim not 2/3/6, n_nodes < 1, non-finite
  * position, radius <= 0, dim 6 without velocities or with k_out, horizon or
  * traj_steps out of range, more than 1024 boxes), MPAP_ERR_NOGOAL (no node in
@@ -156,6 +161,9 @@ typedef struct {
                                  single wave (16 merges per CU at once); 0 = four times the
                                  waves of the grid, < 0 = never.  Never changes the
                                  result. */
+    int32_t skip;             /* 1: leave this query out of a batched search (its root
+                                 label is not seeded; its goal front is empty); 0 =
+                                 search it */
 } mpap_search_params;
 
 /*
@@ -258,6 +266,8 @@ typedef struct {
     int32_t max_front;        /* largest final per-node front */
     int32_t wave_build;       /* 1: the wave-first kernel build ran (single-wave merges in
                                  iterations with many small targets), 0: the weight-ordered one */
+    int32_t judged_failed;    /* queries whose learned-drift front mpap_judge rejected */
+    float fallback_ms;        /* device time of the analytic re-search of those queries */
 } mpap_stats;
 
 int mpap_result_stats(const mpap_result *r, mpap_stats *out);
@@ -363,6 +373,44 @@ int mpap_graph_drift(const mpap_graph *g, int32_t which, float *out);
 int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *drift,
                        float *maxdrift, uint8_t *feasible, int32_t capacity, int32_t *count);
 
+/*
+ * mpap_judge - the learned heuristic's judge and fallback.  The learned
+ * heuristic stands in for the per-edge precompute of Alg. 1 step 2 (learned
+ * heuristics, Sec. 5.2); a search on it is accepted per query only if every
+ * goal-front plan, re-walked along its parent chain with the roadmap's
+ * analytic drift (the same float32 fold as the search), stays within the
+ * bound at every step and its drift and max drift differ from the searched
+ * values by at most tol relative to max(analytic value, 1e-3 * beta)
+ * (float64 comparison).  Queries searched on the analytic drift pass.
+ *   fallback = 0: judge only.  fallback = 1: the rejected queries are searched
+ *   again, in one launch, on the analytic drift (the other queries are
+ *   skipped), and r then answers them from that exact search: their goal
+ *   fronts, node fronts, plans and latencies (latency = the first launch, the
+ *   judge and the re-search).  Label ids of re-searched queries are reported
+ *   shifted by the first search's label count, so ids stay unique within r.
+ *   failed (nullable, nq bytes) receives 1 for each rejected query; n_failed
+ *   (nullable) their count; stats.judged_failed and stats.fallback_ms are
+ *   set.  A result is judged once (MPAP_ERR_INVAL on a second call); a plan's
+ *   result is judged before the plan's next run.  Plans longer than 4096
+ *   steps are an error (MPAP_ERR_HIP).
+ * Errors: MPAP_ERR_INVAL (null, tol not > 0, judged already), MPAP_ERR_HIP,
+ * errors of mpap_search_batch for the re-search.
+ */
+int mpap_judge(mpap_result *r, float tol, int32_t fallback, void *stream, uint8_t *failed,
+               int32_t *n_failed);
+
+/*
+ * mpap_surrogate_save / mpap_surrogate_load - the network's 5313 float32
+ * parameters in a little-endian file: the 8 bytes "MPAPSUR1", the count
+ * (int32, 5313), the parameters (W1, b1, W2, b2, w3, b3 as in
+ * mpap_surrogate_set_params), and a 32-bit FNV-1a hash of the parameter
+ * bytes.  Loading replaces the parameters and resets the optimiser state.
+ * Errors: MPAP_ERR_INVAL (null, unreadable or malformed file, wrong count or
+ * hash, non-finite values), MPAP_ERR_HIP.
+ */
+int mpap_surrogate_save(const mpap_surrogate *s, const char *path);
+int mpap_surrogate_load(mpap_surrogate *s, const char *path);
+
 /* ----------------------------------------------------------------- misc */
 const char *mpap_status_string(int status);
 const char *mpap_last_error(void);
@@ -381,13 +429,19 @@ typedef struct mpap_plan mpap_plan;
  * nparts == the graph's query count): parts[q] is the roadmap query q was
  * concatenated from and models[q] (nullable) the surrogate that scores it
  * before each search, writing the part's slice of g's surrogate drift (used by
- * queries with heuristic = 1).  g, the parts and the models must outlive the
- * plan; the plan owns its own search workspace.  Errors: as
+ * queries with heuristic = 1).  flags: MPAP_PLAN_ANALYTIC = every part without
+ * a model has its analytic drift (Alg. 1 step 2 precompute, as
+ * mpap_analytic_drift) recomputed inside the graph before each search,
+ * writing the part's slice of g's analytic drift (the per-batch precompute
+ * the learned heuristic replaces); 0 = none.  g, the parts and the models
+ * must outlive the plan; the plan owns its own search workspace.  Errors: as
  * mpap_search_batch, MPAP_ERR_INVAL (part sizes that do not match the
- * queries, a scored part without an environment), MPAP_ERR_HIP (recording). */
+ * queries, a scored part without an environment, unknown flags,
+ * MPAP_PLAN_ANALYTIC without parts), MPAP_ERR_HIP (recording). */
+#define MPAP_PLAN_ANALYTIC 1
 int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t n_params,
                      mpap_graph *const *parts, const mpap_surrogate *const *models,
-                     int32_t nparts, void *stream, mpap_plan **out);
+                     int32_t nparts, int32_t flags, void *stream, mpap_plan **out);
 
 /* mpap_plan_run - launch the recorded graph on `stream` and wait.  The result
  * holds the goal fronts, statistics and latencies like mpap_search_batch's;

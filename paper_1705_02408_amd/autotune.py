@@ -1,11 +1,14 @@
 """Autotuner for the search's free parameters.
 
-None of the tuned settings changes a result (the fronts are the same for any
-group factor, near-scan length or LDS staging size); they only trade the
-number of Explore iterations (grid barriers) against wasted expansions, and
-scan work against staging.  The tuner times a small grid of settings on the
-caller's graph (or batch) with the device clock of the search launch, keeps
-the fastest, and caches the choice in a JSON file keyed by device and a
+None of the tuned settings changes a result: the fronts are the same for any
+group factor (lambda), near-scan length, LDS staging size of a front (the
+bucket stage), workgroup size and single-wave threshold (the tile of one
+merge: a workgroup or a wave).  They trade the number of Explore iterations
+(grid barriers) against wasted expansions, scan work against staging, and
+large merges against many small ones.  The tuner times the search launch
+with its device clock over one setting at a time (coordinate descent in the
+order lambda, near-scan, workgroup size, single-wave threshold, LDS stage),
+keeps the fastest, and caches the choice in a JSON file keyed by device and a
 workload class (dimension mix, objective count and a size bucket).
 """
 from __future__ import annotations
@@ -22,6 +25,12 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 
 LAMBDAS = (0.25, 0.5, 1.0, 2.0)
 NEAR_SCANS = (8, 16, 32)
+BLOCK_THREADS = (1024, 512)
+WAVE_MIN_TARGETS = (0, -1, 1)   # default threshold, never, every iteration
+STAGE_CAPS = (0, 2048)          # 0 = all the LDS holds
+
+# the tuned fields of mpap_search_params, in descent order
+FIELDS = ("lambda_", "near_scan", "block_threads", "wave_min_targets", "stage_cap")
 
 
 @dataclasses.dataclass
@@ -30,6 +39,13 @@ class Choice:
     near_scan: int
     kernel_ms: float
     tried: list
+    block_threads: int = 0
+    wave_min_targets: int = 0
+    stage_cap: int = 0
+
+    def fields(self) -> dict:
+        return dict(lambda_=self.lam, near_scan=self.near_scan, block_threads=self.block_threads,
+                    wave_min_targets=self.wave_min_targets, stage_cap=self.stage_cap)
 
 
 def workload_key(device: str, dims, n_obj: int, nodes: int) -> str:
@@ -55,13 +71,23 @@ def _time(graph, params, repeats: int) -> float:
     return best
 
 
+def _copy(p, **over):
+    q = mpap.mpap_search_params()
+    for f, _ in mpap.mpap_search_params._fields_:
+        setattr(q, f, getattr(p, f))
+    for k, v in over.items():
+        setattr(q, k, v)
+    return q
+
+
 def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_CACHE,
-         repeats: int = 2, lambdas=LAMBDAS, near_scans=NEAR_SCANS, use_cache: bool = True,
-         log=None) -> Choice:
-    """Pick (lambda, near_scan) for ``graph`` searched with ``base_params`` (one
-    mpap_search_params, or one per query; their lambda/near_scan fields are
-    overridden).  Returns the choice; the cache is updated.  ``log`` (optional)
-    receives one line per timed setting."""
+         repeats: int = 2, lambdas=LAMBDAS, near_scans=NEAR_SCANS,
+         block_threads=BLOCK_THREADS, wave_min_targets=WAVE_MIN_TARGETS,
+         stage_caps=STAGE_CAPS, use_cache: bool = True, log=None) -> Choice:
+    """Pick the settings for ``graph`` searched with ``base_params`` (one
+    mpap_search_params, or one per query; their tuned fields are overridden).
+    Returns the choice; the cache is updated.  ``log`` (optional) receives one
+    line per timed setting."""
     nodes = graph.info()["n"]
     key = workload_key(_device_name(), dims, n_obj, nodes)
     cache = {}
@@ -70,43 +96,45 @@ def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_
             cache = json.load(f)
     if use_cache and key in cache:
         c = cache[key]
-        return Choice(c["lam"], c["near_scan"], c["kernel_ms"], c.get("tried", []))
+        return Choice(c["lam"], c["near_scan"], c["kernel_ms"], c.get("tried", []),
+                      c.get("block_threads", 0), c.get("wave_min_targets", 0),
+                      c.get("stage_cap", 0))
     base = base_params if isinstance(base_params, list) else [base_params]
-
-    def with_(lam, ns):
-        out = []
-        for p in base:
-            q = mpap.mpap_search_params()
-            for f, _ in mpap.mpap_search_params._fields_:
-                setattr(q, f, getattr(p, f))
-            q.lambda_ = lam
-            q.near_scan = ns
-            out.append(q)
-        return out
-
+    cur = dict(lambda_=0.5, near_scan=16, block_threads=1024, wave_min_targets=0, stage_cap=0)
+    grid = dict(lambda_=lambdas, near_scan=near_scans, block_threads=block_threads,
+                wave_min_targets=wave_min_targets, stage_cap=stage_caps)
     tried = []
-    _time(graph, with_(0.5, 16), 1)  # warm the workspace (capacities)
-    for lam in lambdas:
-        ms = _time(graph, with_(lam, 16), repeats)
-        tried.append(dict(lam=lam, near_scan=16, kernel_ms=ms))
-        if log:
-            log(f"# autotune lambda {lam} near_scan 16: {ms:.1f} ms")
-    best_lam = min(tried, key=lambda r: r["kernel_ms"])["lam"]
-    for ns in near_scans:
-        if ns == 16:
-            continue
-        ms = _time(graph, with_(best_lam, ns), repeats)
-        tried.append(dict(lam=best_lam, near_scan=ns, kernel_ms=ms))
-        if log:
-            log(f"# autotune lambda {best_lam} near_scan {ns}: {ms:.1f} ms")
-    best = min(tried, key=lambda r: r["kernel_ms"])
-    choice = Choice(best["lam"], best["near_scan"], best["kernel_ms"], tried)
+    seen = {}
+
+    def measure(setting):
+        k = tuple(setting[f] for f in FIELDS)
+        if k not in seen:
+            ms = _time(graph, [_copy(p, **setting) for p in base], repeats)
+            seen[k] = ms
+            tried.append(dict(setting, kernel_ms=ms))
+            if log:
+                log("# autotune " + " ".join(f"{f.rstrip('_')} {setting[f]}" for f in FIELDS) +
+                    f": {ms:.1f} ms")
+        return seen[k]
+
+    _time(graph, [_copy(p, **cur) for p in base], 1)  # warm the workspace (capacities)
+    for f in FIELDS:
+        best_v, best_ms = cur[f], measure(cur)
+        for v in grid[f]:
+            ms = measure(dict(cur, **{f: v}))
+            if ms < best_ms:
+                best_v, best_ms = v, ms
+        cur[f] = best_v
+    choice = Choice(cur["lambda_"], cur["near_scan"], seen[tuple(cur[f] for f in FIELDS)], tried,
+                    cur["block_threads"], cur["wave_min_targets"], cur["stage_cap"])
     if cache_path:
         cache[key] = dict(lam=choice.lam, near_scan=choice.near_scan,
+                          block_threads=choice.block_threads,
+                          wave_min_targets=choice.wave_min_targets, stage_cap=choice.stage_cap,
                           kernel_ms=choice.kernel_ms, tried=tried, when=time.time())
         tmp = cache_path + f".tmp{os.getpid()}"
-        with open(tmp, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
         os.replace(tmp, cache_path)
     return choice
 
@@ -114,12 +142,5 @@ def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_
 def apply(params, choice: Choice):
     """Copies of ``params`` (one or a list) with the tuned settings."""
     single = not isinstance(params, list)
-    out = []
-    for p in ([params] if single else params):
-        q = mpap.mpap_search_params()
-        for f, _ in mpap.mpap_search_params._fields_:
-            setattr(q, f, getattr(p, f))
-        q.lambda_ = choice.lam
-        q.near_scan = choice.near_scan
-        out.append(q)
+    out = [_copy(p, **choice.fields()) for p in ([params] if single else params)]
     return out[0] if single else out

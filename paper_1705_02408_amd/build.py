@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpap.so")
 SOURCES = ["mpap_runtime.hip", "search_kernels.hip", "graph_kernels.hip", "mlp_kernels.hip",
-           "surrogate_runtime.hip", "plan_runtime.hip",
+           "surrogate_runtime.hip", "plan_runtime.hip", "judge_runtime.hip",
            "steer_kernels.hip"]
 
 HIPCC_FLAGS = [

@@ -40,6 +40,24 @@ __device__ __forceinline__ float blob_quality(const BuildArgs &g, const float *x
     return fminf(fmaxf(acc, 0.0f), 1.0f);
 }
 
+// The same quality in float64 on a float64 point (float32 blob parameters
+// widened exactly), summed in blob order and clamped: the definition the
+// per-edge drift and the relocalisation flag are evaluated with, rounded to
+// float32 only at the end by the caller.
+__device__ __forceinline__ double blob_quality_f64(const BuildArgs &g, const double *x) {
+    double acc = 0.0;
+    for (int j = 0; j < g.nblob; ++j) {
+        double d2 = 0.0;
+        for (int k = 0; k < g.dim; ++k) {
+            const double t = x[k] - (double)g.mu[j * g.dim + k];
+            d2 = d2 + t * t;
+        }
+        const double s = (double)g.sig[j];
+        acc = acc + (double)g.amp[j] * exp(-d2 / (2.0 * (s * s)));
+    }
+    return fmin(fmax(acc, 0.0), 1.0);
+}
+
 __global__ void k_near_count(BuildArgs g, int *cnt);
 __global__ void k_near_fill(BuildArgs g, const int *off, int *cand_u, int *cand_v,
                             float *cand_c);

@@ -141,8 +141,10 @@ __global__ void __launch_bounds__(256) k_row_ptr(int n, long long m, const int *
 }
 
 // drift of edge row u -> col[e]: sum_j (len/K)(1 - q(mid_j)) over the K
-// sub-step midpoints of the id-ordered pair (a, b) (the same value for both
-// directions of an edge).
+// sub-step midpoints x_a + ((j + 1/2)/K)(x_b - x_a) of the id-ordered pair
+// (a, b) (the same value for both directions of an edge), evaluated in
+// float64 in j order from the float32 positions and length and rounded once
+// to float32.
 __global__ void __launch_bounds__(256) k_edge_drift(BuildArgs g, int n, const int *row_ptr,
                                                     const int *col, const float *cost,
                                                     float *drift) {
@@ -170,24 +172,24 @@ __global__ void __launch_bounds__(256) k_edge_drift(BuildArgs g, int n, const in
     {
         const int v = col[e];
         const int a = min(u, v), b = max(u, v);
-        float xa[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};
+        double xa[3] = {0.0, 0.0, 0.0}, df[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < g.dim; ++k) {
-            xa[k] = g.pos[a * g.dim + k];
-            df[k] = g.pos[b * g.dim + k] - xa[k];
+            xa[k] = (double)g.pos[a * g.dim + k];
+            df[k] = (double)g.pos[b * g.dim + k] - xa[k];
         }
         const float len = cost[e];
         int K = (int)ceilf(len / g.step);
         if (K < 1) K = 1;
-        const float fK = (float)K;
-        const float w = len / fK;
-        float acc = 0.0f;
+        const double dK = (double)K;
+        const double w = (double)len / dK;
+        double acc = 0.0;
         for (int j = 0; j < K; ++j) {
-            const float s = ((float)j + 0.5f) / fK;
-            float p[3];
+            const double s = ((double)j + 0.5) / dK;
+            double p[3];
             for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + s * df[k];
-            acc = acc + w * (1.0f - blob_quality(gl, p));
+            acc = acc + w * (1.0 - blob_quality_f64(gl, p));
         }
-        drift[e] = acc;
+        drift[e] = (float)acc;
     }
 }
 
@@ -195,9 +197,13 @@ __global__ void __launch_bounds__(256) k_node_flags(BuildArgs g, uint8_t *flag) 
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.n) return;
     float x[3] = {0.f, 0.f, 0.f};
-    for (int k = 0; k < g.dim; ++k) x[k] = g.pos[v * g.dim + k];
+    double xd[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < g.dim; ++k) {
+        x[k] = g.pos[v * g.dim + k];
+        xd[k] = (double)x[k];
+    }
     uint8_t f = 0;
-    if (blob_quality(g, x) > g.reset_q) f |= 1u;
+    if (blob_quality_f64(g, xd) > (double)g.reset_q) f |= 1u;
     float gg[3] = {g.goal[0], g.goal[1], g.goal[2]};
     const float r = g.goal_r;
     if (sqdist(gg, x, g.dim) <= r * r) f |= 2u;

@@ -551,6 +551,7 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
             return fail(MPAP_ERR_INVAL, "block_threads must be 0, 256, 512 or 1024");
         if (x.block_threads != 0) p.block_threads = x.block_threads;
         if (x.wave_min_targets != 0) p.wave_min_targets = x.wave_min_targets;
+        if (x.skip != 0 && x.skip != 1) return fail(MPAP_ERR_INVAL, "skip must be 0 or 1");
     }
     if (p.max_waves <= 0) p.max_waves = 1 << 18;
     if (nsp == 1 && nq > 1) {
@@ -563,6 +564,7 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
     p.nobj.resize(nq);
     p.root.resize(nq);
     p.heur.resize(nq);
+    p.skip.resize(nq);
     for (int q = 0; q < nq; ++q) {
         const mpap_search_params &x = sp[nsp == 1 ? 0 : q];
         p.beta[q] = x.beta;
@@ -570,6 +572,7 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
         p.nobj[q] = x.n_obj;
         p.root[q] = g->qoff_h[q] + x.init_node;
         p.heur[q] = x.heuristic;
+        p.skip[q] = x.skip;
     }
     return MPAP_OK;
 }
@@ -629,7 +632,11 @@ int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(w->qbeta, p.beta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w->qdelta, p.delta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w->qnobj, p.nobj.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w->qroot, p.root.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    // a skipped query's root is not seeded (-1)
+    std::vector<int> root(p.root);
+    for (size_t q = 0; q < nq; ++q)
+        if (q < p.skip.size() && p.skip[q]) root[q] = -1;
+    HIP_TRY(hipMemcpyAsync(w->qroot, root.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     return MPAP_OK;
 }
@@ -674,6 +681,13 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
     res->qbeta = p.beta;
     res->qnobj = p.nobj;
     res->qheur = p.heur;
+    res->qdelta = p.delta;
+    res->qroot = p.root;
+    res->max_waves = p.max_waves;
+    res->near_scan = p.near_scan;
+    res->stage_cap = p.stage_cap;
+    res->block_threads = p.block_threads;
+    res->wave_min_targets = p.wave_min_targets;
     res->front_off.assign(nq + 1, 0);
     for (int q = 0; q < nq; ++q) res->front_off[q + 1] = res->front_off[q] + counts[q];
     const long long tot = res->front_off[nq];
@@ -823,6 +837,34 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
     return MPAP_OK;
 }
 
+int acquire_workspace(mpap_graph *g, const SearchShape &L, Workspace **out) {
+    *out = nullptr;
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (!g->spare.empty()) {
+            w = g->spare.back();
+            g->spare.pop_back();
+        }
+    }
+    if (w && w->nblocks != L.nblocks) {
+        w->free_all();
+        delete w;
+        w = nullptr;
+    }
+    if (!w) {
+        w = new Workspace();
+        const int r = ws_alloc_nodes(w, g->n, L.nblocks);
+        if (r) {
+            w->free_all();
+            delete w;
+            return r;
+        }
+    }
+    *out = w;
+    return MPAP_OK;
+}
+
 extern "C" {
 
 int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_t nsp,
@@ -842,26 +884,7 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     Workspace *w = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g->mu);
-        if (!g->spare.empty()) {
-            w = g->spare.back();
-            g->spare.pop_back();
-        }
-    }
-    if (w && w->nblocks != L.nblocks) {
-        w->free_all();
-        delete w;
-        w = nullptr;
-    }
-    if (!w) {
-        w = new Workspace();
-        if ((r = ws_alloc_nodes(w, g->n, L.nblocks))) {
-            w->free_all();
-            delete w;
-            return r;
-        }
-    }
+    if ((r = acquire_workspace(g, L, &w))) return r;
     mpap_result *res = new mpap_result();
     res->g = g;
     res->ws = w;
@@ -921,6 +944,18 @@ int mpap_node_front(const mpap_result *r, int32_t node, float *cost, float *drif
                     float *maxdrift, int32_t *label_id, int32_t capacity, int32_t *count) {
     if (!r || !count) return fail(MPAP_ERR_INVAL, "null result or count");
     if (node < 0 || node >= r->g->n) return fail(MPAP_ERR_INVAL, "node out of range");
+    if (r->fallback) {
+        // a query the judge rejected is answered by the analytic re-search
+        const auto &qo = r->g->qoff_h;
+        const int q = (int)(std::upper_bound(qo.begin(), qo.end(), node) - qo.begin()) - 1;
+        if (q >= 0 && q < (int)r->qfall.size() && r->qfall[q]) {
+            const int st = mpap_node_front(r->fallback, node, cost, drift, maxdrift, label_id,
+                                           capacity, count);
+            if (st == MPAP_OK && label_id)
+                for (int i = 0; i < *count; ++i) label_id[i] += (int32_t)r->id_offset;
+            return st;
+        }
+    }
     int4 nbv;
     HIP_TRY(hipMemcpy(&nbv, r->ws->nb + node, sizeof(int4), hipMemcpyDeviceToHost));
     *count = nbv.z;
@@ -942,6 +977,9 @@ int mpap_label_path(const mpap_result *rc, int32_t label_id, int32_t *nodes, int
                     int32_t *length) {
     mpap_result *r = const_cast<mpap_result *>(rc);
     if (!r || !length) return fail(MPAP_ERR_INVAL, "null result or length");
+    if (r->fallback && label_id >= r->id_offset)
+        return mpap_label_path(r->fallback, (int32_t)(label_id - r->id_offset), nodes, capacity,
+                               length);
     const long long L = r->stats.labels_expanded;
     if (label_id < 0 || label_id >= L) return fail(MPAP_ERR_INVAL, "label id out of range");
     if (!r->arena_loaded) {
@@ -979,6 +1017,8 @@ int mpap_result_stats(const mpap_result *r, mpap_stats *out) {
 
 void mpap_result_free(mpap_result *r) {
     if (!r) return;
+    if (r->fallback) mpap_result_free(r->fallback);
+    r->fallback = nullptr;
     if (r->ws_borrowed) {
         // the workspace belongs to a plan
     } else if (r->ws && r->g) {

@@ -26,6 +26,7 @@ struct mpap_plan {
     std::vector<mpap_graph *> parts;
     std::vector<const mpap_surrogate *> models;
     std::vector<long long> eoff;  // first edge of each part in the batch graph
+    bool analytic = false;        // parts without a model: analytic drift recomputed
     SearchArgs args{};
     GoalArgs gargs{};
     hipGraph_t graph = nullptr;
@@ -113,8 +114,12 @@ int plan_record(mpap_plan *p) {
     hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (he != hipSuccess) r = fail(MPAP_ERR_HIP, hipGetErrorString(he));
     if (!r) {
-        for (size_t q = 0; q < p->models.size() && !r; ++q)
-            if (p->models[q]) r = sur_enqueue_score(p->models[q], p->parts[q], g->sdrift + p->eoff[q], cs);
+        for (size_t q = 0; q < p->models.size() && !r; ++q) {
+            if (p->models[q])
+                r = sur_enqueue_score(p->models[q], p->parts[q], g->sdrift + p->eoff[q], cs);
+            else if (p->analytic)
+                r = enqueue_analytic_drift(p->parts[q], g->odrift + p->eoff[q], cs);
+        }
         if (!r) {
             k_search_init<<<div_up(g->n, 256), 256, 0, cs>>>(a);
             k_search_roots<<<div_up(nq, 256), 256, 0, cs>>>(a);
@@ -214,15 +219,17 @@ extern "C" {
 
 int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
                      mpap_graph *const *parts, const mpap_surrogate *const *models,
-                     int32_t nparts, void *stream, mpap_plan **out) {
+                     int32_t nparts, int32_t flags, void *stream, mpap_plan **out) {
     if (!out) return fail(MPAP_ERR_INVAL, "out is null");
     *out = nullptr;
     if (!g || !sp) return fail(MPAP_ERR_INVAL, "null graph or params");
+    if (flags & ~MPAP_PLAN_ANALYTIC) return fail(MPAP_ERR_INVAL, "unknown plan flags");
     if (nparts != 0 && nparts != g->nq)
         return fail(MPAP_ERR_INVAL, "nparts must be 0 or the graph's query count");
     if (nparts > 0 && (!parts || !models)) return fail(MPAP_ERR_INVAL, "null parts or models");
     mpap_plan *p = new mpap_plan();
     p->g = g;
+    p->analytic = (flags & MPAP_PLAN_ANALYTIC) != 0;
     int r = search_prep(g, sp, nsp, p->prep);
     if (!r) r = search_shape(p->prep.stage_cap, p->prep.block_threads, p->prep.wave_min_targets,
                              p->shape);
@@ -244,17 +251,19 @@ int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
                 return bail(fail(MPAP_ERR_INVAL, "a part's node count differs from its query's"));
             p->eoff[q] = eo;
             eo += pq->e;
-            if (models[q]) {
-                scoring = true;
+            if (models[q] || p->analytic) {
+                scoring = scoring || models[q] != nullptr;
                 if (!pq->pos || !pq->symmetric_alias)
                     return bail(fail(MPAP_ERR_INVAL, "a scored part needs its environment "
                                                      "(mpap_build_graph)"));
             }
         }
         if (eo != g->e) return bail(fail(MPAP_ERR_INVAL, "the parts' edges do not add up"));
+    } else if (p->analytic) {
+        return bail(fail(MPAP_ERR_INVAL, "MPAP_PLAN_ANALYTIC needs the parts"));
     }
-    if (scoring && !g->symmetric_alias)
-        return bail(fail(MPAP_ERR_INVAL, "the surrogate drift needs a symmetric roadmap"));
+    if ((scoring || p->analytic) && !g->symmetric_alias)
+        return bail(fail(MPAP_ERR_INVAL, "scoring inside a plan needs a symmetric roadmap"));
     if (scoring && !g->sdrift && (r = dalloc(&g->sdrift, std::max<long long>(g->e, 1))))
         return bail(r);
     for (int q = 0; q < p->prep.nq; ++q)
@@ -262,8 +271,12 @@ int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
             return bail(fail(MPAP_ERR_INVAL, "no surrogate drift on this graph"));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // score once eagerly so the sizing search sees the same drift
-    for (int q = 0; q < nparts && !r; ++q)
-        if (models[q]) r = sur_enqueue_score(models[q], parts[q], g->sdrift + p->eoff[q], s);
+    for (int q = 0; q < nparts && !r; ++q) {
+        if (models[q])
+            r = sur_enqueue_score(models[q], parts[q], g->sdrift + p->eoff[q], s);
+        else if (p->analytic)
+            r = enqueue_analytic_drift(parts[q], g->odrift + p->eoff[q], s);
+    }
     if (r) return bail(r);
     p->w = new Workspace();
     if ((r = ws_alloc_nodes(p->w, g->n, p->shape.nblocks))) return bail(r);

@@ -317,6 +317,18 @@ struct mpap_result {
     std::vector<int2> arena_host;  // filled on first mpap_label_path
     bool arena_loaded = false;
     bool ws_borrowed = false;  // ws belongs to a plan (valid until its next run)
+    // the parameters the search ran with (the judge's fallback re-search uses them)
+    std::vector<float> qdelta;
+    std::vector<int> qroot;
+    int max_waves = 0, near_scan = 16, stage_cap = 0, block_threads = 1024;
+    int wave_min_targets = 0;
+    // judge of a search on the learned drift: queries whose front it rejected
+    // are answered by an analytic re-search (fallback), whose label ids are
+    // reported shifted by id_offset
+    bool judged = false;
+    mpap_result *fallback = nullptr;
+    std::vector<uint8_t> qfall;
+    long long id_offset = 0;
 };
 
 // ------------------------------------------------------ search preparation
@@ -328,6 +340,7 @@ struct SearchPrep {
     int wave_min_targets = 0;  // 0: default; < 0: never merge by single waves
     std::vector<float> beta;
     std::vector<int> nobj, root, heur;
+    std::vector<int> skip;  // 1: the query is not searched (its root is not seeded)
 };
 // Launch shape of the persistent search kernel.
 struct SearchShape {
@@ -347,6 +360,8 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
                  hipStream_t s, mpap_result *res);
 SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
                        const SearchShape &L);
+// A search workspace of g for launch shape L (a spare one when it fits).
+int acquire_workspace(mpap_graph *g, const SearchShape &L, Workspace **out);
 GoalArgs goal_args(const mpap_graph *g, Workspace *w);
 // The search kernel build for a launch on g: with single-wave merges only
 // when some iteration can have wmin targets (or the caller asked for them).
@@ -365,4 +380,7 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
 // stream, writing the drift to out[e]; used by plans and mpap_surrogate_score.
 struct mpap_surrogate;
 int sur_enqueue_score(const mpap_surrogate *s, mpap_graph *g, float *out, hipStream_t st);
+// The analytic drift of every edge of g (built by mpap_build_graph) enqueued
+// on a stream, written to out[e] (forward edge order).
+int enqueue_analytic_drift(const mpap_graph *g, float *out, hipStream_t st);
 

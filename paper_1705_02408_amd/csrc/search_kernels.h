@@ -129,11 +129,13 @@ struct GoalArgs {
 };
 
 __global__ void k_search_init(SearchArgs a);
-// analytic re-walk of labels' plans (surrogate check): out = {c, d, m, feasible}
+// analytic re-walk of labels' plans (surrogate check): out = {c, d, m, feasible};
+// with sur (nullable) also the judge's per-label decision pass[i]
 __global__ void k_rescore(const int2 *arena, const int *optr, const int *ocol,
                           const float *ocost, const float *odrift, const uint8_t *nflag,
                           const int *lab, const float *beta, const int *nobj, int n, int *path,
-                          int maxlen, float4 *out, int *err);
+                          int maxlen, float4 *out, int *err, const float4 *sur, float tol,
+                          uint8_t *pass);
 __global__ void k_search_roots(SearchArgs a);
 __global__ void k_search(SearchArgs a);
 __global__ void k_search_wave(SearchArgs a);  // with single-wave merges

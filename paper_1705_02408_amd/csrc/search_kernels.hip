@@ -1179,6 +1179,10 @@ __global__ void __launch_bounds__(256) k_search_roots(SearchArgs a) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.nq) return;
     const int r = a.qroot[q];
+    if (r < 0) {  // a query left out of this launch
+        a.qlast[q] = -1;
+        return;
+    }
     a.nb[r] = make_int4(16 * q, 16, 1, 1);
     a.minopen[r] = 0.0f;
     a.pool[(size_t)16 * q] = make_float4(0.f, 0.f, 0.f, __uint_as_float(MPAP_OPEN_BIT));
@@ -1584,12 +1588,16 @@ __global__ void __launch_bounds__(256) k_goal_pack(GoalArgs g, float4 *plab, int
 // of a search run on the learned surrogate's drift): thread i follows the
 // parent chain of label lab[i] back to its root, then folds cost, drift
 // (bound on the pre-reset drift, relocalisation) and max drift forward.
+// With sur (the searched values of the labels) the thread also decides the
+// judge: feasible, and drift and max drift within tol of the analytic ones
+// relative to max(analytic, 1e-3 beta), compared in float64 -> pass[i].
 __global__ void __launch_bounds__(256) k_rescore(const int2 *arena, const int *optr,
                                                  const int *ocol, const float *ocost,
                                                  const float *odrift, const uint8_t *nflag,
                                                  const int *lab, const float *beta,
                                                  const int *nobj, int n, int *path, int maxlen,
-                                                 float4 *out, int *err) {
+                                                 float4 *out, int *err, const float4 *sur,
+                                                 float tol, uint8_t *pass) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int *pth = path + (size_t)i * maxlen;
@@ -1603,6 +1611,7 @@ __global__ void __launch_bounds__(256) k_rescore(const int2 *arena, const int *o
     if (id >= 0) {
         atomicOr(err, 1);
         out[i] = make_float4(MPAP_INF, MPAP_INF, MPAP_INF, 0.f);
+        if (pass) pass[i] = 0;
         return;
     }
     float c = 0.f, d = 0.f, m = 0.f;
@@ -1626,4 +1635,11 @@ __global__ void __launch_bounds__(256) k_rescore(const int2 *arena, const int *o
         m = (nobj[i] >= 3) ? fmaxf(m, dpre) : 0.0f;
     }
     out[i] = make_float4(c, d, m, ok ? 1.f : 0.f);
+    if (pass) {
+        const float4 s = sur[i];
+        const double floor = 1e-3 * (double)beta[i];
+        const double ed = fabs((double)s.y - (double)d) / fmax((double)d, floor);
+        const double em = fabs((double)s.z - (double)m) / fmax((double)m, floor);
+        pass[i] = (ok && ed <= (double)tol && em <= (double)tol) ? 1 : 0;
+    }
 }

@@ -362,10 +362,14 @@ __global__ void __launch_bounds__(256) k_steer_compact(int n, int k_out, const i
 }
 
 // one wave per source row: drift = sum over the K chords of the checked
-// points of |chord| (1 - q(chord midpoint)); elen = sum of |chord|
+// points of |chord| (1 - q(chord midpoint)), the terms in float64 from the
+// float32 check points, summed in chord order and rounded once to float32;
+// elen = float32 sum of |chord| (the trajectory length of the surrogate's
+// inputs)
 __global__ void __launch_bounds__(64) k_traj_drift(SteerArgs a, const int *row_ptr,
                                                    const int *col, float *drift, float *elen) {
     extern __shared__ float blob[];
+    __shared__ double term[kSteerMaxSteps + 1];
     for (int i = threadIdx.x; i < 3 * a.nblob; i += blockDim.x) blob[i] = a.mu[i];
     for (int i = threadIdx.x; i < a.nblob; i += blockDim.x) {
         blob[3 * a.nblob + i] = a.sig[i];
@@ -389,24 +393,31 @@ __global__ void __launch_bounds__(64) k_traj_drift(SteerArgs a, const int *row_p
         load3(a.pos, col[e], p1);
         load3(a.vel, col[e], v1);
         (void)steer3(p0, v0, p1, v1, a.T, c0, c1);
-        float acc = 0.0f, len = 0.0f;
+        float len = 0.0f;
         for (int k = l; k < a.K; k += 64) {
-            float pa[3], pb[3], mid[3];
+            float pa[3], pb[3];
             traj_at(p0, v0, c0, c1, check_time(k, a.T, a.K), pa, nullptr);
             traj_at(p0, v0, c0, c1, check_time(k + 1, a.T, a.K), pb, nullptr);
-            const float dx = pb[0] - pa[0], dy = pb[1] - pa[1], dz = pb[2] - pa[2];
-            const float ln = sqrtf((dx * dx + dy * dy) + dz * dz);
+            const float fx = pb[0] - pa[0], fy = pb[1] - pa[1], fz = pb[2] - pa[2];
+            len = len + sqrtf((fx * fx + fy * fy) + fz * fz);
+            double sq = 0.0, mid[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) mid[d] = (pa[d] + pb[d]) * 0.5f;
-            acc = acc + ln * (1.0f - blob_quality(q, mid));
-            len = len + ln;
+            for (int d = 0; d < 3; ++d) {
+                const double t = (double)pb[d] - (double)pa[d];
+                sq = sq + t * t;
+                mid[d] = 0.5 * ((double)pb[d] + (double)pa[d]);
+            }
+            term[k] = sqrt(sq) * (1.0 - blob_quality_f64(q, mid));
         }
-        acc = wave_sum(acc);
         len = wave_sum(len);
+        __syncthreads();
         if (l == 0) {
-            drift[e] = acc;
+            double acc = 0.0;
+            for (int k = 0; k < a.K; ++k) acc = acc + term[k];
+            drift[e] = (float)acc;
             if (elen) elen[e] = len;
         }
+        __syncthreads();
     }
 }
 

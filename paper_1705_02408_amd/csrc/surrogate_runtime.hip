@@ -168,6 +168,18 @@ double unit(uint64_t key, uint64_t i) {
     return ((double)(sm64(key + (i + 1) * 0x9E3779B97F4A7C15ull) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
 }
 
+// 32-bit FNV-1a of a byte range (the check word of saved parameters)
+uint32_t fnv1a(const void *data, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(data);
+    uint32_t h = 2166136261u;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 16777619u;
+    }
+    return h;
+}
+constexpr char kSurMagic[8] = {'M', 'P', 'A', 'P', 'S', 'U', 'R', '1'};
+
 }  // namespace
 
 extern "C" {
@@ -240,6 +252,43 @@ int mpap_surrogate_init(mpap_surrogate *s, uint64_t seed) {
     for (int i = 0; i < kMlpIn * kMlpH; ++i) p[kOffW1 + i] = (float)(normal() * std::sqrt(2.0 / kMlpIn));
     for (int i = 0; i < kMlpH * kMlpH; ++i) p[kOffW2 + i] = (float)(normal() * std::sqrt(2.0 / kMlpH));
     // output layer zero: an untrained network predicts exactly the 8-point base
+    return mpap_surrogate_set_params(s, p.data(), kMlpParams);
+}
+
+int mpap_surrogate_save(const mpap_surrogate *s, const char *path) {
+    if (!s || !path) return fail(MPAP_ERR_INVAL, "null argument");
+    std::vector<float> p(kMlpParams);
+    HIP_TRY(hipMemcpy(p.data(), s->p, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    const uint32_t h = fnv1a(p.data(), sizeof(float) * kMlpParams);
+    const int32_t cnt = kMlpParams;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(MPAP_ERR_INVAL, std::string("cannot open ") + path + " for writing");
+    bool ok = std::fwrite(kSurMagic, 1, 8, f) == 8 && std::fwrite(&cnt, 4, 1, f) == 1 &&
+              std::fwrite(p.data(), sizeof(float), kMlpParams, f) == (size_t)kMlpParams &&
+              std::fwrite(&h, 4, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(MPAP_ERR_INVAL, std::string("cannot write ") + path);
+    return MPAP_OK;
+}
+
+int mpap_surrogate_load(mpap_surrogate *s, const char *path) {
+    if (!s || !path) return fail(MPAP_ERR_INVAL, "null argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(MPAP_ERR_INVAL, std::string("cannot open ") + path);
+    char magic[8] = {};
+    int32_t cnt = 0;
+    uint32_t h = 0;
+    std::vector<float> p(kMlpParams);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kSurMagic, 8) == 0 &&
+              std::fread(&cnt, 4, 1, f) == 1 && cnt == kMlpParams &&
+              std::fread(p.data(), sizeof(float), kMlpParams, f) == (size_t)kMlpParams &&
+              std::fread(&h, 4, 1, f) == 1;
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the hash
+    std::fclose(f);
+    if (!ok) return fail(MPAP_ERR_INVAL, std::string("not a surrogate parameter file: ") + path);
+    if (h != fnv1a(p.data(), sizeof(float) * kMlpParams))
+        return fail(MPAP_ERR_INVAL, std::string("parameter hash mismatch in ") + path);
     return mpap_surrogate_set_params(s, p.data(), kMlpParams);
 }
 
@@ -397,31 +446,21 @@ int mpap_analytic_drift(mpap_graph *g, void *stream, float *ms) {
     if (!g) return fail(MPAP_ERR_INVAL, "null graph");
     if (!g->pos) return fail(MPAP_ERR_INVAL, "graph has no environment (build it with mpap_build_graph)");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    BuildArgs a{};
-    a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu;
-    a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
-    a.reset_q = g->reset_q;
-    const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    if (g->n > 0 && g->dim == 6)
-        k_traj_drift<<<g->n, 64, sizeof(float) * 5 * (size_t)g->nblob, st>>>(
-            steer_view(g), g->optr, g->ocol, g->odrift, nullptr);
-    else if (g->n > 0)
-        if (g->e > 0)
-            k_edge_drift<<<div_up(g->e, 256), 256, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost,
-                                                              g->odrift);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipEventSynchronize(e1));
-    float t = 0.f;
-    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    if (ms) *ms = t;
+    int r = enqueue_analytic_drift(g, g->odrift, st);
+    if (r == MPAP_OK) {
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (ms) *ms = t;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return MPAP_OK;
+    return r;
 }
 
 int mpap_graph_drift(const mpap_graph *g, int32_t which, float *out) {
@@ -429,66 +468,6 @@ int mpap_graph_drift(const mpap_graph *g, int32_t which, float *out) {
     const float *src = which == 0 ? g->odrift : g->sdrift;
     if (!src) return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph");
     if (g->e > 0) HIP_TRY(hipMemcpy(out, src, sizeof(float) * g->e, hipMemcpyDeviceToHost));
-    return MPAP_OK;
-}
-
-int mpap_rescore_front(const mpap_result *r, int32_t query, float *cost, float *drift,
-                       float *maxdrift, uint8_t *feasible, int32_t capacity, int32_t *count) {
-    if (!r || !count) return fail(MPAP_ERR_INVAL, "null argument");
-    const int nq = r->g->nq;
-    if (query < -1 || query >= nq) return fail(MPAP_ERR_INVAL, "query out of range");
-    const int q0 = query < 0 ? 0 : query, q1 = query < 0 ? nq : query + 1;
-    const int64_t o = r->front_off[q0];
-    const int n = (int)(r->front_off[q1] - o);
-    *count = n;
-    if (capacity < n) return fail(MPAP_ERR_CAPACITY, "capacity below the front size");
-    if (n == 0) return MPAP_OK;
-    std::vector<int> lab(n), nobj(n);
-    std::vector<float> beta(n);
-    for (int q = q0; q < q1; ++q)
-        for (int64_t i = r->front_off[q]; i < r->front_off[q + 1]; ++i) {
-            std::memcpy(&lab[i - o], &r->front[i].w, sizeof(int));
-            beta[i - o] = r->qbeta[q];
-            nobj[i - o] = r->qnobj[q];
-        }
-    const int maxlen = 4096;
-    int *dlab = nullptr, *dnobj = nullptr, *dpath = nullptr, *derr = nullptr;
-    float *dbeta = nullptr;
-    float4 *dout = nullptr;
-    int rc;
-    auto cleanup = [&]() {
-        dfree(dlab); dfree(dnobj); dfree(dpath); dfree(derr); dfree(dbeta); dfree(dout);
-    };
-    if ((rc = dalloc(&dlab, n)) || (rc = dalloc(&dnobj, n)) || (rc = dalloc(&dbeta, n)) ||
-        (rc = dalloc(&dpath, (size_t)n * maxlen)) || (rc = dalloc(&derr, 1)) ||
-        (rc = dalloc(&dout, n))) {
-        cleanup();
-        return rc;
-    }
-    const mpap_graph *g = r->g;
-    std::vector<float4> out(n);
-    int err = 0;
-    hipError_t he = hipMemcpy(dlab, lab.data(), sizeof(int) * n, hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMemcpy(dnobj, nobj.data(), sizeof(int) * n, hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMemcpy(dbeta, beta.data(), sizeof(float) * n, hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMemcpy(derr, &err, sizeof(int), hipMemcpyHostToDevice);
-    if (he == hipSuccess) {
-        k_rescore<<<div_up(n, 256), 256>>>(r->ws->arena, g->optr, g->ocol, g->ocost, g->odrift,
-                                          g->nflag, dlab, dbeta, dnobj, n, dpath, maxlen, dout,
-                                          derr);
-        he = hipGetLastError();
-    }
-    if (he == hipSuccess) he = hipMemcpy(out.data(), dout, sizeof(float4) * n, hipMemcpyDeviceToHost);
-    if (he == hipSuccess) he = hipMemcpy(&err, derr, sizeof(int), hipMemcpyDeviceToHost);
-    cleanup();
-    if (he != hipSuccess) return fail(MPAP_ERR_HIP, hipGetErrorString(he));
-    if (err) return fail(MPAP_ERR_HIP, "a plan could not be re-walked (longer than 4096 steps?)");
-    for (int i = 0; i < n; ++i) {
-        if (cost) cost[i] = out[i].x;
-        if (drift) drift[i] = out[i].y;
-        if (maxdrift) maxdrift[i] = out[i].z;
-        if (feasible) feasible[i] = out[i].w > 0.5f ? 1 : 0;
-    }
     return MPAP_OK;
 }
 
@@ -508,6 +487,25 @@ int sur_enqueue_score(const mpap_surrogate *s, mpap_graph *g, float *out, hipStr
             // in-edge order for the search of a directed roadmap
             k_gather_f32<<<div_up(g->e, 256), 256, 0, st>>>(g->e, g->rperm, g->sdrift, g->srdrift);
         }
+    }
+    HIP_TRY(hipGetLastError());
+    return MPAP_OK;
+}
+
+int enqueue_analytic_drift(const mpap_graph *g, float *out, hipStream_t st) {
+    if (!g || !out) return fail(MPAP_ERR_INVAL, "null argument");
+    if (!g->pos) return fail(MPAP_ERR_INVAL, "graph has no environment (build it with mpap_build_graph)");
+    if (g->n > 0 && g->dim == 6) {
+        k_traj_drift<<<g->n, 64, sizeof(float) * 5 * (size_t)g->nblob, st>>>(
+            steer_view(g), g->optr, g->ocol, out, nullptr);
+    } else if (g->n > 0 && g->e > 0) {
+        BuildArgs a{};
+        a.n = g->n; a.dim = g->dim; a.pos = g->pos; a.nblob = g->nblob; a.mu = g->bmu;
+        a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
+        a.reset_q = g->reset_q;
+        const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
+        k_edge_drift<<<div_up(g->e, 256), 256, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost,
+                                                          out);
     }
     HIP_TRY(hipGetLastError());
     return MPAP_OK;

@@ -24,6 +24,7 @@ MPAP_ERR_OVERFLOW = 5
 MPAP_ERR_NOCONVERGE = 6
 MPAP_ERR_CAPACITY = 7
 MPAP_ERR_DEVICE = 8
+MPAP_PLAN_ANALYTIC = 1
 
 
 class MpapError(RuntimeError):
@@ -54,7 +55,7 @@ class mpap_search_params(ctypes.Structure):
                 ("init_node", ctypes.c_int32), ("max_waves", ctypes.c_int32),
                 ("near_scan", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
                 ("heuristic", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("wave_min_targets", ctypes.c_int32)]
+                ("wave_min_targets", ctypes.c_int32), ("skip", ctypes.c_int32)]
 
 
 class mpap_stats(ctypes.Structure):
@@ -63,7 +64,8 @@ class mpap_stats(ctypes.Structure):
                 ("merges", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("relaxations", ctypes.c_int64), ("gpu_ms", ctypes.c_float),
                 ("lds_front_cap", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("max_front", ctypes.c_int32), ("wave_build", ctypes.c_int32)]
+                ("max_front", ctypes.c_int32), ("wave_build", ctypes.c_int32),
+                ("judged_failed", ctypes.c_int32), ("fallback_ms", ctypes.c_float)]
 
 
 SYMBOLS = [
@@ -77,6 +79,7 @@ SYMBOLS = [
     "mpap_surrogate_forward", "mpap_surrogate_gradient", "mpap_surrogate_train",
     "mpap_surrogate_score", "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
     "mpap_plan_create", "mpap_plan_run", "mpap_plan_info", "mpap_plan_free",
+    "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load",
 ]
 
 _lib = None
@@ -128,9 +131,12 @@ def load(path: str = LIB_PATH):
     lib.mpap_graph_drift.argtypes = [P, I32, P]
     lib.mpap_analytic_drift.argtypes = [P, P, P]
     lib.mpap_rescore_front.argtypes = [P, I32, P, P, P, P, I32, P]
-    lib.mpap_plan_create.argtypes = [P, P, I32, P, P, I32, P, ctypes.POINTER(P)]
+    lib.mpap_plan_create.argtypes = [P, P, I32, P, P, I32, I32, P, ctypes.POINTER(P)]
     lib.mpap_plan_run.argtypes = [P, P, ctypes.POINTER(P)]
     lib.mpap_plan_info.argtypes = [P, P, P, P]
+    lib.mpap_judge.argtypes = [P, ctypes.c_float, I32, P, P, P]
+    lib.mpap_surrogate_save.argtypes = [P, ctypes.c_char_p]
+    lib.mpap_surrogate_load.argtypes = [P, ctypes.c_char_p]
     lib.mpap_plan_free.argtypes = [P]
     lib.mpap_plan_free.restype = None
     lib.mpap_result_free.argtypes = [P]
@@ -147,7 +153,8 @@ def load(path: str = LIB_PATH):
                  "mpap_surrogate_set_params", "mpap_surrogate_get_params",
                  "mpap_surrogate_init", "mpap_edge_features", "mpap_surrogate_forward",
                  "mpap_surrogate_gradient", "mpap_surrogate_train", "mpap_surrogate_score",
-                 "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift"):
+                 "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
+                 "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -296,6 +303,9 @@ class Result:
     def wave_trace(self) -> np.ndarray:
         return mpap_wave_trace(self)
 
+    def judge(self, tol: float = 1e-2, fallback: bool = True, stream=None) -> np.ndarray:
+        return mpap_judge(self, tol, fallback, stream)
+
     def close(self):
         if self.handle:
             load().mpap_result_free(self.handle)
@@ -311,10 +321,11 @@ class Result:
 def search_params(beta: float, n_obj: int, radius: float, lam: float = 0.5,
                   init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
                   stage_cap: int = 0, heuristic: int = 0, block_threads: int = 0,
-                  wave_min_targets: int = 0):
+                  wave_min_targets: int = 0, skip: int = 0):
     return mpap_search_params(float(beta), float(lam), float(radius), int(n_obj),
                               int(init_node), int(max_waves), int(near_scan), int(stage_cap),
-                              int(heuristic), int(block_threads), int(wave_min_targets))
+                              int(heuristic), int(block_threads), int(wave_min_targets),
+                              int(skip))
 
 
 def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float = 0.5,
@@ -486,6 +497,12 @@ class Surrogate:
                                            _stream(stream), _p(loss)))
         return loss[:epochs]
 
+    def save(self, path: str):
+        _check(load().mpap_surrogate_save(self.handle, os.fsencode(path)))
+
+    def load(self, path: str):
+        _check(load().mpap_surrogate_load(self.handle, os.fsencode(path)))
+
     def score(self, graph: Graph, stream=None) -> float:
         ms = ctypes.c_float()
         _check(load().mpap_surrogate_score(self.handle, graph.handle, _stream(stream),
@@ -543,45 +560,17 @@ def mpap_rescore_front(res: Result, query: int = 0) -> dict:
     return dict(cost=c, drift=d, maxdrift=m, feasible=f.astype(bool))
 
 
-def surrogate_judge(res: Result, betas, tol: float = 1e-2) -> list:
-    """surrogate_front_ok for every query of a result, from one re-walk launch."""
-    nq = len(betas)
-    fronts = [mpap_query_goal_front(res, q) for q in range(nq)]
-    rs = mpap_rescore_front(res, -1)
-    out, o = [], 0
-    for q, fr in enumerate(fronts):
-        k = fr.vecs.shape[0]
-        ok = True
-        if k:
-            feas = rs["feasible"][o:o + k]
-            floor = 1e-3 * betas[q]
-            ok = bool(feas.all())
-            for col, key in ((1, "drift"), (2, "maxdrift")):
-                a = rs[key][o:o + k].astype(np.float64)
-                err = np.abs(fr.vecs[:, col].astype(np.float64) - a) / np.maximum(a, floor)
-                ok = ok and bool((err <= tol).all())
-        out.append(ok)
-        o += k
-    return out
-
-
-def surrogate_front_ok(res: Result, query: int, beta: float, tol: float = 1e-2) -> bool:
-    """Judge a search run on the surrogate's drift: every goal-front plan,
-    re-walked with the analytic drift, stays within the bound and its drift
-    (and max drift) differ from the surrogate's by at most tol relative to
-    max(analytic value, 1e-3 beta)."""
-    fr = mpap_query_goal_front(res, query)
-    rs = mpap_rescore_front(res, query)
-    if fr.vecs.shape[0] == 0:
-        return True
-    if not rs["feasible"].all():
-        return False
-    floor = 1e-3 * beta
-    for k, a in ((1, rs["drift"]), (2, rs["maxdrift"])):
-        err = np.abs(fr.vecs[:, k].astype(np.float64) - a) / np.maximum(a, floor)
-        if (err > tol).any():
-            return False
-    return True
+def mpap_judge(res: Result, tol: float = 1e-2, fallback: bool = True, stream=None) -> np.ndarray:
+    """The library's judge of a search on the learned drift (and, with
+    fallback, the analytic re-search of the rejected queries); returns the
+    per-query rejection flags (bool [nq])."""
+    nq = ctypes.c_int32()
+    _check(load().mpap_graph_queries(res.graph.handle, ctypes.byref(nq), None))
+    failed = np.zeros(nq.value, np.uint8)
+    nf = ctypes.c_int32()
+    _check(load().mpap_judge(res.handle, ctypes.c_float(tol), int(bool(fallback)),
+                             _stream(stream), _p(failed), ctypes.byref(nf)))
+    return failed.astype(bool)
 
 
 class Plan:
@@ -590,7 +579,8 @@ class Plan:
     goal fronts, launched with run().  A result of run() reads the plan's
     workspace for per-node queries until the next run()."""
 
-    def __init__(self, graph: Graph, params, parts=None, models=None, stream=None):
+    def __init__(self, graph: Graph, params, parts=None, models=None, stream=None,
+                 analytic: bool = False):
         lib = load()
         if isinstance(params, mpap_search_params):
             params = [params]
@@ -604,7 +594,8 @@ class Plan:
             ma = (ctypes.c_void_p * n)(*[(m.handle if m is not None else None) for m in models])
         self.graph, self.parts, self.models = graph, parts, models
         h = ctypes.c_void_p()
-        _check(lib.mpap_plan_create(graph.handle, arr, len(params), pa, ma, n, _stream(stream),
+        _check(lib.mpap_plan_create(graph.handle, arr, len(params), pa, ma, n,
+                                    MPAP_PLAN_ANALYTIC if analytic else 0, _stream(stream),
                                     ctypes.byref(h)))
         self.handle = h
 

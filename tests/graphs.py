@@ -32,3 +32,29 @@ def load_golden(name):
 
 def as_vecs(rows):
     return np.array(rows, dtype=np.float32).reshape(-1, 3)
+
+
+def load_plain3d_golden():
+    """Stored whole-oracle result of the 3D benchmark workload (seed 0):
+    (summary dict, per-node front sizes int32 [n], per-node 8-byte digests
+    uint8 [n, 8]).  Written by tests/golden/make_plain3d_golden.py."""
+    with open(os.path.join(GOLDEN, "plain3d_s0_front.json")) as f:
+        summary = json.load(f)
+    z = np.load(os.path.join(GOLDEN, "plain3d_s0_fronts.npz"))
+    return summary, z["count"], z["digest"]
+
+
+def front_digest(v) -> bytes:
+    """8-byte BLAKE2b of a front's (c, d, m) float32 rows sorted
+    lexicographically (the digest of the stored whole-oracle result)."""
+    import hashlib
+    v = np.ascontiguousarray(v, dtype=np.float32).reshape(-1, 3)
+    if v.shape[0]:
+        v = v[np.lexsort((v[:, 2], v[:, 1], v[:, 0]))]
+    return hashlib.blake2b(np.ascontiguousarray(v).astype("<f4").tobytes(),
+                           digest_size=8).digest()
+
+
+def array_digest(a) -> str:
+    import hashlib
+    return hashlib.blake2b(np.ascontiguousarray(a).tobytes(), digest_size=16).hexdigest()

@@ -36,11 +36,11 @@ def test_device_build_matches_oracle(built):
     assert np.array_equal(got["col"], ref["col"])
     assert np.array_equal(bits(got["cost"]), bits(ref["cost"]))
     assert np.array_equal(got["goal"], ref["goal"])
-    # drift: float32 device sum of K chord terms vs float64
-    err = np.abs(got["drift"].astype(np.float64) - ref["drift"].astype(np.float64))
-    assert np.all(err <= 1e-5 * ref["drift"] + 1e-6), float(err.max())
-    clear = np.abs(ref["q"] - env.reset_q) > 1e-4
-    assert np.array_equal(got["reset"][clear], ref["reset"][clear])
+    # drift: float64 chord terms summed in chord order, rounded once, as the
+    # oracle does; relocalisation from the float64 q: the same bits
+    bad = np.nonzero(bits(got["drift"]) != bits(ref["drift"]))[0]
+    assert bad.size == 0, (bad.size, bad[:8])
+    assert np.array_equal(got["reset"], ref["reset"])
 
 
 @pytest.mark.parametrize("seed,n", [(1, 1200), (2, 2000)])
@@ -59,9 +59,11 @@ def test_search_on_oracle_arrays_matches_oracle(seed, n):
     dg.close()
 
 
-def test_search_on_device_built_roadmap_matches_oracle_on_same_arrays(built):
-    env, _, dg = built
-    g = dg.export()
+def test_search_on_device_built_roadmap_matches_oracle(built):
+    """The search on the library's own roadmap against the oracle search of
+    the oracle's roadmap (the two roadmaps are the same bits, checked
+    above)."""
+    env, g, dg = built
     ref = osearch.search(g, env.beta, env.n_obj)
     res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam)
     check_against_oracle(g, res, ref, env.beta, env.n_obj, all_nodes=False, node_stride=4)
@@ -69,8 +71,7 @@ def test_search_on_device_built_roadmap_matches_oracle_on_same_arrays(built):
 
 
 def test_features_match_oracle(built):
-    env, _, dg = built
-    g = dg.export()
+    env, g, dg = built
     X, base = mpap.mpap_edge_features(dg, with_base=True)
     f, rbase, _ = graph6d.edge_features6d(env, g)
     rb = mlp.bf16_bits(mlp.bf16_round(f))
@@ -99,9 +100,10 @@ def test_surrogate_on_6d_edges(built):
     print(f"6D held-out median rel err {np.median(rel):.3g}, p90 {np.percentile(rel, 90):.3g}")
     assert np.median(rel) < 0.02
     res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam, heuristic=1)
-    ok = mpap.surrogate_front_ok(res, 0, env.beta)
     rs = mpap.mpap_rescore_front(res, 0)
     assert np.array_equal(bits(rs["cost"]), bits(res.goal_front().vecs[:, 0]))
-    print(f"6D surrogate front: {res.goal_front().vecs.shape[0]} labels, judge {ok}")
+    rejected = res.judge(1e-2, fallback=False)[0]
+    print(f"6D surrogate front: {res.goal_front().vecs.shape[0]} labels, rejected {rejected}")
+    assert not rejected
     res.close()
     s.close()

@@ -104,7 +104,7 @@ def test_near_scan_setting_does_not_change_results(small_batch):
 def test_rewalk_of_all_queries(small_batch):
     """The re-walk of every goal front in one launch equals the per-query
     re-walks, and on an analytic search reproduces the fronts bit for bit (the
-    same float32 fold along the same edges), so the judge passes every query."""
+    same float32 fold along the same edges)."""
     envs, graphs, parts, union = small_batch
     res = mpap.mpap_search_batch(union, params_of(envs))
     allq = mpap.mpap_rescore_front(res, -1)
@@ -121,5 +121,4 @@ def test_rewalk_of_all_queries(small_batch):
         assert one["feasible"].all(), q
         o += k
     assert o == allq["cost"].shape[0]
-    assert all(mpap.surrogate_judge(res, [e.beta for e in envs]))
     res.close()

@@ -272,14 +272,12 @@ def test_build_graph_matches_oracle(dim, n, seed):
     assert np.array_equal(got["col"], ref["col"])
     assert np.array_equal(bits(got["cost"]), bits(ref["cost"]))
     assert np.array_equal(got["goal"], ref["goal"])
-    # drift uses the device expf in float32: within a float32 error bound of
-    # the float64 reference (K terms, each a few ulp of the edge length)
-    err = np.abs(got["drift"].astype(np.float64) - ref["drift"].astype(np.float64))
-    bound = 256 * np.finfo(np.float32).eps * ref["cost"].astype(np.float64)
-    assert np.all(err <= bound), float((err / bound).max())
-    # relocalisation flags agree wherever q is not within 1e-4 of the threshold
-    clear = np.abs(ref["q"] - env.reset_q) > 1e-4
-    assert np.array_equal(got["reset"][clear], ref["reset"][clear])
+    # drift and relocalisation flags: the same float64 evaluation of q
+    # (summed in the same order, rounded once to float32) as the oracle, so
+    # the same bits
+    bad = np.nonzero(bits(got["drift"]) != bits(ref["drift"]))[0]
+    assert bad.size == 0, (bad.size, bad[:8])
+    assert np.array_equal(got["reset"], ref["reset"])
 
 
 def test_build_graph_without_goal_sample_fails():
@@ -290,10 +288,15 @@ def test_build_graph_without_goal_sample_fails():
     assert ei.value.status == mpap.MPAP_ERR_NOGOAL
 
 
-def test_search_on_device_built_graph_matches_oracle_on_same_arrays():
+def test_search_on_device_built_graph_matches_oracle():
+    """The library's roadmap is the oracle's (same bits); the search on it
+    gives the oracle's fronts."""
     env = synth.plain2d(4)
     dg = mpap.mpap_build_graph(env)
-    g = dg.export()
+    g = ograph.build_graph(env)
+    got = dg.export()
+    for k in ("row_ptr", "col", "cost", "drift", "reset", "goal"):
+        assert np.array_equal(np.asarray(got[k]).view(np.uint8), np.asarray(g[k]).view(np.uint8)), k
     ref = osearch.search(g, env.beta, 2)
     res = mpap.mpap_search(dg, env.beta, 2, env.radius, env.lam)
     check_against_oracle(g, res, ref, env.beta, 2, all_nodes=False, node_stride=5)

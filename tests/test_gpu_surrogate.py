@@ -52,6 +52,12 @@ def test_forward_matches_reference(n):
 
 @pytest.mark.parametrize("n", [64, 1024, 4096])
 def test_gradient_matches_reference(n):
+    """Gradients of the matrix-core kernels against the exact float64
+    gradients of the same bfloat16 model, entry by entry, within the bound of
+    the kernels' own roundings: the two output gradients rounded to bfloat16
+    (relative 2^-9 each), one bfloat16 step of h1 where the float32 and the
+    float64 first layer round differently (2 * 2^-9), and float32 sums of n
+    terms (n * 2^-24), all relative to the entry's absolute-term sum."""
     p = trained_like_params(2)
     Xf, Xbits, t = random_inputs(3, n)
     s = mpap.Surrogate()
@@ -59,9 +65,16 @@ def test_gradient_matches_reference(n):
     g, y = s.gradient(Xbits, t)
     yref, gref = mlp.backward(p, Xf, t)
     assert rel_fro(y, yref) <= 1e-3
+    absg = mlp.gradient_abs_terms(p, Xf, t)
+    u = 2.0 ** -9
+    tol = 4 * u + n * 2.0 ** -24
     gd = mlp.unflat(g)
     for k in ("W1", "b1", "W2", "b2", "w3", "b3"):
-        assert rel_fro(gd[k], gref[k]) <= 1e-3, (k, rel_fro(gd[k], gref[k]))
+        err = np.abs(gd[k].astype(np.float64) - gref[k])
+        bound = tol * absg[k] + 1e-30
+        assert np.all(err <= bound), (k, float((err / bound).max()))
+        # and the whole block close in the Frobenius sense
+        assert rel_fro(gd[k], gref[k]) <= 4 * u, (k, rel_fro(gd[k], gref[k]))
     s.close()
 
 
@@ -75,7 +88,9 @@ def road3d():
 
 def test_edge_features_match_oracle(road3d):
     env, dg = road3d
-    g = dg.export()
+    g = ograph.build_graph(env)
+    got = dg.export()
+    assert np.array_equal(got["col"], g["col"]) and np.array_equal(bits(got["cost"]), bits(g["cost"]))
     X, base = mpap.mpap_edge_features(dg, with_base=True)
     ref, ref_base = ograph.edge_features(env.pos, g["row_ptr"], g["col"], g["cost"],
                                          env.blob_mu, env.blob_sigma, env.blob_amp)
@@ -127,25 +142,26 @@ def test_surrogate_search_is_judged_and_falls_back(road3d):
     rs = mpap.mpap_rescore_front(res, 0)
     # the re-walk reproduces the cost exactly (cost does not use the surrogate)
     assert np.array_equal(bits(rs["cost"]), bits(fr.vecs[:, 0]))
-    ok = mpap.surrogate_front_ok(res, 0, env.beta)
+    # the trained network passes the judge (1e-2 relative drift after the
+    # analytic re-walk, bound kept)
+    assert not res.judge(1e-2, fallback=False)[0]
     res.close()
-    # corrupted weights: the judge must reject the surrogate's front
+    # corrupted weights: the judge must reject the surrogate's front, and the
+    # library's fallback answers with the analytic search, exact against the
+    # oracle on the oracle's own roadmap (the library's roadmap equals it)
     bad = mlp.flat(mlp.init_params(1))
     bad[mlp.flat(mlp.init_params(1)).shape[0] - 1] = -500.0  # output bias: drift clamps to 0
     s.set_params(bad)
     s.score(dg)
     res2 = mpap.mpap_search(dg, env.beta, 3, env.radius, env.lam, heuristic=1)
-    assert not mpap.surrogate_front_ok(res2, 0, env.beta)
-    res2.close()
-    # the fallback is the analytic search, exact against the oracle
-    g = dg.export()
+    assert res2.judge(1e-2, fallback=True)[0]
+    g = ograph.build_graph(env)
     ref = osearch.search(g, env.beta, 3)
     rv, _, _ = osearch.goal_front(ref, g["goal"])
-    res3 = mpap.mpap_search(dg, env.beta, 3, env.radius, env.lam, heuristic=0)
-    assert np.array_equal(bits(res3.goal_front().vecs), bits(rv))
-    res3.close()
+    assert np.array_equal(bits(res2.goal_front().vecs), bits(rv))
+    assert res2.stats()["judged_failed"] == 1
+    res2.close()
     s.close()
-    assert ok in (True, False)
 
 
 def test_surrogate_gain_on_fine_drift_integration():
