@@ -357,11 +357,12 @@ def measure_batch(args, with_surrogate: bool = True):
     info = union.info()
     log(f"# {nq} roadmaps ({info}) built in {build_s:.2f}s; analytic drift {ana_ms:.1f} ms")
     base = [mpap.search_params(e.beta, e.n_obj, e.radius, e.lam) for e in envs]
-    sub = mpap.mpap_graph_concat(parts[:32])
+    # tuned on the whole batch: a subset of queries has fewer merge targets per
+    # iteration and picks other merge tiles (a 32-query subset chose
+    # workgroup-only merges, which are 1.7x slower on all 256 queries)
     t0 = time.perf_counter()
-    choice = autotune.tune(sub, base[:32], sorted({e.dim for e in envs}), 2, repeats=1,
-                           lambdas=(0.5, 1.0, 2.0), log=log)
-    sub.close()
+    choice = autotune.tune(union, base, sorted({e.dim for e in envs}), 2, repeats=1,
+                           lambdas=(0.5, 1.0), log=log)
     out["autotune"] = {"s": time.perf_counter() - t0, **{k.rstrip("_"): v for k, v in
                                                          choice.fields().items()}}
     log(f"# autotuned {choice.fields()} in {out['autotune']['s']:.1f}s")
