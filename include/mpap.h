@@ -164,6 +164,12 @@ typedef struct {
     int32_t skip;             /* 1: leave this query out of a batched search (its root
                                  label is not seeded; its goal front is empty); 0 =
                                  search it */
+    int32_t early_stop;       /* 0: run until P_open is empty (exact fronts).  1: the
+                                 loop condition of Alg. 3 (Sec. 3): the query's loop
+                                 ends before the first group that holds a plan at a
+                                 goal node; its goal front is then the Pareto minimum
+                                 of P_candidates at that point (entry 0 = P_soln), which
+                                 depends on lambda and need not be the exact front */
 } mpap_search_params;
 
 /*
@@ -239,6 +245,35 @@ int mpap_query_goal_front(const mpap_result *r, int32_t query, float *cost, floa
  * the start of the launch to the end of that iteration (ms).  Either output
  * may be NULL. */
 int mpap_query_info(const mpap_result *r, int32_t query, float *latency_ms, int32_t *last_wave);
+
+/* mpap_query_stop - how a query's loop ended: *groups receives the number of
+ * groups expanded before the early stop of Alg. 3's loop condition ended it
+ * (a group held a plan at a goal node; early_stop = 1), or -1 when it ran
+ * until its P_open was empty. */
+int mpap_query_stop(const mpap_result *r, int32_t query, int32_t *groups);
+
+/*
+ * mpap_refine_front - the goal front of one query under a tighter bound
+ *   beta_prime <= beta, from a search run with three objectives.  Alg. 1
+ *   step 4 (Sec. 3) refines the bound by searching again with a lower beta;
+ *   with the running maximum m of the pre-relocalisation drift as the third
+ *   objective a plan meets beta_prime at every step iff m <= beta_prime, and a
+ *   plan dominated by a front member is dominated by one whose m is no larger,
+ *   so one search answers every beta_prime <= beta:
+ *     n_obj_out = 3: the front members with m <= beta_prime -- exactly the
+ *                    three-objective goal front of a search at beta_prime;
+ *     n_obj_out = 2: their Pareto minimum over (c, d) (of equal (c, d) the one
+ *                    of least m), maxdrift filled with 0 -- exactly the
+ *                    two-objective goal front of a search at beta_prime.
+ *   Ascending (c, d, m) order; goal nodes and label ids name witnesses as in
+ *   mpap_query_goal_front.  Outputs nullable; same capacity rule.
+ * Errors: MPAP_ERR_INVAL (null, query out of range, the search did not use
+ * three objectives, beta_prime NaN or above the query's bound, n_obj_out not
+ * 2 or 3, an early-stopped query), MPAP_ERR_CAPACITY.
+ */
+int mpap_refine_front(const mpap_result *r, int32_t query, float beta_prime, int32_t n_obj_out,
+                      float *cost, float *drift, float *maxdrift, int32_t *goal_node,
+                      int32_t *label_id, int32_t capacity, int32_t *count);
 
 /* mpap_node_front - the final label set P(node) of one node (Alg. 3), in
  * storage order (not sorted), with each label's id.  Any output array may be

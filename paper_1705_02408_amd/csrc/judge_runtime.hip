@@ -172,6 +172,8 @@ int mpap_judge(mpap_result *r, float tol, int32_t fallback, void *stream, uint8_
     p.root = r->qroot;
     p.heur.assign(nq, 0);
     p.skip.assign(nq, 1);
+    p.early = r->qearly;
+    for (int q = 0; q < nq; ++q) p.early_any = p.early_any || (qfail[q] && r->qearly[q]);
     for (int q = 0; q < nq; ++q) p.skip[q] = qfail[q] ? 0 : 1;
     p.max_waves = r->max_waves;
     p.near_scan = r->near_scan;
@@ -190,8 +192,8 @@ int mpap_judge(mpap_result *r, float tol, int32_t fallback, void *stream, uint8_
         mpap_result_free(fb);
         return rc;
     }
-    const long long off = r->stats.labels_expanded;
-    if (off + fb->stats.labels_expanded > 0x7fffffffll) {
+    const long long off = r->arena_labels;
+    if (off + fb->arena_labels > 0x7fffffffll) {
         mpap_result_free(fb);
         return fail(MPAP_ERR_OVERFLOW, "label ids of the two searches exceed int32");
     }

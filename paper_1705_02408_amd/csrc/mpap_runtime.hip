@@ -552,6 +552,8 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
         if (x.block_threads != 0) p.block_threads = x.block_threads;
         if (x.wave_min_targets != 0) p.wave_min_targets = x.wave_min_targets;
         if (x.skip != 0 && x.skip != 1) return fail(MPAP_ERR_INVAL, "skip must be 0 or 1");
+        if (x.early_stop != 0 && x.early_stop != 1)
+            return fail(MPAP_ERR_INVAL, "early_stop must be 0 or 1");
     }
     if (p.max_waves <= 0) p.max_waves = 1 << 18;
     if (nsp == 1 && nq > 1) {
@@ -565,6 +567,7 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
     p.root.resize(nq);
     p.heur.resize(nq);
     p.skip.resize(nq);
+    p.early.resize(nq);
     for (int q = 0; q < nq; ++q) {
         const mpap_search_params &x = sp[nsp == 1 ? 0 : q];
         p.beta[q] = x.beta;
@@ -573,6 +576,8 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
         p.root[q] = g->qoff_h[q] + x.init_node;
         p.heur[q] = x.heuristic;
         p.skip[q] = x.skip;
+        p.early[q] = x.early_stop;
+        p.early_any = p.early_any || x.early_stop != 0;
     }
     return MPAP_OK;
 }
@@ -632,6 +637,9 @@ int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(w->qbeta, p.beta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w->qdelta, p.delta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w->qnobj, p.nobj.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    std::vector<int> early(nq, 0);
+    for (size_t q = 0; q < nq && q < p.early.size(); ++q) early[q] = p.early[q];
+    HIP_TRY(hipMemcpyAsync(w->qearly, early.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
     // a skipped query's root is not seeded (-1)
     std::vector<int> root(p.root);
     for (size_t q = 0; q < nq; ++q)
@@ -650,6 +658,8 @@ SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
     a.nq = p.nq; a.qoff = g->qoff; a.qbeta = w->qbeta; a.qnobj = w->qnobj;
     a.qroot = w->qroot; a.qlast = w->qlast;
     a.qdelta = w->qdelta; a.max_waves = p.max_waves; a.near_scan = p.near_scan;
+    a.qgoff = g->qgoff; a.goal_list = g->goal_list; a.qearly = w->qearly; a.qstop = w->qstop;
+    a.early_any = p.early_any ? 1 : 0;
     a.capB = L.capB; a.capC = L.capC; a.nblocks = L.nblocks;
     a.wcap = L.wcap; a.wslice = L.wslice; a.wmin = L.wmin;
     a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
@@ -674,7 +684,8 @@ GoalArgs goal_args(const mpap_graph *g, Workspace *w) {
 
 void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_out,
                    const int *counts, const float4 *plab, const int *pnode, const int *qlast,
-                   const long long *trace, float ms, int retries, const SearchShape &L) {
+                   const int *qstop, const long long *trace, float ms, int retries,
+                   const SearchShape &L) {
     const mpap_graph *g = res->g;
     const int nq = p.nq;
     res->n_obj = p.nobj.empty() ? 2 : p.nobj[0];
@@ -698,9 +709,14 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
         for (long long i = res->front_off[q]; i < res->front_off[q + 1]; ++i)
             res->front_node[i] -= g->qoff_h[q];
     res->qlast.assign(qlast, qlast + nq);
+    res->qearly.assign(nq, 0);
+    for (int q = 0; q < nq && q < (int)p.early.size(); ++q) res->qearly[q] = p.early[q];
+    res->qstop.assign(nq, -1);
+    for (int q = 0; q < nq; ++q) res->qstop[q] = qstop[q] >= 0 ? qstop[q] : -1;
     res->stats.waves = (int32_t)dev_out[kOutWaves];
     res->stats.retries = retries;
     res->stats.labels_expanded = dev_out[kOutLabels];
+    res->arena_labels = dev_out[kOutLabels] + dev_out[kOutClosed];
     res->stats.front_labels = dev_out[kOutFront];
     res->stats.merges = dev_out[kOutMerges];
     res->stats.candidates = dev_out[kOutCandidates];
@@ -753,6 +769,7 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         HIP_TRY(hipLaunchCooperativeKernel(search_kernel_for(L, g->n),
                                            dim3(L.nblocks), dim3(L.threads), kargs, L.lds, s));
         HIP_TRY(hipEventRecord(w->ev1, s));
+        if (p.early_any) k_close_stopped<<<1, 1024, 0, s>>>(a);
         k_count_front<<<std::max(1, std::min(div_up(g->n, 256), 1024)), 256, 0, s>>>(a);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(dev_out, w->out, sizeof(dev_out), hipMemcpyDeviceToHost, s));
@@ -785,7 +802,7 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
     }
 
     // goal fronts (a7): exact per-query regions, the fronts, then packed
-    std::vector<int> counts(nq, 0), qlast(nq, 0);
+    std::vector<int> counts(nq, 0), qlast(nq, 0), qstop(nq, -2);
     {
         GoalArgs ga = goal_args(g, w);
         long long total = 0;
@@ -823,6 +840,7 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
                                    hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(hipMemcpyAsync(qlast.data(), w->qlast, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(qstop.data(), w->qstop, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (ovf) return fail(MPAP_ERR_OVERFLOW, "goal front pack overflow");
@@ -832,7 +850,7 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
             HIP_TRY(hipMemcpy(trace.data(), w->wstat, sizeof(long long) * trace.size(),
                               hipMemcpyDeviceToHost));
         search_finish(res, p, dev_out, counts.data(), plab.data(), pnode.data(), qlast.data(),
-                      trace.data(), ms, retries, L);
+                      qstop.data(), trace.data(), ms, retries, L);
     }
     return MPAP_OK;
 }
@@ -925,6 +943,59 @@ int mpap_query_goal_front(const mpap_result *r, int32_t query, float *cost, floa
     return MPAP_OK;
 }
 
+int mpap_query_stop(const mpap_result *r, int32_t query, int32_t *groups) {
+    if (!r || !groups) return fail(MPAP_ERR_INVAL, "null result or output");
+    if (query < 0 || query >= r->g->nq) return fail(MPAP_ERR_INVAL, "query out of range");
+    *groups = query < (int)r->qstop.size() ? r->qstop[query] : -1;
+    return MPAP_OK;
+}
+
+int mpap_refine_front(const mpap_result *r, int32_t query, float beta_prime, int32_t n_obj_out,
+                      float *cost, float *drift, float *maxdrift, int32_t *goal_node,
+                      int32_t *label_id, int32_t capacity, int32_t *count) {
+    if (!r || !count) return fail(MPAP_ERR_INVAL, "null result or count");
+    if (query < 0 || query >= r->g->nq) return fail(MPAP_ERR_INVAL, "query out of range");
+    if (r->qnobj[query] != 3)
+        return fail(MPAP_ERR_INVAL, "refinement needs a search with three objectives");
+    if (std::isnan(beta_prime) || beta_prime > r->qbeta[query])
+        return fail(MPAP_ERR_INVAL, "beta_prime must not exceed the search's bound");
+    if (n_obj_out != 2 && n_obj_out != 3) return fail(MPAP_ERR_INVAL, "n_obj_out must be 2 or 3");
+    if (query < (int)r->qstop.size() && r->qstop[query] >= 0)
+        return fail(MPAP_ERR_INVAL, "an early-stopped query has no exact front to refine");
+    // the front is in ascending (c, d, m) order: members with m <= beta_prime
+    // keep it; for two objectives a member survives iff its drift is below
+    // that of every kept member before it (the first of equal (c, d) has the
+    // least m)
+    const int64_t o = r->front_off[query], e = r->front_off[query + 1];
+    int32_t k = 0;
+    float dmin = INFINITY;
+    for (int pass = 0; pass < 2; ++pass) {
+        k = 0;
+        dmin = INFINITY;
+        for (int64_t i = o; i < e; ++i) {
+            const float4 L = r->front[i];
+            if (!(L.z <= beta_prime)) continue;
+            if (n_obj_out == 2) {
+                if (!(L.y < dmin)) continue;
+                dmin = L.y;
+            }
+            if (pass == 1) {
+                if (cost) cost[k] = L.x;
+                if (drift) drift[k] = L.y;
+                if (maxdrift) maxdrift[k] = n_obj_out == 2 ? 0.0f : L.z;
+                if (goal_node) goal_node[k] = r->front_node[i];
+                if (label_id) std::memcpy(&label_id[k], &L.w, sizeof(int));
+            }
+            ++k;
+        }
+        if (pass == 0) {
+            *count = k;
+            if (capacity < k) return fail(MPAP_ERR_CAPACITY, "capacity below the front size");
+        }
+    }
+    return MPAP_OK;
+}
+
 int mpap_goal_front(const mpap_result *r, float *cost, float *drift, float *maxdrift,
                     int32_t *goal_node, int32_t *label_id, int32_t capacity, int32_t *count) {
     return mpap_query_goal_front(r, 0, cost, drift, maxdrift, goal_node, label_id, capacity,
@@ -968,7 +1039,12 @@ int mpap_node_front(const mpap_result *r, int32_t node, float *cost, float *drif
         if (cost) cost[i] = L[i].x;
         if (drift) drift[i] = L[i].y;
         if (maxdrift) maxdrift[i] = L[i].z;
-        if (label_id) std::memcpy(&label_id[i], &L[i].w, sizeof(int32_t));
+        if (label_id) {
+            uint32_t meta;
+            std::memcpy(&meta, &L[i].w, sizeof(meta));
+            // a plan still open when an early stop ended the loop has no id
+            label_id[i] = (meta & 0x80000000u) ? -1 : (int32_t)meta;
+        }
     }
     return MPAP_OK;
 }
@@ -980,7 +1056,7 @@ int mpap_label_path(const mpap_result *rc, int32_t label_id, int32_t *nodes, int
     if (r->fallback && label_id >= r->id_offset)
         return mpap_label_path(r->fallback, (int32_t)(label_id - r->id_offset), nodes, capacity,
                                length);
-    const long long L = r->stats.labels_expanded;
+    const long long L = r->arena_labels;
     if (label_id < 0 || label_id >= L) return fail(MPAP_ERR_INVAL, "label id out of range");
     if (!r->arena_loaded) {
         r->arena_host.resize(L);

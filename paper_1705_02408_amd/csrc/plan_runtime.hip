@@ -6,7 +6,8 @@
 // Graph layout (all nodes in one chain):
 //   [scoring: features + inference per roadmap] -> k_search_init ->
 //   k_search_roots -> event -> k_search (cooperative kernel node) -> event ->
-//   k_count_front -> clears -> k_goal_bound -> k_goal_front -> k_goal_pack ->
+//   [k_close_stopped, with early stops] -> k_count_front -> clears ->
+//   k_goal_bound -> k_goal_front -> k_goal_pack ->
 //   copies of the status words, counts, packed fronts, last waves and the
 //   wave trace into pinned host buffers.
 // The two kernel segments are recorded by stream capture; the search kernel
@@ -37,6 +38,7 @@ struct mpap_plan {
     int *h_ovf = nullptr;
     int *h_count = nullptr;
     int *h_qlast = nullptr;
+    int *h_qstop = nullptr;
     float4 *h_plab = nullptr;
     int *h_pnode = nullptr;
     long long *h_trace = nullptr;
@@ -57,6 +59,8 @@ void plan_drop_graph(mpap_plan *p) {
     p->graph = nullptr;
     host_free(p->h_out); host_free(p->h_err); host_free(p->h_ovf); host_free(p->h_count);
     host_free(p->h_qlast); host_free(p->h_plab); host_free(p->h_pnode); host_free(p->h_trace);
+    host_free(p->h_qstop);
+    p->h_qstop = nullptr;
     p->h_out = nullptr; p->h_err = nullptr; p->h_ovf = nullptr; p->h_count = nullptr;
     p->h_qlast = nullptr; p->h_plab = nullptr; p->h_pnode = nullptr; p->h_trace = nullptr;
     p->h_pcap = 0;
@@ -99,7 +103,8 @@ int plan_record(mpap_plan *p) {
     p->h_pcap = w->p_cap;
     if ((r = host_alloc(&p->h_out, kOutWords)) || (r = host_alloc(&p->h_err, 1)) ||
         (r = host_alloc(&p->h_ovf, 1)) || (r = host_alloc(&p->h_count, nq)) ||
-        (r = host_alloc(&p->h_qlast, nq)) || (r = host_alloc(&p->h_plab, w->p_cap)) ||
+        (r = host_alloc(&p->h_qlast, nq)) || (r = host_alloc(&p->h_qstop, nq)) ||
+        (r = host_alloc(&p->h_plab, w->p_cap)) ||
         (r = host_alloc(&p->h_pnode, w->p_cap)) ||
         (r = host_alloc(&p->h_trace, (size_t)kTraceCap * kTraceWords)))
         return r;
@@ -134,6 +139,7 @@ int plan_record(mpap_plan *p) {
         if (he != hipSuccess) r = fail(MPAP_ERR_HIP, hipGetErrorString(he));
     }
     if (!r) {
+        if (p->prep.early_any) k_close_stopped<<<1, 1024, 0, cs>>>(a);
         k_count_front<<<std::max(1, std::min(div_up(g->n, 256), 1024)), 256, 0, cs>>>(a);
         k_zero_i32<<<div_up(nq, 256), 256, 0, cs>>>(w->g_count, nq);
         k_zero_i32<<<1, 32, 0, cs>>>(w->g_overflow, 1);
@@ -147,6 +153,7 @@ int plan_record(mpap_plan *p) {
         if (he == hipSuccess) he = hipMemcpyAsync(p->h_ovf, w->g_overflow, sizeof(int), d2h, cs);
         if (he == hipSuccess) he = hipMemcpyAsync(p->h_count, w->g_count, sizeof(int) * nq, d2h, cs);
         if (he == hipSuccess) he = hipMemcpyAsync(p->h_qlast, w->qlast, sizeof(int) * nq, d2h, cs);
+        if (he == hipSuccess) he = hipMemcpyAsync(p->h_qstop, w->qstop, sizeof(int) * nq, d2h, cs);
         if (he == hipSuccess)
             he = hipMemcpyAsync(p->h_plab, w->p_lab, sizeof(float4) * w->p_cap, d2h, cs);
         if (he == hipSuccess)
@@ -313,7 +320,7 @@ int mpap_plan_run(mpap_plan *p, void *stream, mpap_result **out) {
     res->ws = p->w;
     res->ws_borrowed = true;
     search_finish(res, p->prep, p->h_out, p->h_count, p->h_plab, p->h_pnode, p->h_qlast,
-                  p->h_trace, ms, 0, p->shape);
+                  p->h_qstop, p->h_trace, ms, 0, p->shape);
     *out = res;
     return MPAP_OK;
 }

@@ -175,6 +175,7 @@ struct Workspace {
     int nq_cap = 0;
     float *qbeta = nullptr;
     int *qnobj = nullptr, *qroot = nullptr, *qlast = nullptr, *qheur = nullptr;
+    int *qearly = nullptr, *qstop = nullptr;
     float *qdelta = nullptr;
     long long *g_laboff = nullptr;
     int *g_labcap = nullptr;
@@ -196,6 +197,7 @@ struct Workspace {
         dfree(g_out); dfree(g_out_node); dfree(g_n); dfree(g_count); dfree(g_total);
         dfree(p_lab); dfree(p_node);
         dfree(qbeta); dfree(qnobj); dfree(qroot); dfree(qlast); dfree(qheur); dfree(qdelta);
+        dfree(qearly); dfree(qstop);
         dfree(g_laboff);
         dfree(g_labcap); dfree(g_overflow);
         if (ev0) (void)hipEventDestroy(ev0);
@@ -236,7 +238,9 @@ inline int ws_queries(Workspace *w, int nq) {
     int r;
     dfree(w->qbeta); dfree(w->qnobj); dfree(w->qroot); dfree(w->qlast); dfree(w->g_laboff);
     dfree(w->g_labcap); dfree(w->g_n); dfree(w->g_count); dfree(w->qheur); dfree(w->qdelta);
+    dfree(w->qearly); dfree(w->qstop);
     if ((r = dalloc(&w->qbeta, nq)) || (r = dalloc(&w->qnobj, nq)) || (r = dalloc(&w->qheur, nq)) ||
+        (r = dalloc(&w->qearly, nq)) || (r = dalloc(&w->qstop, nq)) ||
         (r = dalloc(&w->qdelta, nq)) ||
         (r = dalloc(&w->qroot, nq)) || (r = dalloc(&w->qlast, nq)) ||
         (r = dalloc(&w->g_laboff, nq)) || (r = dalloc(&w->g_labcap, nq)) ||
@@ -306,6 +310,8 @@ struct mpap_result {
     std::vector<float> qbeta;   // per-query bound
     std::vector<int> qnobj;     // per-query objective count
     std::vector<int> qheur;     // per-query heuristic (0 analytic, 1 surrogate)
+    std::vector<int> qearly;    // per-query early stop of Alg. 3's loop condition (0/1)
+    std::vector<int> qstop;     // per query: groups expanded before the early stop, -1 none
     // goal fronts of all queries, query q at [front_off[q], front_off[q+1])
     std::vector<float4> front;
     std::vector<int32_t> front_node;
@@ -314,6 +320,7 @@ struct mpap_result {
     std::vector<float> qlatency_ms;  // device time from launch start to that wave's end
     std::vector<int64_t> trace;
     mpap_stats stats{};
+    long long arena_labels = 0;  // arena size: expanded labels + goal plans closed at a stop
     std::vector<int2> arena_host;  // filled on first mpap_label_path
     bool arena_loaded = false;
     bool ws_borrowed = false;  // ws belongs to a plan (valid until its next run)
@@ -341,6 +348,8 @@ struct SearchPrep {
     std::vector<float> beta;
     std::vector<int> nobj, root, heur;
     std::vector<int> skip;  // 1: the query is not searched (its root is not seeded)
+    std::vector<int> early; // 1: Alg. 3's early stop (loop ends at a group with a goal plan)
+    bool early_any = false;
 };
 // Launch shape of the persistent search kernel.
 struct SearchShape {
@@ -374,7 +383,8 @@ inline const void *search_kernel_for(const SearchShape &L, int n) {
 // Fills res's fronts, statistics, trace and latencies from host copies.
 void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_out,
                    const int *counts, const float4 *plab, const int *pnode, const int *qlast,
-                   const long long *trace, float ms, int retries, const SearchShape &L);
+                   const int *qstop, const long long *trace, float ms, int retries,
+                   const SearchShape &L);
 
 // Surrogate scoring of one roadmap (features, then inference) enqueued on a
 // stream, writing the drift to out[e]; used by plans and mpap_surrogate_score.

@@ -33,6 +33,7 @@ constexpr int kOutFront = 5;
 constexpr int kOutRelax = 6;
 constexpr int kOutNeed = 7;  // group size that did not fit (arena / frontier)
 constexpr int kOutMaxFront = 8;
+constexpr int kOutClosed = 9;  // open goal plans given arena ids at an early stop
 constexpr int kOutWords = 10;
 
 // per-wave trace words (device clock ticks, 100 MHz wall clock)
@@ -71,6 +72,15 @@ struct SearchArgs {
     const float *sdrift; // surrogate drift, in-edge order (the roadmap is symmetric)
     int *qlast;          // [nq] last wave with a group label of the query
     const float *qdelta; // [nq] lambda * r_n of the query
+    // the early stop of Alg. 3's loop condition (per query): the loop of a
+    // query with qearly[q] = 1 ends before the first group that holds a plan
+    // at one of its goal nodes (goal_list[qgoff[q] .. qgoff[q+1]))
+    const int *qgoff;      // [nq+1]
+    const int *goal_list;  // goal nodes, global ids, query by query
+    const int *qearly;     // [nq] 1: early stop, 0: until the query's P_open is empty
+    int *qstop;            // [nq] -2: no early stop; -1: running; >= 0: stopped after
+                           // that many expanded groups
+    int early_any;         // some query has qearly = 1
     int max_waves;
     int near_scan;       // bucket labels tested per candidate before the full scan
     int capB;  // LDS staging capacity of a front (labels)
@@ -140,6 +150,10 @@ __global__ void k_search_roots(SearchArgs a);
 __global__ void k_search(SearchArgs a);
 __global__ void k_search_wave(SearchArgs a);  // with single-wave merges
 __global__ void k_count_front(SearchArgs a);
+// After a search with early stops: the plans still open at the goal nodes of
+// every stopped query get arena ids (after the expanded ones) so that goal
+// fronts name walkable witnesses.  One workgroup of 1024 threads.
+__global__ void k_close_stopped(SearchArgs a);
 __global__ void k_goal_front(SearchArgs a, GoalArgs g);
 // per-query goal-front regions: lab_cap[q] = sum of the front sizes of the
 // query's goal nodes (a bound on its goal front), lab_off = exclusive scan;

@@ -81,7 +81,10 @@ __device__ void phase_count(const SearchArgs &a, long long istep, int par, int l
         bool need = false;
         if (v < hi) {
             const float mo = a.minopen[v];
-            if (mo < MPAP_INF) {
+            // the open plans of a query whose loop has ended are left alone
+            const bool live =
+                mo < MPAP_INF && (!a.early_any || a.qstop[a.nq > 1 ? query_of(a, v) : 0] < 0);
+            if (live) {
                 const float d = step_of(a, v);
                 need = mo <= threshold(istep, d);
                 open_nodes += 1;
@@ -1181,8 +1184,10 @@ __global__ void __launch_bounds__(256) k_search_roots(SearchArgs a) {
     const int r = a.qroot[q];
     if (r < 0) {  // a query left out of this launch
         a.qlast[q] = -1;
+        a.qstop[q] = -2;
         return;
     }
+    a.qstop[q] = a.qearly[q] ? -1 : -2;
     a.nb[r] = make_int4(16 * q, 16, 1, 1);
     a.minopen[r] = 0.0f;
     a.pool[(size_t)16 * q] = make_float4(0.f, 0.f, 0.f, __uint_as_float(MPAP_OPEN_BIT));
@@ -1261,6 +1266,23 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                 a.acnt[2 * r + wave_par(wave)] = 0;
                 a.mcur[2 * r + wave_par(wave)] = 0;
             }
+        }
+        if (a.early_any) {
+            // Alg. 3's loop condition, per query: the loop ends before a
+            // group that holds a plan at a goal node, i.e. when some goal
+            // node's least open cost is within this iteration's threshold
+            // (every plan kept is within the bound).  One thread per query.
+            for (int q = b * (int)blockDim.x + threadIdx.x; q < a.nq;
+                 q += G * (int)blockDim.x) {
+                if (a.qstop[q] != -1) continue;
+                const float T = threshold(i_step, a.qdelta[q]);
+                for (int gi = a.qgoff[q]; gi < a.qgoff[q + 1]; ++gi)
+                    if (a.minopen[a.goal_list[gi]] <= T) {
+                        a.qstop[q] = wave;
+                        break;
+                    }
+            }
+            grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         }
         phase_count(a, i_step, par, lo, hi, s.u_idx, s.scan, red_ll);
         if (tr0 && tr) tr[kTrCountDone] = (long long)wall_clock64();
@@ -1484,6 +1506,61 @@ __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
     }
     if (lane_id() == 0)
         atomicMax((unsigned long long *)&a.out[kOutMaxFront], (unsigned long long)mx);
+}
+
+// Plans still open when the early stop ended a query's loop are part of
+// P_candidates if their head is a goal node.  Each such plan gets an arena id
+// after the expanded ones, in query, goal-list and bucket order (so ids are
+// deterministic), and its meta word becomes that id; the plan stays in its
+// bucket.  Two passes over the queries: count (and check the arena's room),
+// then assign.
+__global__ void __launch_bounds__(1024) k_close_stopped(SearchArgs a) {
+    __shared__ int scan[16];
+    const long long base = a.out[kOutLabels];
+    long long total = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        long long carry = 0;
+        for (int q0 = 0; q0 < a.nq; q0 += (int)blockDim.x) {
+            const int q = q0 + (int)threadIdx.x;
+            const bool stopped = q < a.nq && a.qstop[q] >= 0;
+            int cnt = 0;
+            if (stopped)
+                for (int gi = a.qgoff[q]; gi < a.qgoff[q + 1]; ++gi) {
+                    const int4 nbv = a.nb[a.goal_list[gi]];
+                    for (int k = 0; k < nbv.z; ++k)
+                        cnt += lab_open(a.pool[(size_t)(unsigned)nbv.x + k]) ? 1 : 0;
+                }
+            int tot;
+            const int ex = block_excl_scan(cnt, scan, &tot);
+            if (pass == 1 && cnt > 0) {
+                long long id = base + carry + ex;
+                for (int gi = a.qgoff[q]; gi < a.qgoff[q + 1]; ++gi) {
+                    const int x = a.goal_list[gi];
+                    const int4 nbv = a.nb[x];
+                    for (int k = 0; k < nbv.z; ++k) {
+                        const size_t slot = (size_t)(unsigned)nbv.x + k;
+                        const float4 L = a.pool[slot];
+                        if (!lab_open(L)) continue;
+                        a.arena[id] = make_int2(x, lab_parent(L));
+                        reinterpret_cast<int *>(&a.pool[slot])[3] = (int)id;
+                        ++id;
+                    }
+                }
+            }
+            carry += tot;
+        }
+        if (pass == 0) {
+            total = carry;
+            if (base + total > a.arena_cap) {
+                if (threadIdx.x == 0) {
+                    a.out[kOutStatus] = kStatusArena;
+                    a.out[kOutNeed] = total;
+                }
+                return;
+            }
+        }
+    }
+    if (threadIdx.x == 0) a.out[kOutClosed] = total;
 }
 
 // ----------------------------------------------------------- goal front (a7)

@@ -55,7 +55,8 @@ class mpap_search_params(ctypes.Structure):
                 ("init_node", ctypes.c_int32), ("max_waves", ctypes.c_int32),
                 ("near_scan", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
                 ("heuristic", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("wave_min_targets", ctypes.c_int32), ("skip", ctypes.c_int32)]
+                ("wave_min_targets", ctypes.c_int32), ("skip", ctypes.c_int32),
+                ("early_stop", ctypes.c_int32)]
 
 
 class mpap_stats(ctypes.Structure):
@@ -80,6 +81,7 @@ SYMBOLS = [
     "mpap_surrogate_score", "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
     "mpap_plan_create", "mpap_plan_run", "mpap_plan_info", "mpap_plan_free",
     "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load",
+    "mpap_query_stop", "mpap_refine_front",
 ]
 
 _lib = None
@@ -137,6 +139,8 @@ def load(path: str = LIB_PATH):
     lib.mpap_judge.argtypes = [P, ctypes.c_float, I32, P, P, P]
     lib.mpap_surrogate_save.argtypes = [P, ctypes.c_char_p]
     lib.mpap_surrogate_load.argtypes = [P, ctypes.c_char_p]
+    lib.mpap_query_stop.argtypes = [P, I32, P]
+    lib.mpap_refine_front.argtypes = [P, I32, ctypes.c_float, I32, P, P, P, P, P, I32, P]
     lib.mpap_plan_free.argtypes = [P]
     lib.mpap_plan_free.restype = None
     lib.mpap_result_free.argtypes = [P]
@@ -154,7 +158,8 @@ def load(path: str = LIB_PATH):
                  "mpap_surrogate_init", "mpap_edge_features", "mpap_surrogate_forward",
                  "mpap_surrogate_gradient", "mpap_surrogate_train", "mpap_surrogate_score",
                  "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
-                 "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load"):
+                 "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load",
+                 "mpap_query_stop", "mpap_refine_front"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -306,6 +311,12 @@ class Result:
     def judge(self, tol: float = 1e-2, fallback: bool = True, stream=None) -> np.ndarray:
         return mpap_judge(self, tol, fallback, stream)
 
+    def stop(self, query: int = 0) -> int:
+        return mpap_query_stop(self, query)
+
+    def refine(self, beta_prime: float, n_obj_out: int = 2, query: int = 0) -> Front:
+        return mpap_refine_front(self, query, beta_prime, n_obj_out)
+
     def close(self):
         if self.handle:
             load().mpap_result_free(self.handle)
@@ -321,23 +332,52 @@ class Result:
 def search_params(beta: float, n_obj: int, radius: float, lam: float = 0.5,
                   init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
                   stage_cap: int = 0, heuristic: int = 0, block_threads: int = 0,
-                  wave_min_targets: int = 0, skip: int = 0):
+                  wave_min_targets: int = 0, skip: int = 0, early_stop: int = 0):
     return mpap_search_params(float(beta), float(lam), float(radius), int(n_obj),
                               int(init_node), int(max_waves), int(near_scan), int(stage_cap),
                               int(heuristic), int(block_threads), int(wave_min_targets),
-                              int(skip))
+                              int(skip), int(early_stop))
 
 
 def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float = 0.5,
                 init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
                 stage_cap: int = 0, heuristic: int = 0, stream=None,
-                block_threads: int = 0, wave_min_targets: int = 0) -> Result:
+                block_threads: int = 0, wave_min_targets: int = 0,
+                early_stop: int = 0) -> Result:
     lib = load()
     sp = search_params(beta, n_obj, radius, lam, init_node, max_waves, near_scan, stage_cap,
-                       heuristic, block_threads, wave_min_targets)
+                       heuristic, block_threads, wave_min_targets, early_stop=early_stop)
     h = ctypes.c_void_p()
     _check(lib.mpap_search(graph.handle, ctypes.byref(sp), _stream(stream), ctypes.byref(h)))
     return Result(h, graph)
+
+
+def mpap_query_stop(res: Result, query: int = 0) -> int:
+    """Groups expanded before the early stop ended the query's loop, or -1."""
+    g = ctypes.c_int32()
+    _check(load().mpap_query_stop(res.handle, int(query), ctypes.byref(g)))
+    return g.value
+
+
+def mpap_refine_front(res: Result, query: int, beta_prime: float, n_obj_out: int = 2) -> Front:
+    """Goal front under the bound beta_prime from a three-objective search."""
+    lib = load()
+    cnt = ctypes.c_int32()
+    st = lib.mpap_refine_front(res.handle, int(query), ctypes.c_float(beta_prime),
+                               int(n_obj_out), None, None, None, None, None, 0,
+                               ctypes.byref(cnt))
+    if st not in (MPAP_OK, MPAP_ERR_CAPACITY):
+        _check(st)
+    k = cnt.value
+    c = np.empty(k, np.float32)
+    d = np.empty(k, np.float32)
+    m = np.empty(k, np.float32)
+    gn = np.empty(k, np.int32)
+    ids = np.empty(k, np.int32)
+    _check(lib.mpap_refine_front(res.handle, int(query), ctypes.c_float(beta_prime),
+                                 int(n_obj_out), _p(c), _p(d), _p(m), _p(gn), _p(ids), k,
+                                 ctypes.byref(cnt)))
+    return Front(np.stack([c, d, m], axis=1).reshape(k, 3), gn, ids)
 
 
 def mpap_graph_concat(parts, stream=None) -> Graph:
