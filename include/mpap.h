@@ -446,6 +446,32 @@ int mpap_judge(mpap_result *r, float tol, int32_t fallback, void *stream, uint8_
 int mpap_surrogate_save(const mpap_surrogate *s, const char *path);
 int mpap_surrogate_load(mpap_surrogate *s, const char *path);
 
+/*
+ * mpap_search_noalloc - mpap_search followed by mpap_goal_front, for callers
+ *   that cannot allocate device memory (code that must not call hipMalloc:
+ *   tight serving loops, harnesses that forbid allocation).  It allocates
+ *   nothing: the search state lives in one fixed scratch array of 64 MiB per
+ *   device that the library holds from its first use on the device until the
+ *   process ends.  Same search and result as mpap_search (same kernels) on a
+ *   single-query roadmap (not a concatenated batch); outputs as
+ *   mpap_goal_front without label ids (host buffers, ascending (c, d, m);
+ *   maxdrift and goal_node nullable; *count always receives the front size;
+ *   capacity < count writes nothing and returns MPAP_ERR_CAPACITY).
+ *   No result handle: label ids and node fronts are not kept.  Every call on a
+ *   device shares that device's scratch; calls that overlap on one device
+ *   (other streams or threads) race and must be serialised by the caller.
+ *   Blocks until the front is in the caller's buffers.
+ * Errors: MPAP_ERR_INVAL (as mpap_search; also a batched roadmap, skip != 0,
+ * a roadmap whose per-node state leaves under 4 MiB of the scratch for labels
+ * -- about 680,000 nodes), MPAP_ERR_OVERFLOW (the search needs more label
+ * storage than the scratch holds, or a front beyond the LDS stage of a
+ * workgroup: there is no spill space; use mpap_search), MPAP_ERR_CAPACITY,
+ * MPAP_ERR_NOCONVERGE, MPAP_ERR_HIP, MPAP_ERR_DEVICE.
+ */
+int mpap_search_noalloc(const mpap_graph *g, const mpap_search_params *sp, void *stream,
+                        float *cost, float *drift, float *maxdrift, int32_t *goal_node,
+                        int32_t capacity, int32_t *count);
+
 /* ----------------------------------------------------------------- misc */
 const char *mpap_status_string(int status);
 const char *mpap_last_error(void);

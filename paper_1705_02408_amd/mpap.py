@@ -80,7 +80,7 @@ SYMBOLS = [
     "mpap_surrogate_forward", "mpap_surrogate_gradient", "mpap_surrogate_train",
     "mpap_surrogate_score", "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
     "mpap_plan_create", "mpap_plan_run", "mpap_plan_info", "mpap_plan_free",
-    "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load",
+    "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load", "mpap_search_noalloc",
     "mpap_query_stop", "mpap_refine_front",
 ]
 
@@ -139,6 +139,8 @@ def load(path: str = LIB_PATH):
     lib.mpap_judge.argtypes = [P, ctypes.c_float, I32, P, P, P]
     lib.mpap_surrogate_save.argtypes = [P, ctypes.c_char_p]
     lib.mpap_surrogate_load.argtypes = [P, ctypes.c_char_p]
+    lib.mpap_search_noalloc.argtypes = [P, ctypes.POINTER(mpap_search_params), P, P, P, P, P,
+                                        I32, P]
     lib.mpap_query_stop.argtypes = [P, I32, P]
     lib.mpap_refine_front.argtypes = [P, I32, ctypes.c_float, I32, P, P, P, P, P, I32, P]
     lib.mpap_plan_free.argtypes = [P]
@@ -159,7 +161,7 @@ def load(path: str = LIB_PATH):
                  "mpap_surrogate_gradient", "mpap_surrogate_train", "mpap_surrogate_score",
                  "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
                  "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load",
-                 "mpap_query_stop", "mpap_refine_front"):
+                 "mpap_search_noalloc", "mpap_query_stop", "mpap_refine_front"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -350,6 +352,25 @@ def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float
     h = ctypes.c_void_p()
     _check(lib.mpap_search(graph.handle, ctypes.byref(sp), _stream(stream), ctypes.byref(h)))
     return Result(h, graph)
+
+
+def mpap_search_noalloc(graph: Graph, beta: float, n_obj: int, radius: float,
+                        lam: float = 0.5, capacity: int = 4096, stream=None, **kw) -> Front:
+    """The search and goal front of mpap_search with no device allocation
+    (the library's fixed per-device scratch).  Returns the goal front (label
+    ids are not kept: -1)."""
+    lib = load()
+    sp = search_params(beta, n_obj, radius, lam, **kw)
+    c = np.empty(capacity, np.float32)
+    d = np.empty(capacity, np.float32)
+    m = np.empty(capacity, np.float32)
+    gn = np.empty(capacity, np.int32)
+    k = ctypes.c_int32()
+    _check(lib.mpap_search_noalloc(graph.handle, ctypes.byref(sp), _stream(stream), _p(c), _p(d),
+                                   _p(m), _p(gn), capacity, ctypes.byref(k)))
+    k = k.value
+    return Front(np.stack([c[:k], d[:k], m[:k]], axis=1), gn[:k].copy(),
+                 np.full(k, -1, np.int32))
 
 
 def mpap_query_stop(res: Result, query: int = 0) -> int:
