@@ -472,6 +472,47 @@ int mpap_search_noalloc(const mpap_graph *g, const mpap_search_params *sp, void 
                         float *cost, float *drift, float *maxdrift, int32_t *goal_node,
                         int32_t capacity, int32_t *count);
 
+/*
+ * Online updates (Sec. 3, online implementation: when obstacles are
+ * discovered only the new collision checks are made, and the exploration is
+ * run again).
+ *
+ * mpap_graph_add_boxes - a new roadmap: g (2D/3D, built by mpap_build_graph,
+ *   one query) without the edges that collide with the n_boxes new boxes
+ *   (host [n_boxes][dim] closed lower/upper corners).  Only the new boxes are
+ *   checked (Alg. 2 Collision at g's check step); costs, drifts, flags and
+ *   the environment are kept, so the result is the roadmap mpap_build_graph
+ *   makes for the same samples with the boxes added.  g is not changed; the
+ *   new graph is owned by the caller (mpap_graph_free).
+ * Errors: MPAP_ERR_INVAL (null, n_boxes < 0, non-finite corners, a roadmap
+ * not built by mpap_build_graph in 2D/3D, a batch), MPAP_ERR_NOMEM,
+ * MPAP_ERR_HIP.
+ */
+int mpap_graph_add_boxes(const mpap_graph *g, int32_t n_boxes, const float *box_lo,
+                         const float *box_hi, void *stream, mpap_graph **out);
+
+/*
+ * mpap_search_update - the search of roadmap g (Alg. 3 until no plan is
+ *   open, the same result as mpap_search on g) continued from an earlier
+ *   result prev on a roadmap over the same nodes (for instance
+ *   mpap_graph_add_boxes of prev's roadmap, or edges with new costs or
+ *   drifts, or new relocalisation flags).  prev's labels whose plans use no
+ *   changed edge (removed, added, other cost or drift bits, or a head whose
+ *   relocalisation flag changed) are kept; the labels of the in-neighbours of
+ *   nodes that lost labels, and of the tails of new or changed edges, are
+ *   opened again; the search runs from there.  sp must repeat prev's bound,
+ *   objective count, root and heuristic (analytic); lambda and the tuning
+ *   fields may differ.  prev is not changed (a plan's result must not have
+ *   been superseded by the plan's next run).  In the new result's statistics
+ *   labels_expanded counts this call's expansions only; label ids of kept
+ *   labels are prev's.
+ * Errors: MPAP_ERR_INVAL (null, batches, different node counts, a judged or
+ * early-stopped prev, sp unlike prev's search, early_stop or skip set, more
+ * than 4096 iterations in prev), and as mpap_search.
+ */
+int mpap_search_update(const mpap_result *prev, const mpap_graph *g,
+                       const mpap_search_params *sp, void *stream, mpap_result **out);
+
 /* ----------------------------------------------------------------- misc */
 const char *mpap_status_string(int status);
 const char *mpap_last_error(void);

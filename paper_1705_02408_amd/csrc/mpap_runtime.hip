@@ -801,6 +801,14 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         }
     }
 
+    return search_goal_finish(g, p, L, w, s, res, a, dev_out, ms, retries);
+}
+
+int search_goal_finish(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Workspace *w,
+                       hipStream_t s, mpap_result *res, const SearchArgs &a,
+                       const long long *dev_out, float ms, int retries) {
+    const int nq = p.nq;
+    int r;
     // goal fronts (a7): exact per-query regions, the fronts, then packed
     std::vector<int> counts(nq, 0), qlast(nq, 0), qstop(nq, -2);
     {
@@ -841,6 +849,8 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         }
         HIP_TRY(hipMemcpyAsync(qlast.data(), w->qlast, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(qstop.data(), w->qstop, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+        unsigned ptop = 0;
+        HIP_TRY(hipMemcpyAsync(&ptop, w->pool_top, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (ovf) return fail(MPAP_ERR_OVERFLOW, "goal front pack overflow");
@@ -851,6 +861,7 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
                               hipMemcpyDeviceToHost));
         search_finish(res, p, dev_out, counts.data(), plab.data(), pnode.data(), qlast.data(),
                       qstop.data(), trace.data(), ms, retries, L);
+        res->pool_used = ptop;
     }
     return MPAP_OK;
 }

@@ -321,6 +321,12 @@ struct mpap_result {
     std::vector<int64_t> trace;
     mpap_stats stats{};
     long long arena_labels = 0;  // arena size: expanded labels + goal plans closed at a stop
+    unsigned long long pool_used = 0;  // bucket pool slots in use when the search ended
+    long long reused_arena = 0;  // an update: arena ids taken over from the earlier result
+    // an update: arena id where each expanded group starts (earlier results'
+    // groups first), and the arena size last; empty for a plain search (its
+    // trace has the group sizes)
+    std::vector<long long> group_start;
     std::vector<int2> arena_host;  // filled on first mpap_label_path
     bool arena_loaded = false;
     bool ws_borrowed = false;  // ws belongs to a plan (valid until its next run)
@@ -369,6 +375,11 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
                  hipStream_t s, mpap_result *res);
 SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
                        const SearchShape &L);
+// After a successful search launch with arguments a (device status words in
+// dev_out): goal fronts, host copies and statistics into res.
+int search_goal_finish(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Workspace *w,
+                       hipStream_t s, mpap_result *res, const SearchArgs &a,
+                       const long long *dev_out, float ms, int retries);
 // A search workspace of g for launch shape L (a spare one when it fits).
 int acquire_workspace(mpap_graph *g, const SearchShape &L, Workspace **out);
 GoalArgs goal_args(const mpap_graph *g, Workspace *w);

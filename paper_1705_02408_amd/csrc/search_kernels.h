@@ -110,6 +110,8 @@ struct SearchArgs {
     long long F_cap;
     int2 *arena;       // per expanded label {node, parent id}
     long long arena_cap;
+    long long arena_base;  // ids already in the arena when the launch starts (a re-search
+                           // that continues from an earlier result's labels); 0 otherwise
     long long *part_cnt;   // [2][nblocks]
     long long *part_open;  // [2][nblocks]
     long long *part_step;  // [2][nblocks] least iteration index with a non-empty group

@@ -1250,7 +1250,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
     unsigned epoch = 0;
     long long i_step = 0;  // iteration index: query q's threshold is i_step * qdelta[q]
     int wave = 0;          // number of groups expanded so far
-    long long abase = 0;   // arena ids handed out so far
+    long long abase = a.arena_base;  // arena ids handed out so far
     int it = 0;            // loop trips (parity of the partial sums)
     long long st_merges = 0, st_cand = 0;  // workgroup merges (thread 0 counts)
     long long wv_merges = 0, wv_cand = 0;  // single-wave merges (lane 0 counts)

@@ -81,7 +81,7 @@ SYMBOLS = [
     "mpap_surrogate_score", "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
     "mpap_plan_create", "mpap_plan_run", "mpap_plan_info", "mpap_plan_free",
     "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load", "mpap_search_noalloc",
-    "mpap_query_stop", "mpap_refine_front",
+    "mpap_query_stop", "mpap_refine_front", "mpap_graph_add_boxes", "mpap_search_update",
 ]
 
 _lib = None
@@ -142,6 +142,9 @@ def load(path: str = LIB_PATH):
     lib.mpap_search_noalloc.argtypes = [P, ctypes.POINTER(mpap_search_params), P, P, P, P, P,
                                         I32, P]
     lib.mpap_query_stop.argtypes = [P, I32, P]
+    lib.mpap_graph_add_boxes.argtypes = [P, I32, P, P, P, ctypes.POINTER(P)]
+    lib.mpap_search_update.argtypes = [P, P, ctypes.POINTER(mpap_search_params), P,
+                                       ctypes.POINTER(P)]
     lib.mpap_refine_front.argtypes = [P, I32, ctypes.c_float, I32, P, P, P, P, P, I32, P]
     lib.mpap_plan_free.argtypes = [P]
     lib.mpap_plan_free.restype = None
@@ -161,7 +164,8 @@ def load(path: str = LIB_PATH):
                  "mpap_surrogate_gradient", "mpap_surrogate_train", "mpap_surrogate_score",
                  "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
                  "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load",
-                 "mpap_search_noalloc", "mpap_query_stop", "mpap_refine_front"):
+                 "mpap_search_noalloc", "mpap_query_stop", "mpap_refine_front",
+                 "mpap_graph_add_boxes", "mpap_search_update"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -371,6 +375,26 @@ def mpap_search_noalloc(graph: Graph, beta: float, n_obj: int, radius: float,
     k = k.value
     return Front(np.stack([c[:k], d[:k], m[:k]], axis=1), gn[:k].copy(),
                  np.full(k, -1, np.int32))
+
+
+def mpap_graph_add_boxes(graph: Graph, box_lo, box_hi, stream=None) -> Graph:
+    """A new roadmap without the edges that collide with the added boxes."""
+    lo = np.ascontiguousarray(box_lo, np.float32)
+    hi = np.ascontiguousarray(box_hi, np.float32)
+    h = ctypes.c_void_p()
+    _check(load().mpap_graph_add_boxes(graph.handle, lo.shape[0], _p(lo), _p(hi),
+                                       _stream(stream), ctypes.byref(h)))
+    return Graph(h)
+
+
+def mpap_search_update(prev: Result, graph: Graph, beta: float, n_obj: int, radius: float,
+                       lam: float = 0.5, stream=None, **kw) -> Result:
+    """The search of ``graph`` continued from the earlier result ``prev``."""
+    sp = search_params(beta, n_obj, radius, lam, **kw)
+    h = ctypes.c_void_p()
+    _check(load().mpap_search_update(prev.handle, graph.handle, ctypes.byref(sp),
+                                     _stream(stream), ctypes.byref(h)))
+    return Result(h, graph)
 
 
 def mpap_query_stop(res: Result, query: int = 0) -> int:

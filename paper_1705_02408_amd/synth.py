@@ -36,6 +36,7 @@ TAG_QUERY = 4
 TAG_BATCH = 5
 TAG_VEL = 6
 TAG_EDGES = 7
+TAG_DISCOVER = 8
 
 
 def mix64(z):
@@ -190,6 +191,41 @@ def make_env(seed: int, dim: int, n: int, n_boxes: int, n_blobs: int,
                blob_amp=amp, goal=goal, goal_radius=float(np.float32(goal_radius)),
                radius=float(r), beta=float(np.float32(beta)), n_obj=n_obj,
                lam=float(np.float32(lam)), name=name, seed=seed)
+
+
+def discovered_boxes(env: Env, seed: int, count: int, hmin: float = 0.03,
+                     hmax: float = 0.08):
+    """Obstacles found after the roadmap was built (online updates): boxes
+    with uniform centres in the middle of the workspace ([0.25, 0.75] per
+    axis) and uniform half-extents, redrawn if they cover the start or touch
+    the goal ball.  Returns (lo, hi) float32 [count, dim]."""
+    s = Stream(seed, TAG_DISCOVER)
+    d = env.wdim
+    init = env.pos[0][:d]
+    goal64 = np.asarray(env.goal, np.float64)
+    lo_l, hi_l = [], []
+    while len(lo_l) < count:
+        u = s.uniform(2 * d)
+        c = np.float32(0.25) + np.float32(0.5) * u[:d]
+        h = np.float32(hmin) + np.float32(hmax - hmin) * u[d:]
+        lo = (c - h).astype(np.float32)
+        hi = (c + h).astype(np.float32)
+        if np.all(init >= lo) and np.all(init <= hi):
+            continue
+        near = np.clip(goal64, lo.astype(np.float64), hi.astype(np.float64))
+        if float(np.sum((near - goal64) ** 2)) <= float(env.goal_radius) ** 2:
+            continue
+        lo_l.append(lo)
+        hi_l.append(hi)
+    return (np.array(lo_l, dtype=np.float32).reshape(count, d),
+            np.array(hi_l, dtype=np.float32).reshape(count, d))
+
+
+def with_boxes(env: Env, lo, hi) -> Env:
+    """The same instance (same samples) with the boxes added to its map."""
+    return dataclasses.replace(env, box_lo=np.concatenate([env.box_lo, lo]).astype(np.float32),
+                               box_hi=np.concatenate([env.box_hi, hi]).astype(np.float32),
+                               name=env.name + f"_plus{lo.shape[0]}boxes")
 
 
 def plain2d(seed: int = 0, n: int = 2000) -> Env:
