@@ -513,6 +513,67 @@ int mpap_graph_add_boxes(const mpap_graph *g, int32_t n_boxes, const float *box_
 int mpap_search_update(const mpap_result *prev, const mpap_graph *g,
                        const mpap_search_params *sp, void *stream, mpap_result **out);
 
+/*
+ * Monte Carlo verification of a plan (Sec. 3, final phase: an estimate by
+ * sampling of the probability that the plan keeps the localisation error
+ * within a bound when it is flown; the system and localisation models of
+ * Sec. 4.1).  The model, fixed where the paper gives only its structure:
+ * the nominal trajectory is, per edge, the minimum-energy cubic between
+ * its two states: at rest at both nodes over 1.5 length / speed (2D/3D
+ * roadmaps; peak speed `speed`), the roadmap's states over the steering
+ * time (6D); per axis a double integrator with applied acceleration u + sigma_w xi
+ * tracks it (feed-forward: the nominal velocity change over the step;
+ * feedback: the steady-state discrete LQR gain for Q = diag(q_p, q_v),
+ * R = r_u) from a Kalman estimate predicted with the measured acceleration
+ * (noise sigma_a) and corrected by a position fix of noise sigma_v / sqrt(q)
+ * wherever the feature quality q of the map is >= q_min; the start position
+ * is off by sigma_0 per axis.  Steps of dt (float64 state); normals from
+ * Philox4x32-10 keyed by seed.  A flight succeeds when its largest
+ * localisation error stays <= err_bound and no true position lies in a box.
+ */
+typedef struct {
+    int32_t rollouts;  /* sampled flights (>= 1) */
+    float dt;          /* time step (s, > 0) */
+    float speed;       /* 2D/3D: peak nominal speed along each segment (> 0) */
+    float sigma_w;     /* std of the applied-acceleration noise per step */
+    float sigma_a;     /* std of the accelerometer noise per step */
+    float sigma_v;     /* std of a position fix at feature quality 1 (> 0) */
+    float q_min;       /* least feature quality that gives a fix */
+    float sigma0;      /* std of the initial position error per axis */
+    float err_bound;   /* localisation error bound */
+    float q_p, q_v;    /* LQR state weights (>= 0) */
+    float r_u;         /* LQR control weight (> 0) */
+    uint64_t seed;     /* Philox key (low word, high word) */
+} mpap_mc_params;
+
+typedef struct {
+    int64_t rollouts;
+    int64_t within_bound;    /* flights whose largest localisation error <= err_bound */
+    int64_t collision_free;  /* flights that never entered a box */
+    int64_t success;         /* both */
+    int32_t steps;           /* time steps K of the nominal trajectory */
+    double duration;         /* its duration (s) */
+    double mean_max_err;     /* mean over flights of the largest error */
+    double max_max_err;      /* the largest over all flights (-1 if max_err was NULL) */
+    double gain_p, gain_v;   /* the LQR gain used */
+    float gpu_ms;            /* device time of the flights */
+} mpap_mc_stats;
+
+/* mpap_mc_verify - sample mp->rollouts flights of the plan through
+ *   nodes[0 .. n_nodes) (host; a plan's node sequence as mpap_label_path gives
+ *   it, root first; consecutive nodes are flown straight from rest to rest in
+ *   2D/3D, along the steering cubic in 6D) on roadmap g (built by mpap_build_graph: its
+ *   samples, blobs and boxes).  max_err (nullable, host double [rollouts])
+ *   and collided (nullable, host u8 [rollouts]) receive the per-flight
+ *   outcomes.
+ * Errors: MPAP_ERR_INVAL (null, an imported or batched roadmap, fewer than
+ * two nodes, a node out of range, non-positive dt, speed, sigma_v or r_u,
+ * negative or non-finite parameters, more than 1e8 steps), MPAP_ERR_NOMEM,
+ * MPAP_ERR_HIP. */
+int mpap_mc_verify(const mpap_graph *g, const int32_t *nodes, int32_t n_nodes,
+                   const mpap_mc_params *mp, void *stream, double *max_err, uint8_t *collided,
+                   mpap_mc_stats *out);
+
 /* ----------------------------------------------------------------- misc */
 const char *mpap_status_string(int status);
 const char *mpap_last_error(void);

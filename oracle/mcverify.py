@@ -10,8 +10,10 @@ noise drives the prediction of a Kalman filter, and position fixes from the
 mapped features correct it.  The paper gives the structure, not the numbers,
 so the model is fixed here (the same one the library's kernels run):
 
-* nominal trajectory: 2D/3D roadmaps -- the plan's polyline flown at a
-  constant speed (velocity constant per segment, no nominal acceleration);
+* nominal trajectory: 2D/3D roadmaps -- the plan's polyline flown from rest
+  to rest along every segment (the minimum-energy cubic between the two
+  nodes at zero velocity, over 1.5 length / speed, so the peak speed is
+  ``speed``; a double integrator cannot follow a corner at speed);
   6D roadmaps -- per edge the cubic through both states over the steering
   time T (the fixed-time minimum-energy trajectory of a double integrator),
   with its velocity and acceleration; sampled at t_k = k dt, k = 0..K with
@@ -19,9 +21,12 @@ so the model is fixed here (the same one the library's kernels run):
 * per axis (identical axes) x = (p, v), x_{k+1} = A x_k + B a_k with
   A = [[1, dt], [0, 1]], B = [dt^2/2, dt]; applied acceleration
   a_k = u_k + sigma_w xi_k;
-* control u_k = a_nom,k - k_p (p_hat_k - p_nom,k) - k_v (v_hat_k - v_nom,k),
-  the steady-state discrete LQR gain for Q = diag(q_p, q_v), R = r_u
-  (Riccati recursion from P = Q, a fixed 20,000 steps);
+* control u_k = (v_nom,k+1 - v_nom,k) / dt - k_p (p_hat_k - p_nom,k)
+  - k_v (v_hat_k - v_nom,k): the feed-forward is the nominal velocity change
+  over the step (the discrete double integrator then keeps the nominal
+  velocity exactly), the feedback the steady-state discrete LQR gain for
+  Q = diag(q_p, q_v), R = r_u (Riccati recursion from P = Q, a fixed 20,000
+  steps);
 * Kalman filter: prediction with the measured acceleration a_k + sigma_a eta_k
   and process covariance sigma_a^2 B B^T; a position fix at the new true
   position when the feature quality there is q >= q_min, with noise variance
@@ -105,21 +110,29 @@ def lqr_gain(dt: float, q_p: float, q_v: float, r_u: float, steps: int = 20000):
 
 
 def nominal_segments(pts, speed: float, dt: float):
-    """Polyline through pts (float32 [m, d]) at constant speed: p, v, a
-    float64 [K+1, d] at t_k = k dt (clamped to the end)."""
+    """The polyline through pts (float32 [m, d]) flown from rest to rest along
+    every segment: per segment the cubic between the two nodes at zero
+    velocity (the cubic of nominal_cubic with v0 = v1 = 0) over the time
+    1.5 length / speed, so that the peak speed (at mid-segment) is ``speed``;
+    p, v, a float64 [K+1, d] at t_k = k dt (clamped to the end)."""
     P = np.asarray(pts, np.float64)
     seg = P[1:] - P[:-1]
     length = np.sqrt((seg * seg).sum(axis=1))
-    dur = length / speed
+    dur = 1.5 * length / speed
     tau = np.concatenate([[0.0], np.cumsum(dur)])
     total = tau[-1]
     K = max(1, int(math.ceil(total / dt)))
     t = np.minimum(np.arange(K + 1) * dt, total)
     i = np.clip(np.searchsorted(tau, t, side="right") - 1, 0, len(dur) - 1)
-    s = (t - tau[i]) / dur[i]
-    p = P[i] + s[:, None] * seg[i]
-    v = seg[i] / dur[i][:, None]
-    return p, v, np.zeros_like(p)
+    s = (t - tau[i])[:, None]
+    T = dur[i][:, None]
+    p0, p1 = P[i], P[i + 1]
+    c2 = (3.0 * (p1 - p0)) / (T * T)
+    c3 = (2.0 * (p0 - p1)) / (T * T * T)
+    p = p0 + c2 * s * s + c3 * s * s * s
+    v = 2.0 * c2 * s + 3.0 * c3 * s * s
+    a = 2.0 * c2 + 6.0 * c3 * s
+    return p, v, a
 
 
 def nominal_cubic(states_p, states_v, horizon: float, dt: float):
@@ -161,14 +174,14 @@ def quality(x, mu, sig, amp):
 class MCParams:
     """Model constants (float32 values, as the library takes them)."""
     rollouts: int = 4096
-    dt: float = 0.01
-    speed: float = 1.0
-    sigma_w: float = 0.5
-    sigma_a: float = 1.0
+    dt: float = 0.005
+    speed: float = 0.5
+    sigma_w: float = 0.1
+    sigma_a: float = 0.1
     sigma_v: float = 0.005
-    q_min: float = 0.5
+    q_min: float = 0.8
     sigma0: float = 0.002
-    err_bound: float = 0.02
+    err_bound: float = 0.05
     q_p: float = 100.0
     q_v: float = 20.0
     r_u: float = 1.0
@@ -228,7 +241,8 @@ def rollouts(p_nom, v_nom, a_nom, mp: MCParams, mu, sig, amp, box_lo, box_hi,
         z = np.concatenate([normals(mp.seed, k, ids[:, None], j) for j in range(nz)],
                            axis=-1).reshape(R, -1)
         xi, eta, zeta = z[:, :d], z[:, d:2 * d], z[:, 2 * d:3 * d]
-        u = a_nom[k][None, :] - kp * (ph - p_nom[k][None, :]) - kv * (vh - v_nom[k][None, :])
+        ff = (v_nom[k + 1] - v_nom[k]) / dt
+        u = ff[None, :] - kp * (ph - p_nom[k][None, :]) - kv * (vh - v_nom[k][None, :])
         a = u + sw * xi
         p = p + v * dt + half * a
         v = v + dt * a

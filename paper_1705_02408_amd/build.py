@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpap.so")
 SOURCES = ["mpap_runtime.hip", "search_kernels.hip", "graph_kernels.hip", "mlp_kernels.hip",
            "surrogate_runtime.hip", "plan_runtime.hip", "judge_runtime.hip",
-           "steer_kernels.hip", "noalloc_runtime.hip", "update_runtime.hip"]
+           "steer_kernels.hip", "noalloc_runtime.hip", "update_runtime.hip",
+           "mc_runtime.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

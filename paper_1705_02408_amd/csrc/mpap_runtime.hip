@@ -244,8 +244,9 @@ static int build_graph6(const mpap_env *env, const mpap_graph_params *gp, void *
     g->check_step = gp->check_step; g->reset_q = gp->reset_q; g->radius = gp->radius;
     g->horizon = gp->horizon; g->traj_steps = gp->traj_steps; g->k_out = k_out;
     g->pos = d_pos; g->vel = d_vel; g->bmu = d_mu; g->bsig = d_sig; g->bamp = d_amp;
+    g->blo = d_blo; g->bhi = d_bhi;
     g->elen = elen;
-    d_pos = d_vel = d_mu = d_sig = d_amp = elen = nullptr;
+    d_pos = d_vel = d_mu = d_sig = d_amp = elen = d_blo = d_bhi = nullptr;
     cleanup();
     *out = g;
     return MPAP_OK;
@@ -376,7 +377,8 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
     g->dim = dim; g->nbox = env->n_boxes; g->nblob = env->n_blobs;
     g->check_step = gp->check_step; g->reset_q = gp->reset_q; g->radius = gp->radius;
     g->pos = d_pos; g->bmu = d_mu; g->bsig = d_sig; g->bamp = d_amp;
-    d_pos = d_mu = d_sig = d_amp = nullptr;
+    g->blo = d_blo; g->bhi = d_bhi;
+    d_pos = d_mu = d_sig = d_amp = d_blo = d_bhi = nullptr;
     cleanup();
     if (hg == 0) {
         graph_release(g);
@@ -1132,6 +1134,7 @@ void graph_release(mpap_graph *g) {
     dfree(g->optr); dfree(g->ocol); dfree(g->ocost); dfree(g->odrift);
     dfree(g->nflag); dfree(g->goal_list); dfree(g->qoff); dfree(g->qgoff);
     dfree(g->pos); dfree(g->bmu); dfree(g->bsig); dfree(g->bamp); dfree(g->feat); dfree(g->sbase); dfree(g->sdrift);
+    dfree(g->blo); dfree(g->bhi);
     dfree(g->vel); dfree(g->elen); dfree(g->rperm); dfree(g->srdrift);
     delete g;
 }

@@ -113,6 +113,7 @@ struct mpap_graph {
     int dim = 0, nbox = 0, nblob = 0;
     float check_step = 0.f, reset_q = 0.f, radius = 0.f;
     float *pos = nullptr, *bmu = nullptr, *bsig = nullptr, *bamp = nullptr;
+    float *blo = nullptr, *bhi = nullptr;  // obstacle boxes [nbox][w] (closed), w = 3 for dim 6
     // double integrator (dim 6): velocities, steering time, check steps, and
     // the trajectory length of every edge (the drift's length)
     float *vel = nullptr, *elen = nullptr;

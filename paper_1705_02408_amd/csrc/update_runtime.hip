@@ -285,7 +285,9 @@ int mpap_graph_add_boxes(const mpap_graph *gc, int32_t n_boxes, const float *box
         (r = dalloc(&ng->ocost, e_new)) || (r = dalloc(&ng->odrift, e_new)) ||
         (r = dalloc(&ng->nflag, n)) || (r = dalloc(&ng->goal_list, std::max(g->n_goal, 1))) ||
         (r = dalloc(&ng->pos, (size_t)n * dim)) || (r = dalloc(&ng->bmu, nf * dim)) ||
-        (r = dalloc(&ng->bsig, nf)) || (r = dalloc(&ng->bamp, nf)))
+        (r = dalloc(&ng->bsig, nf)) || (r = dalloc(&ng->bamp, nf)) ||
+        (r = dalloc(&ng->blo, (size_t)(g->nbox + n_boxes) * dim)) ||
+        (r = dalloc(&ng->bhi, (size_t)(g->nbox + n_boxes) * dim)))
         return bail(r);
     if (m > 0) {
         k_compact_edges<<<div_up(m, 256), 256, 0, s>>>(m, keep, kscan, g->ocol, g->ocost,
@@ -300,7 +302,11 @@ int mpap_graph_add_boxes(const mpap_graph *gc, int32_t n_boxes, const float *box
         (r = copy_d2d(ng->goal_list, g->goal_list, g->n_goal, s)) ||
         (r = copy_d2d(ng->pos, g->pos, (size_t)n * dim, s)) ||
         (r = copy_d2d(ng->bmu, g->bmu, nf * dim, s)) || (r = copy_d2d(ng->bsig, g->bsig, nf, s)) ||
-        (r = copy_d2d(ng->bamp, g->bamp, nf, s)))
+        (r = copy_d2d(ng->bamp, g->bamp, nf, s)) ||
+        (r = copy_d2d(ng->blo, g->blo, (size_t)g->nbox * dim, s)) ||
+        (r = copy_d2d(ng->bhi, g->bhi, (size_t)g->nbox * dim, s)) ||
+        (r = copy_d2d(ng->blo + (size_t)g->nbox * dim, d_blo, nb_, s)) ||
+        (r = copy_d2d(ng->bhi + (size_t)g->nbox * dim, d_bhi, nb_, s)))
         return bail(r);
     ng->rptr = ng->optr; ng->rsrc = ng->ocol; ng->rcost = ng->ocost; ng->rdrift = ng->odrift;
     ng->dim = dim; ng->nbox = g->nbox + n_boxes; ng->nblob = g->nblob;

@@ -69,6 +69,24 @@ class mpap_stats(ctypes.Structure):
                 ("judged_failed", ctypes.c_int32), ("fallback_ms", ctypes.c_float)]
 
 
+class mpap_mc_params(ctypes.Structure):
+    _fields_ = [("rollouts", ctypes.c_int32), ("dt", ctypes.c_float), ("speed", ctypes.c_float),
+                ("sigma_w", ctypes.c_float), ("sigma_a", ctypes.c_float),
+                ("sigma_v", ctypes.c_float), ("q_min", ctypes.c_float),
+                ("sigma0", ctypes.c_float), ("err_bound", ctypes.c_float),
+                ("q_p", ctypes.c_float), ("q_v", ctypes.c_float), ("r_u", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class mpap_mc_stats(ctypes.Structure):
+    _fields_ = [("rollouts", ctypes.c_int64), ("within_bound", ctypes.c_int64),
+                ("collision_free", ctypes.c_int64), ("success", ctypes.c_int64),
+                ("steps", ctypes.c_int32), ("duration", ctypes.c_double),
+                ("mean_max_err", ctypes.c_double), ("max_max_err", ctypes.c_double),
+                ("gain_p", ctypes.c_double), ("gain_v", ctypes.c_double),
+                ("gpu_ms", ctypes.c_float)]
+
+
 SYMBOLS = [
     "mpap_build_graph", "mpap_graph_from_csr", "mpap_graph_info", "mpap_graph_export",
     "mpap_graph_free", "mpap_search", "mpap_goal_front", "mpap_node_front",
@@ -82,6 +100,7 @@ SYMBOLS = [
     "mpap_plan_create", "mpap_plan_run", "mpap_plan_info", "mpap_plan_free",
     "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load", "mpap_search_noalloc",
     "mpap_query_stop", "mpap_refine_front", "mpap_graph_add_boxes", "mpap_search_update",
+    "mpap_mc_verify",
 ]
 
 _lib = None
@@ -142,6 +161,8 @@ def load(path: str = LIB_PATH):
     lib.mpap_search_noalloc.argtypes = [P, ctypes.POINTER(mpap_search_params), P, P, P, P, P,
                                         I32, P]
     lib.mpap_query_stop.argtypes = [P, I32, P]
+    lib.mpap_mc_verify.argtypes = [P, P, I32, ctypes.POINTER(mpap_mc_params), P, P, P,
+                                   ctypes.POINTER(mpap_mc_stats)]
     lib.mpap_graph_add_boxes.argtypes = [P, I32, P, P, P, ctypes.POINTER(P)]
     lib.mpap_search_update.argtypes = [P, P, ctypes.POINTER(mpap_search_params), P,
                                        ctypes.POINTER(P)]
@@ -165,7 +186,7 @@ def load(path: str = LIB_PATH):
                  "mpap_graph_drift", "mpap_rescore_front", "mpap_analytic_drift",
                  "mpap_judge", "mpap_surrogate_save", "mpap_surrogate_load",
                  "mpap_search_noalloc", "mpap_query_stop", "mpap_refine_front",
-                 "mpap_graph_add_boxes", "mpap_search_update"):
+                 "mpap_graph_add_boxes", "mpap_search_update", "mpap_mc_verify"):
         getattr(lib, name).restype = ctypes.c_int
     _ = I64
     _lib = lib
@@ -395,6 +416,32 @@ def mpap_search_update(prev: Result, graph: Graph, beta: float, n_obj: int, radi
     _check(load().mpap_search_update(prev.handle, graph.handle, ctypes.byref(sp),
                                      _stream(stream), ctypes.byref(h)))
     return Result(h, graph)
+
+
+MC_DEFAULTS = dict(rollouts=4096, dt=0.005, speed=0.5, sigma_w=0.1, sigma_a=0.1, sigma_v=0.005,
+                   q_min=0.8, sigma0=0.002, err_bound=0.05, q_p=100.0, q_v=20.0, r_u=1.0,
+                   seed=1)
+
+
+def mpap_mc_verify(graph: Graph, nodes, with_samples: bool = True, stream=None, **kw):
+    """Monte Carlo verification of the plan through ``nodes`` (root first).
+    Keyword arguments override MC_DEFAULTS.  Returns (stats dict, max_err
+    float64 [R] or None, collided bool [R] or None)."""
+    path = np.ascontiguousarray(nodes, np.int32)
+    p = dict(MC_DEFAULTS, **kw)
+    mp = mpap_mc_params(int(p["rollouts"]), *(float(p[k]) for k in (
+        "dt", "speed", "sigma_w", "sigma_a", "sigma_v", "q_min", "sigma0", "err_bound", "q_p",
+        "q_v", "r_u")), int(p["seed"]))
+    R = mp.rollouts
+    me = np.empty(R, np.float64) if with_samples else None
+    co = np.empty(R, np.uint8) if with_samples else None
+    st = mpap_mc_stats()
+    _check(load().mpap_mc_verify(graph.handle, _p(path), path.shape[0], ctypes.byref(mp),
+                                 _stream(stream),
+                                 _p(me) if with_samples else None,
+                                 _p(co) if with_samples else None, ctypes.byref(st)))
+    stats = {f: getattr(st, f) for f, _ in mpap_mc_stats._fields_}
+    return stats, me, (co.astype(bool) if with_samples else None)
 
 
 def mpap_query_stop(res: Result, query: int = 0) -> int:

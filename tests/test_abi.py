@@ -65,7 +65,7 @@ def test_binding_structs_match_the_header(tmp_path):
     import subprocess
     from paper_1705_02408_amd import mpap
     structs = [getattr(mpap, n) for n in ("mpap_env", "mpap_graph_params", "mpap_search_params",
-                                          "mpap_stats")]
+                                          "mpap_stats", "mpap_mc_params", "mpap_mc_stats")]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpap.h"', 'int main(void) {']
     for st in structs:
         name = st.__name__
