@@ -214,6 +214,94 @@ def cpu_whole_search(env):
             "sample": "the whole search of the same workload (oracle roadmap, one thread)"}
 
 
+# ------------------------------------------------------------ online update
+def measure_update(env, reps: int = 3):
+    """Obstacles found after the search (Sec. 3, online implementation): five
+    boxes added to the roadmap (only the new collision checks), the search
+    continued from the earlier labels, against a fresh search of the changed
+    roadmap (wall times of the whole calls, fronts compared)."""
+    import numpy as np
+    import torch
+    from paper_1705_02408_amd import mpap, synth
+    lo, hi = synth.discovered_boxes(env, 4, 5)
+    g0 = mpap.mpap_build_graph(env)
+    r0 = mpap.mpap_search(g0, env.beta, env.n_obj, env.radius, env.lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g1 = mpap.mpap_graph_add_boxes(g0, lo, hi)
+    torch.cuda.synchronize()
+    add_ms = 1e3 * (time.perf_counter() - t0)
+    upd_ms, fresh_ms = [], []
+    for _ in range(reps + 1):
+        ts = time.perf_counter()
+        upd = mpap.mpap_search_update(r0, g1, env.beta, env.n_obj, env.radius, env.lam)
+        upd_ms.append(1e3 * (time.perf_counter() - ts))
+        ts = time.perf_counter()
+        fresh = mpap.mpap_search(g1, env.beta, env.n_obj, env.radius, env.lam)
+        fresh_ms.append(1e3 * (time.perf_counter() - ts))
+        same = np.array_equal(upd.goal_front().vecs.view(np.uint32),
+                              fresh.goal_front().vecs.view(np.uint32))
+        su, sf = upd.stats(), fresh.stats()
+        upd.close()
+        fresh.close()
+    out = {"workload": f"{env.name} + 5 boxes found after the search",
+           "edges_removed": g0.info()["e"] - g1.info()["e"], "add_boxes_ms": add_ms,
+           "update_ms": statistics.median(upd_ms[1:]), "fresh_search_ms": statistics.median(fresh_ms[1:]),
+           "update_kernel_ms": su["gpu_ms"], "fresh_kernel_ms": sf["gpu_ms"],
+           "update_labels_expanded": su["labels_expanded"],
+           "fresh_labels_expanded": sf["labels_expanded"],
+           "same_goal_front": bool(same), "front_labels": sf["front_labels"]}
+    out["speedup"] = out["fresh_search_ms"] / out["update_ms"]
+    r0.close()
+    g1.close()
+    g0.close()
+    log(f"# online update: {out}")
+    return out
+
+
+# --------------------------------------------------------- MC verification
+def measure_mc(env, flights: int = 262144, cpu_flights: int = 256):
+    """Monte Carlo verification of two plans of the goal front (the cheapest,
+    P_soln, and the one of least largest drift): GPU flights/s, the outcome
+    rates, and the oracle on a bounded sample of flights on one host core."""
+    import numpy as np
+    from oracle import mcverify as omc
+    from paper_1705_02408_amd import mpap
+    dg = mpap.mpap_build_graph(env)
+    res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam)
+    fr = res.goal_front()
+    out = {"workload": f"{env.name}: goal front {fr.vecs.shape[0]} plans",
+           "model": dict(mpap.MC_DEFAULTS, rollouts=flights), "plans": {}}
+    picks = {"least_cost": 0, "least_max_drift": int(np.argmin(fr.vecs[:, 2]))}
+    for name, k in picks.items():
+        path = res.path(int(fr.label[k]))
+        mpap.mpap_mc_verify(dg, path, with_samples=False, rollouts=1024)  # warm
+        st, _, _ = mpap.mpap_mc_verify(dg, path, with_samples=False, rollouts=flights)
+        out["plans"][name] = {
+            "cost_drift_maxdrift": [float(x) for x in fr.vecs[k]], "nodes": len(path),
+            "steps": st["steps"], "flight_s": st["duration"], "gpu_ms": st["gpu_ms"],
+            "flights_per_s": flights / (st["gpu_ms"] * 1e-3),
+            "flight_steps_per_s": flights * st["steps"] / (st["gpu_ms"] * 1e-3),
+            "within_bound": st["within_bound"] / flights,
+            "collision_free": st["collision_free"] / flights,
+            "success": st["success"] / flights, "mean_max_err": st["mean_max_err"]}
+    # the oracle on a bounded sample of the cheapest plan's flights
+    path = res.path(int(fr.label[0]))
+    mp = omc.MCParams(rollouts=cpu_flights)
+    p, v, a = omc.nominal_segments(env.pos[path], mp.f64("speed"), mp.f64("dt"))
+    t0 = time.perf_counter()
+    omc.rollouts(p, v, a, mp, env.blob_mu, env.blob_sigma, env.blob_amp, env.box_lo, env.box_hi)
+    cpu_s = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": cpu_flights / cpu_s, "unit": "flights/s", "cores": 1,
+                           "kind": "oracle",
+                           "sample": f"{cpu_flights} flights of the cheapest plan, numpy float64 "
+                                     f"vectorised over flights, one core, {cpu_s:.2f} s"}
+    res.close()
+    dg.close()
+    log(f"# MC verification: {out['plans']}")
+    return out
+
+
 # ------------------------------------------------------------------- batch
 def surrogate_error_stats(ana, sur, held, beta):
     import numpy as np
@@ -592,6 +680,9 @@ def main():
                 r["cpu_baseline"] = cpu_whole_search(env2)
             rows[name] = r
         out["configs"] = rows
+    if headline_3d and not args.no_configs:
+        out["online_update"] = measure_update(env)
+        out["mc_verification"] = measure_mc(env)
     if not args.no_batch and headline_3d:
         out["batched_serving"] = measure_batch(args, with_surrogate=not args.no_surrogate)
     print(json.dumps(out), flush=True)
