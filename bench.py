@@ -578,7 +578,8 @@ def run_copy(args):
 def run_batch(args):
     b = measure_batch(args, with_surrogate=not args.no_surrogate)
     out = {
-        "metric": "queries/s (batched, learned drift judged per query, exact fallback)",
+        "metric": ("queries/s (batched, learned drift judged per query, exact fallback)"
+                   if b["batched_surrogate"] else "queries/s (batched, analytic drift)"),
         "value": b["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
         "steps": args.batch_steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * (b["batched_surrogate"] or b["batched_analytic"])["step_wall_s"],
