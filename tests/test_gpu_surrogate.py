@@ -183,7 +183,10 @@ def test_surrogate_gain_on_fine_drift_integration():
 def test_network_improves_on_the_eight_point_base(road3d):
     """What the trained network adds: on held-out edges its prediction
     (base + network) is closer to the analytic drift than the 8-point base
-    alone (the estimate the network corrects)."""
+    alone (the estimate the network corrects), in the median and in the root
+    mean square.  Trained on only 65,536 edges of this 3,000-sample roadmap
+    its p99 is worse than the base's (0.059 against 0.039); the tail at the
+    training size of the batched workload is asserted separately below."""
     env, dg = road3d
     e = dg.info()["e"]
     perm = np.random.default_rng(8).permutation(e)
@@ -212,3 +215,43 @@ def test_network_improves_on_the_eight_point_base(road3d):
     assert np.median(err_net) < 0.5 * np.median(err_base)
     assert rms_net < 0.7 * rms_base
     s.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_network_tail_at_training_scale(dim):
+    """The held-out tail of the relative drift error at the size the networks
+    are trained at for the batched workload (2^20 edges, 8 epochs, the
+    training roadmaps of that workload): the network's p99 stays below the
+    1e-2 gate of the front judge and within 1.25x of the 8-point base's p99
+    (measured: 2D 0.63x, 3D 1.02x).  The tail edges are those whose quality
+    peaks lie between the nine sample points the features carry; weighting
+    the training towards small-drift edges did not lower it."""
+    if dim == 2:
+        env = synth.make_env(10_000, 2, 50000, 20, 30, 20.0, 0.3, 2, blob_amp=0.3)
+    else:
+        env = synth.make_env(20_000, 3, 30000, 100, 80, 40.0, 0.25, 2, blob_amp=0.4)
+    dg = mpap.mpap_build_graph(env)
+    e = dg.info()["e"]
+    n_train = min(1 << 20, (e // 4096) * 4096)
+    perm = np.random.default_rng(dim).permutation(e)
+    held = perm[n_train:]
+    assert held.size > 50000
+    s = mpap.Surrogate(seed=dim)
+    s.train(dg, perm[:n_train], epochs=8, batch=4096, lr=2e-3)
+    s.score(dg)
+    ana = mpap.mpap_graph_drift(dg, 0).astype(np.float64)
+    sur = mpap.mpap_graph_drift(dg, 1).astype(np.float64)
+    _, base = mpap.mpap_edge_features(dg, with_base=True)
+    only_base = dg.export()["cost"].astype(np.float64) * np.clip(base.astype(np.float64), 0, 1)
+    floor = 1e-3 * env.beta
+    err_net = np.abs(sur - ana)[held] / np.maximum(ana[held], floor)
+    err_base = np.abs(only_base - ana)[held] / np.maximum(ana[held], floor)
+    p_net, p_base = np.percentile(err_net, 99), np.percentile(err_base, 99)
+    print(f"{dim}D held-out p99: base {p_base:.3g}, base + network {p_net:.3g} "
+          f"(ratio {p_net / p_base:.2f}); p50 {np.median(err_base):.3g} -> "
+          f"{np.median(err_net):.3g}", flush=True)
+    assert p_net < 1e-2
+    assert p_net <= 1.25 * p_base
+    assert np.median(err_net) < np.median(err_base)
+    s.close()
+    dg.close()
