@@ -170,6 +170,14 @@ typedef struct {
                                  goal node; its goal front is then the Pareto minimum
                                  of P_candidates at that point (entry 0 = P_soln), which
                                  depends on lambda and need not be the exact front */
+    int32_t merge_halves;     /* tuning: merges by halves.  With 1024-thread workgroups,
+                                 in iterations with at least two merge targets per
+                                 workgroup, each half of a workgroup merges its own
+                                 targets (two at once per CU); large fronts and targets
+                                 with more than merge_halves children (0: 8192) take the
+                                 whole workgroup.  0 = on for roadmaps of at least
+                                 16 x (workgroups) nodes; > 0 = on; < 0 = off.  Never
+                                 changes the result. */
 } mpap_search_params;
 
 /*
@@ -303,6 +311,12 @@ typedef struct {
                                  iterations with many small targets), 0: the weight-ordered one */
     int32_t judged_failed;    /* queries whose learned-drift front mpap_judge rejected */
     float fallback_ms;        /* device time of the analytic re-search of those queries */
+    int32_t half_front_cap;   /* front stage of a half workgroup when merges ran by halves
+                                 (two targets at once per workgroup), else 0 */
+    int32_t reserved;
+    int64_t half_merges;      /* merges done by half workgroups */
+    int64_t half_backouts;    /* targets whose front outgrew a half's stage: the half backed
+                                 out (nothing written) and the whole workgroup merged them */
 } mpap_stats;
 
 int mpap_result_stats(const mpap_result *r, mpap_stats *out);

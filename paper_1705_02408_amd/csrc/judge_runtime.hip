@@ -180,8 +180,9 @@ int mpap_judge(mpap_result *r, float tol, int32_t fallback, void *stream, uint8_
     p.stage_cap = r->stage_cap;
     p.block_threads = r->block_threads;
     p.wave_min_targets = r->wave_min_targets;
+    p.merge_halves = r->merge_halves;
     SearchShape L;
-    int rc = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L);
+    int rc = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L, p.merge_halves);
     if (rc) return rc;
     Workspace *w = nullptr;
     if ((rc = acquire_workspace(g, L, &w))) return rc;

@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) k_mc_rollout(McArgs a) {
     if (r < a.rollouts) {
         const double dt = a.dt, h = 0.5 * dt * dt;
         const double kp = a.gain[0], kv = a.gain[1];
-        const double *pn = a.nm.p, *vn = a.nm.v, *an = a.nm.a;
+        const double *pn = a.nm.p, *vn = a.nm.v;
         double p[3], v[3], ph[3], vh[3], z[10];
         normals(a.k0, a.k1, kMcStartStep, (uint32_t)r, d, z);
         double e2 = 0.0;

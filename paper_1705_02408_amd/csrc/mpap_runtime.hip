@@ -553,6 +553,7 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
             return fail(MPAP_ERR_INVAL, "block_threads must be 0, 256, 512 or 1024");
         if (x.block_threads != 0) p.block_threads = x.block_threads;
         if (x.wave_min_targets != 0) p.wave_min_targets = x.wave_min_targets;
+        if (x.merge_halves != 0) p.merge_halves = x.merge_halves;
         if (x.skip != 0 && x.skip != 1) return fail(MPAP_ERR_INVAL, "skip must be 0 or 1");
         if (x.early_stop != 0 && x.early_stop != 1)
             return fail(MPAP_ERR_INVAL, "early_stop must be 0 or 1");
@@ -584,7 +585,8 @@ int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, 
     return MPAP_OK;
 }
 
-int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchShape &L) {
+int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchShape &L,
+                 int merge_halves) {
     DeviceInfo di;
     int r = device_info(&di);
     if (r) return r;
@@ -624,6 +626,27 @@ int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchS
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search, L.threads, L.lds));
     if (per_cu < 1) return fail(MPAP_ERR_DEVICE, "search kernel does not fit on a CU");
     L.nblocks = di.cus * std::min(per_cu, per_cu_want);
+    // merges by halves: each half of a 1024-thread workgroup gets half the
+    // LDS, a 512-label chunk and the largest front stage that fits
+    if (merge_halves >= 0 && L.threads == 1024 && L.nblocks == di.cus) {
+        const int ch = 512;
+        const size_t half = (L.lds / 2) & ~(size_t)15;
+        const size_t hfixed = 16 * (size_t)ch + 16 * 512 + 8 * (size_t)ch + 128 + 32 + ch;
+        long long cb = half > hfixed + 16 ? (long long)(((half - hfixed - 16) * 64) / (17 * 64 + 8)) : 0;
+        cb -= cb % 64;
+        if (stage_cap > 0) cb = std::min<long long>(cb, std::max(stage_cap - stage_cap % 64, 64));
+        const size_t need = hfixed + 17 * (size_t)cb + 8 * (size_t)(std::max<long long>(cb, ch) / 64 + 2);
+        if (cb >= 1024 && need <= half) {
+            L.halves = 1;
+            L.half_lds = (int)half;
+            L.capBh = (int)cb;
+            L.capCh = ch;
+            L.big_front = (int)(3 * cb / 4);
+            L.big_children = merge_halves > 0 ? std::min(merge_halves, 1 << 24) : 8192;
+            L.halves_min = 2 * L.nblocks;
+            L.halves_forced = merge_halves > 0;
+        }
+    }
     // by default a wave-per-target iteration needs four small targets per wave
     if (wave_min_targets < 0) L.wcap = 0;
     L.wmin = wave_min_targets > 0 ? wave_min_targets : 4 * L.nblocks * (L.threads / 64);
@@ -664,6 +687,8 @@ SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
     a.early_any = p.early_any ? 1 : 0;
     a.capB = L.capB; a.capC = L.capC; a.nblocks = L.nblocks;
     a.wcap = L.wcap; a.wslice = L.wslice; a.wmin = L.wmin;
+    a.halves = L.halves; a.half_lds = L.half_lds; a.capBh = L.capBh; a.capCh = L.capCh;
+    a.big_front = L.big_front; a.big_children = L.big_children; a.halves_min = L.halves_min;
     a.pool = w->pool; a.pool_cap = w->pool_cap; a.pool_top = w->pool_top; a.nb = w->nb;
     a.minopen = w->minopen; a.gcnt = w->gcnt; a.fo = w->fo; a.mark = w->mark; a.wt = w->wt;
     a.alist = w->alist; a.acnt = w->acnt; a.mcur = w->mcur; a.F = w->F; a.F_cap = w->F_cap;
@@ -701,6 +726,7 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
     res->stage_cap = p.stage_cap;
     res->block_threads = p.block_threads;
     res->wave_min_targets = p.wave_min_targets;
+    res->merge_halves = p.merge_halves;
     res->front_off.assign(nq + 1, 0);
     for (int q = 0; q < nq; ++q) res->front_off[q + 1] = res->front_off[q] + counts[q];
     const long long tot = res->front_off[nq];
@@ -727,6 +753,11 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
     res->stats.max_front = (int32_t)dev_out[kOutMaxFront];
     res->stats.blocks = L.nblocks;
     res->stats.wave_build = search_kernel_for(L, g->n) == reinterpret_cast<const void *>(k_search_wave);
+    res->stats.half_front_cap =
+        search_kernel_for(L, g->n) == reinterpret_cast<const void *>(k_search_halves) ? L.capBh : 0;
+    res->stats.reserved = 0;
+    res->stats.half_merges = dev_out[kOutHalfMerges];
+    res->stats.half_backouts = dev_out[kOutBackouts];
     res->stats.gpu_ms = ms;
     // per-query latency from the per-wave device clock (100 MHz)
     const int tw = std::min<int>(res->stats.waves, kTraceCap);
@@ -911,7 +942,8 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
         if (p.heur[q] == 1 && !(g->symmetric_alias ? g->sdrift : g->srdrift))
             return fail(MPAP_ERR_INVAL, "no surrogate drift on this graph (mpap_surrogate_score)");
     SearchShape L;
-    if ((r = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L))) return r;
+    if ((r = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L, p.merge_halves)))
+        return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     Workspace *w = nullptr;

@@ -136,7 +136,8 @@ extern "C" int mpap_search_noalloc(const mpap_graph *gc, const mpap_search_param
     if (r) return r;
     SearchShape L;
     if ((r = search_shape(x.stage_cap > 0 ? x.stage_cap : 0,
-                          x.block_threads ? x.block_threads : 1024, x.wave_min_targets, L)))
+                          x.block_threads ? x.block_threads : 1024, x.wave_min_targets, L,
+                          x.merge_halves)))
         return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 

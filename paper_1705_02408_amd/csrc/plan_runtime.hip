@@ -239,7 +239,7 @@ int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
     p->analytic = (flags & MPAP_PLAN_ANALYTIC) != 0;
     int r = search_prep(g, sp, nsp, p->prep);
     if (!r) r = search_shape(p->prep.stage_cap, p->prep.block_threads, p->prep.wave_min_targets,
-                             p->shape);
+                             p->shape, p->prep.merge_halves);
     auto bail = [&](int st) {
         mpap_plan_free(p);
         return st;

@@ -335,7 +335,7 @@ struct mpap_result {
     std::vector<float> qdelta;
     std::vector<int> qroot;
     int max_waves = 0, near_scan = 16, stage_cap = 0, block_threads = 1024;
-    int wave_min_targets = 0;
+    int wave_min_targets = 0, merge_halves = 0;
     // judge of a search on the learned drift: queries whose front it rejected
     // are answered by an analytic re-search (fallback), whose label ids are
     // reported shifted by id_offset
@@ -352,6 +352,8 @@ struct SearchPrep {
     std::vector<float> delta;  // per query lambda * radius
     int max_waves = 0, near_scan = 16, stage_cap = 0, block_threads = 1024;
     int wave_min_targets = 0;  // 0: default; < 0: never merge by single waves
+    int merge_halves = 0;      // 0: by halves on large roadmaps; > 0: always (the children
+                               // threshold of whole-workgroup targets); < 0: never
     std::vector<float> beta;
     std::vector<int> nobj, root, heur;
     std::vector<int> skip;  // 1: the query is not searched (its root is not seeded)
@@ -364,10 +366,17 @@ struct SearchShape {
     int wcap = 0, wslice = 0;  // single-wave merges: front capacity, LDS slice bytes
     int wmin = 0;              // and the least small-target count that uses them
     bool explicit_wmin = false;
+    // merges by halves (1024-thread workgroups, workgroup-only build): each
+    // half's LDS bytes, front stage and chunk; fronts above big_front labels
+    // or targets with more than big_children children go to the whole workgroup
+    int halves = 0, half_lds = 0, capBh = 0, capCh = 0, big_front = 0, big_children = 0;
+    int halves_min = 0;  // least targets of an iteration that merges by halves
+    bool halves_forced = false;  // the halves build whatever the roadmap's size
     size_t lds = 0;
 };
 int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, SearchPrep &p);
-int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchShape &L);
+int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchShape &L,
+                 int merge_halves = 0);
 // Uploads the per-query parameters into w (synchronous).
 int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s);
 // The search with capacity growth and retries, goal fronts and statistics,
@@ -386,10 +395,17 @@ int acquire_workspace(mpap_graph *g, const SearchShape &L, Workspace **out);
 GoalArgs goal_args(const mpap_graph *g, Workspace *w);
 // The search kernel build for a launch on g: with single-wave merges only
 // when some iteration can have wmin targets (or the caller asked for them).
+// The build with merges by halves runs on roadmaps of at least 8 halves_min
+// nodes (smaller ones rarely have iterations with halves_min targets), or
+// when the caller asked for it.
+inline bool halves_build(const SearchShape &L, int n) {
+    return L.halves && (L.halves_forced || n >= 8 * (long long)L.halves_min);
+}
 inline const void *search_kernel_for(const SearchShape &L, int n) {
     const bool wave = L.wcap > 0 && (L.explicit_wmin || n >= 4 * (long long)L.wmin);
     return wave ? reinterpret_cast<const void *>(k_search_wave)
-                : reinterpret_cast<const void *>(k_search);
+           : halves_build(L, n) ? reinterpret_cast<const void *>(k_search_halves)
+                                : reinterpret_cast<const void *>(k_search);
 }
 
 // Fills res's fronts, statistics, trace and latencies from host copies.

@@ -12,7 +12,7 @@ constexpr int kStatusArena = 3;       // arena or frontier capacity too small
 
 constexpr int kErrBucket = 1;   // a front outgrew the LDS staging capacity
 constexpr int kErrPool = 2;     // bucket pool exhausted
-constexpr int kErrTimeout = 4;  // grid barrier wait exceeded its bound
+constexpr int kErrTimeout = 4;  // a grid or half-workgroup barrier wait exceeded its bound
 constexpr int kErrTarget = 8;   // a queued merge target is not a node (internal error)
 
 // Merge targets of a workgroup-only launch are ordered by expected work (the
@@ -21,7 +21,10 @@ constexpr int kErrTarget = 8;   // a queued merge target is not a node (internal
 // classes are merged first, so the longest merges of an iteration start early.
 constexpr int kWeightClasses = 10;
 constexpr int kWeightClassBase = 128;
-constexpr int kListRegions = 1 + kWeightClasses;  // target list regions of n entries each
+// Target list regions of n entries each: all targets, one per weight class,
+// and (with merges by halves) two of targets the whole workgroup merges: the
+// heavy ones (first), then the rest.
+constexpr int kListRegions = 3 + kWeightClasses;
 
 // device output words
 constexpr int kOutWaves = 0;
@@ -34,7 +37,9 @@ constexpr int kOutRelax = 6;
 constexpr int kOutNeed = 7;  // group size that did not fit (arena / frontier)
 constexpr int kOutMaxFront = 8;
 constexpr int kOutClosed = 9;  // open goal plans given arena ids at an early stop
-constexpr int kOutWords = 10;
+constexpr int kOutHalfMerges = 10;  // merges done by half workgroups
+constexpr int kOutBackouts = 11;    // targets a half backed out of (merged again whole)
+constexpr int kOutWords = 12;
 
 // per-wave trace words (device clock ticks, 100 MHz wall clock)
 constexpr int kTraceWords = 10;
@@ -100,12 +105,25 @@ struct SearchArgs {
     int *alist;        // merge targets of the current wave, kListRegions regions of n:
                        // wave build: fronts of at most wcap labels in region 0 (merged
                        // by one wave), larger ones in region 1; workgroup-only build:
-                       // every target in region 0, then by weight class c in region 1+c
+                       // every target in region 0, then by weight class c in region 1+c,
+                       // with merges by halves the whole workgroup's in regions
+                       // 1+kWeightClasses (heavy) and 2+kWeightClasses
     int *acnt;         // [2 kListRegions] target count of region r at [2 r + wave parity]
     int *mcur;         // [2 kListRegions] next target to merge, same layout
     int wcap;          // largest front merged by a single wave (0: none)
     int wmin;          // single-wave merges in iterations with at least wmin small targets
     int wslice;        // LDS bytes of one wave's slice in single-wave merges
+    // merges by halves (workgroup-only build, 1024-thread workgroups): each
+    // half of a workgroup merges its own targets in its half of the LDS
+    // (half_lds bytes from the start of the dynamic LDS, a front stage of
+    // capBh labels and a chunk of capCh); targets with fronts above
+    // big_front labels or more than big_children children queued go to the
+    // whole workgroup first, those above capBh labels or 4 big_children
+    // children before the others
+    int halves;        // 1: merges by halves (the k_search_halves build)
+    int capBh, capCh, half_lds;
+    int big_front, big_children;
+    int halves_min;    // least merge targets of an iteration that merges by halves
     float4 *F;         // frontier labels of the current wave
     long long F_cap;
     int2 *arena;       // per expanded label {node, parent id}
@@ -150,6 +168,7 @@ __global__ void k_rescore(const int2 *arena, const int *optr, const int *ocol,
                           uint8_t *pass);
 __global__ void k_search_roots(SearchArgs a);
 __global__ void k_search(SearchArgs a);
+__global__ void k_search_halves(SearchArgs a);  // with merges by halves
 __global__ void k_search_wave(SearchArgs a);  // with single-wave merges
 __global__ void k_count_front(SearchArgs a);
 // After a search with early stops: the plans still open at the goal nodes of

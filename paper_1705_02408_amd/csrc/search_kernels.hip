@@ -69,7 +69,7 @@ __device__ __forceinline__ long long first_step(float c, float d) {
 // Nodes of the block's range are taken a tile (one per thread) at a time; the
 // nodes whose least open cost is within the threshold go to an LDS list and
 // the block's waves count their group labels in parallel, one node per wave.
-__device__ void phase_count(const SearchArgs &a, long long istep, int par, int lo, int hi,
+__device__ __forceinline__ void phase_count(const SearchArgs &a, long long istep, int par, int lo, int hi,
                             int *list, int *scan, long long *red_ll) {
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
@@ -132,7 +132,7 @@ __device__ void phase_count(const SearchArgs &a, long long istep, int par, int l
 // then handled by one wave: its group labels are copied to the frontier,
 // closed and given their arena ids, and its out-neighbours are queued.
 template <bool kSplit>
-__device__ void phase_select(const SearchArgs &a, long long istep, int wave, long long abase,
+__device__ __forceinline__ void phase_select(const SearchArgs &a, long long istep, int wave, long long abase,
                              long long myoff, int lo, int hi, int *list, int *list_off,
                              int *scan) {
     const int l = lane_id();
@@ -273,23 +273,154 @@ struct MergeLds {
     float *segd;    // [segcap] per 64-label segment: least d
     float *segm;    // [segcap] per 64-label segment: least m
     int segcap;
-    int capC;
+    int capB;       // LDS staging capacity of a front (labels)
+    int capC;       // candidate chunk capacity (labels)
 };
 
 
+// ------------------------------------------------------------ merge groups
+// A merge runs on a group of threads: the whole workgroup (workgroup
+// barriers), or one half of it, so that the two halves merge two targets at
+// once.  A half synchronises through LDS words of its own: an arrival count
+// and a generation (the last wave to arrive resets the count and advances the
+// generation; the others wait for the advance), and three count slots used in
+// rotation.  A half's merge reads global memory but writes it only in its
+// write-back, which no other thread of the half reads, so its barriers order
+// LDS only.
+template <bool kHalf>
+struct Grp {
+    int tid;   // thread index in the group
+    int nt;    // threads in the group
+    int w;     // wave index in the group
+    int nw;    // waves in the group
+    int *bar;  // kHalf: LDS words {arrivals, generation, three count slots}
+    int k;     // kHalf: gcount calls so far, modulo 3 (selects the slot)
+    int *err;  // kHalf: error word (a barrier wait beyond its bound sets kErrTimeout)
+};
+
+// polls of a half's barrier before it gives up (about 0.1 s; a wait is
+// normally one merge step)
+constexpr unsigned kHalfSpinLimit = 1u << 20;
+
+__device__ __forceinline__ Grp<false> whole_group() {
+    return Grp<false>{(int)threadIdx.x, (int)blockDim.x,
+                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)),
+                      (int)(blockDim.x >> 6), nullptr, 0, nullptr};
+}
+
+template <bool kHalf>
+__device__ __forceinline__ void gsync(Grp<kHalf> &gp) {
+    if constexpr (!kHalf) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        if (lane_id() == 0) {
+            int *cnt = gp.bar, *gen = gp.bar + 1;
+            // the generation is read before arriving: it cannot advance until
+            // this wave has arrived
+            const int my = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (__hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+                gp.nw - 1) {
+                __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(gen, my + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                unsigned polls = 0;
+                while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == my) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++polls > kHalfSpinLimit) {
+                        atomicOr(gp.err, kErrTimeout);
+                        break;
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+}
+
+// number of threads of the group with p set (every thread calls)
+template <bool kHalf>
+__device__ __forceinline__ int gcount(Grp<kHalf> &gp, bool p) {
+    if constexpr (!kHalf) {
+        return __syncthreads_count(p);
+    } else {
+        int *slot = gp.bar + 2;
+        const int cur = gp.k, nxt = gp.k == 2 ? 0 : gp.k + 1;
+        gp.k = nxt;
+        // the next call's slot was last read before the previous barrier
+        if (gp.tid == 0) slot[nxt] = 0;
+        const uint64_t m = ballot64(p);
+        if (lane_id() == 0 && m) atomicAdd(&slot[cur], (int)__popcll(m));
+        gsync(gp);
+        return slot[cur];
+    }
+}
+
+template <bool kHalf>
+__device__ __forceinline__ bool gor(Grp<kHalf> &gp, bool p) {
+    if constexpr (!kHalf) return __syncthreads_or(p) != 0;
+    else return gcount(gp, p) != 0;
+}
+
+// group-wide exclusive scan of one int per thread (scratch: one int per wave)
+template <bool kHalf>
+__device__ __forceinline__ int g_excl_scan(Grp<kHalf> &gp, int v, int *scratch, int *total) {
+    const int l = lane_id();
+    const int incl = wave_incl_scan_add(v);
+    gsync(gp);
+    if (l == 63) scratch[gp.w] = incl;
+    gsync(gp);
+    int before = 0, all = 0;
+    for (int i = 0; i < gp.nw; ++i) {
+        const int t = scratch[i];
+        if (i < gp.w) before += t;
+        all += t;
+    }
+    *total = all;
+    gsync(gp);
+    return before + incl - v;
+}
+
+template <bool kHalf>
+__device__ __forceinline__ long long g_min_ll(Grp<kHalf> &gp, long long v, long long *scratch) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (long long)__shfl_xor(v, o, 64));
+    gsync(gp);
+    if (lane_id() == 0) scratch[gp.w] = v;
+    gsync(gp);
+    long long r = scratch[0];
+    for (int i = 1; i < gp.nw; ++i) r = min(r, scratch[i]);
+    gsync(gp);
+    return r;
+}
+
+template <bool kHalf>
+__device__ __forceinline__ float g_min(Grp<kHalf> &gp, float v, float *scratch) {
+    v = wave_min(v);
+    gsync(gp);
+    if (lane_id() == 0) scratch[gp.w] = v;
+    gsync(gp);
+    float r = MPAP_INF;
+    for (int i = 0; i < gp.nw; ++i) r = fminf(r, scratch[i]);
+    gsync(gp);
+    return r;
+}
+
+
 // compact the alive entries of arr[0..n) to the front, stable.
-__device__ int compact_alive(float4 *arr, const uint8_t *dead, int n, int *scan) {
+template <bool kHalf>
+__device__ int compact_alive(Grp<kHalf> &gp, float4 *arr, const uint8_t *dead, int n, int *scan) {
     int out = 0;
-    for (int t0 = 0; t0 < n; t0 += blockDim.x) {
-        const int i = t0 + threadIdx.x;
+    for (int t0 = 0; t0 < n; t0 += gp.nt) {
+        const int i = t0 + gp.tid;
         const bool alive = i < n && !dead[i];
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (alive) v = arr[i];
         int tot;
-        const int ex = block_excl_scan(alive ? 1 : 0, scan, &tot);
+        const int ex = g_excl_scan(gp, alive ? 1 : 0, scan, &tot);
         if (alive) arr[out + ex] = v;
         out += tot;
-        __syncthreads();
+        gsync(gp);
     }
     return out;
 }
@@ -323,10 +454,11 @@ __device__ __forceinline__ int lex_rank(const float4 *arr, int n, const float4 &
 }
 
 // block-wide bitonic sort of v[0..n), n a power of two
-__device__ void bitonic_sort(float4 *v, int n) {
+template <bool kHalf>
+__device__ void bitonic_sort(Grp<kHalf> &gp, float4 *v, int n) {
     for (int k = 2; k <= n; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            for (int i = gp.tid; i < n; i += gp.nt) {
                 const int ixj = i ^ j;
                 if (ixj > i) {
                     const float4 p = v[i], q = v[ixj];
@@ -337,7 +469,7 @@ __device__ void bitonic_sort(float4 *v, int n) {
                     }
                 }
             }
-            __syncthreads();
+            gsync(gp);
         }
     }
 }
@@ -346,8 +478,10 @@ __device__ void bitonic_sort(float4 *v, int n) {
 // A segment whose least d exceeds q.d (or least m exceeds q.m) holds no label
 // that weakly dominates q, so dominance scans skip it.  Returns false (and
 // writes nothing) when the n labels need more than segcap segments.
-__device__ bool seg_summary(const float4 *arr, int n, float *sd, float *sm, int segcap) {
-    const int l = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+template <bool kHalf>
+__device__ bool seg_summary(Grp<kHalf> &gp, const float4 *arr, int n, float *sd, float *sm,
+                            int segcap) {
+    const int l = lane_id(), w = gp.w, nw = gp.nw;
     const int nseg = (n + 63) >> 6;
     if (nseg > segcap) return false;
     for (int sg = w; sg < nseg; sg += nw) {
@@ -365,7 +499,8 @@ __device__ bool seg_summary(const float4 *arr, int n, float *sd, float *sm, int 
             sm[sg] = m;
         }
     }
-    __syncthreads();    return true;
+    gsync(gp);
+    return true;
 }
 
 // does some label of the sorted arr[0..end) weakly dominate q (its cost is
@@ -387,8 +522,9 @@ __device__ __forceinline__ bool any_dominates(const float4 *arr, int end, const 
 
 // block-wide exclusive prefix minimum of one float per thread (scratch: one
 // float per wave); every thread calls
-__device__ __forceinline__ float block_excl_min(float v, float *scratch) {
-    const int l = lane_id(), w = threadIdx.x >> 6;
+template <bool kHalf>
+__device__ __forceinline__ float g_excl_min(Grp<kHalf> &gp, float v, float *scratch) {
+    const int l = lane_id(), w = gp.w;
     float incl = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -397,12 +533,12 @@ __device__ __forceinline__ float block_excl_min(float v, float *scratch) {
     }
     float ex = __shfl_up(incl, 1, 64);
     if (l == 0) ex = MPAP_INF;
-    __syncthreads();
+    gsync(gp);
     if (l == 63) scratch[w] = incl;
-    __syncthreads();
+    gsync(gp);
     float before = MPAP_INF;
     for (int i = 0; i < w; ++i) before = fminf(before, scratch[i]);
-    __syncthreads();
+    gsync(gp);
     return fminf(before, ex);
 }
 
@@ -449,14 +585,15 @@ __device__ __forceinline__ bool near_dead(const float4 *B, int nB, const float4 
 // kWide: the all-pairs survivor step keeps four reads in flight (more
 // registers; the wave-first build, whose single-wave merges share the
 // kernel, keeps one).
-template <bool kWide>
-__device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_scan, bool three,
-                            int &lo, int *err, bool prescanned) {
-    const int bd = blockDim.x;
+template <bool kWide, bool kHalf>
+__device__ __forceinline__ bool merge_chunk(MergeLds &s, Grp<kHalf> &gp, int &nB, int nC, int near_scan,
+                            bool three, int &lo, int *err, bool prescanned) {
+    const int bd = gp.nt;
+    const int capB = s.capB;
     if (!prescanned) {
         // 1. first test; 2. list the undecided candidates
         for (int t0 = 0; t0 < nC; t0 += bd) {
-            const int i = t0 + threadIdx.x;
+            const int i = t0 + gp.tid;
             bool und = false;
             if (i < nC) {
                 int stop;
@@ -469,19 +606,19 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             wave_append(und, &s.misc[6], slot);
             if (und) s.u_idx[slot] = i;
         }
-        __syncthreads();
+        gsync(gp);
     }
     if (three) {
         const int nU = s.misc[6];
         // 3. the rest of the prefix, gs threads per candidate, by segments
         if (nU > 0) {
-            const bool use_seg = seg_summary(s.B, nB, s.segd, s.segm, s.segcap);
+            const bool use_seg = seg_summary(gp, s.B, nB, s.segd, s.segm, s.segcap);
             int gs = 1;
             while (gs < 64 && gs * 2 * nU <= bd) gs <<= 1;
             const int per_round = bd / gs;
             for (int base = 0; base < nU; base += per_round) {
-                const int u = base + (int)threadIdx.x / gs;
-                const int sub = (int)threadIdx.x % gs;
+                const int u = base + gp.tid / gs;
+                const int sub = gp.tid % gs;
                 if (u < nU) {
                     const int i = s.u_idx[u];
                     if (any_dominates(s.B, s.u_end[i], s.C[i], s.segd, s.segm, use_seg, gs, sub,
@@ -489,7 +626,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
                         s.cdead[i] = 1;
                 }
             }
-            __syncthreads();
+            gsync(gp);
         }
     }
     // 4. survivors of the bucket test, gathered (any order) into tmp (the
@@ -498,15 +635,15 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     float4 *tmp = reinterpret_cast<float4 *>(s.u_idx);
     const int pair_max = min(min(kPairMax, s.capC / 2), bd);  // one thread or more each
     for (int t0 = 0; t0 < nC; t0 += bd) {
-        const int i = t0 + threadIdx.x;
+        const int i = t0 + gp.tid;
         const bool alive = i < nC && !s.cdead[i];
         int slot;
         wave_append(alive, &s.misc[7], slot);
         if (alive && slot < pair_max) tmp[slot] = s.C[i];
     }
-    __syncthreads();
+    gsync(gp);
     const int nS = s.misc[7];
-    if (nS == 0) return;
+    if (nS == 0) return true;
     int nS2;
     if (nS <= pair_max) {
         // 4-5 for up to pair_max survivors, all pairs at once: g threads per
@@ -515,7 +652,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         // living ones is its place in the sorted run.
         int g = 1;
         while (g < 64 && g * 2 * nS <= bd) g <<= 1;
-        const int i = (int)threadIdx.x / g, sub = (int)threadIdx.x % g;
+        const int i = gp.tid / g, sub = gp.tid % g;
         const bool mine = i < nS;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         bool dead = false;
@@ -526,8 +663,9 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             if constexpr (kWide)
             for (; j + 3 * g < nS; j += 4 * g) {
                 const float4 o0 = tmp[j], o1 = tmp[j + g], o2 = tmp[j + 2 * g], o3 = tmp[j + 3 * g];
-                dead |= (lex_lt(o0, v) && dm_le(o0, v)) | (lex_lt(o1, v) && dm_le(o1, v)) |
-                        (lex_lt(o2, v) && dm_le(o2, v)) | (lex_lt(o3, v) && dm_le(o3, v));
+                // (bitwise on purpose: the four tests without branches)
+                dead |= (int)(lex_lt(o0, v) && dm_le(o0, v)) | (int)(lex_lt(o1, v) && dm_le(o1, v)) |
+                        (int)(lex_lt(o2, v) && dm_le(o2, v)) | (int)(lex_lt(o3, v) && dm_le(o3, v));
             }
             for (; j < nS; j += g) {
                 const float4 o = tmp[j];
@@ -536,7 +674,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         }
         for (int o = 1; o < g; o <<= 1) dead = __shfl_xor((int)dead, o, 64) != 0 || dead;
         if (mine && sub == 0) s.cdead[i] = dead ? 1 : 0;
-        __syncthreads();
+        gsync(gp);
         int pos = 0;
         if (mine && !dead) {
             int j = sub;
@@ -553,37 +691,37 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         for (int o = 1; o < g; o <<= 1) pos += __shfl_xor(pos, o, 64);
         const bool lead = mine && sub == 0 && !dead;
         if (lead) s.C[pos] = v;  // tmp is the input, C the sorted output
-        nS2 = __syncthreads_count(lead);
+        nS2 = gcount(gp, lead);
     } else {
         // many survivors: compact them in place, sort, sweep
-        const int nSc = compact_alive(s.C, s.cdead, nC, s.scan);
+        const int nSc = compact_alive(gp, s.C, s.cdead, nC, s.scan);
         (void)nSc;
         int P = 1;
         while (P < nS) P <<= 1;
-        for (int i = nS + threadIdx.x; i < P; i += bd)
+        for (int i = nS + gp.tid; i < P; i += bd)
             s.C[i] = make_float4(MPAP_INF, MPAP_INF, MPAP_INF, __uint_as_float(0xffffffffu));
-        __syncthreads();
-        bitonic_sort(s.C, P);
+        gsync(gp);
+        bitonic_sort(gp, s.C, P);
         // 5. candidates among themselves: an earlier (lexicographically
         // smaller) one may dominate
         if (!three) {
         float carry = MPAP_INF;
         for (int t0 = 0; t0 < nS; t0 += bd) {
-            const int i = t0 + threadIdx.x;
+            const int i = t0 + gp.tid;
             const float d = i < nS ? s.C[i].y : MPAP_INF;
-            const float ex = fminf(carry, block_excl_min(d, reinterpret_cast<float *>(s.scan)));
+            const float ex = fminf(carry, g_excl_min(gp, d, reinterpret_cast<float *>(s.scan)));
             if (i < nS) s.cdead[i] = ex <= d ? 1 : 0;
-            carry = fminf(carry, block_min(d, reinterpret_cast<float *>(s.scan)));
+            carry = fminf(carry, g_min(gp, d, reinterpret_cast<float *>(s.scan)));
         }
-        __syncthreads();
+        gsync(gp);
         } else {
-            const bool seg = seg_summary(s.C, nS, s.segd, s.segm, s.segcap);
-            for (int i = threadIdx.x; i < nS; i += bd)
+            const bool seg = seg_summary(gp, s.C, nS, s.segd, s.segm, s.segcap);
+            for (int i = gp.tid; i < nS; i += bd)
                 s.cdead[i] =
                     any_dominates(s.C, i, s.C[i], s.segd, s.segm, seg, 1, 0, nullptr) ? 1 : 0;
-            __syncthreads();
+            gsync(gp);
         }
-        nS2 = compact_alive(s.C, s.cdead, nS, s.scan);
+        nS2 = compact_alive(gp, s.C, s.cdead, nS, s.scan);
     }
     // 6. bucket labels a surviving candidate dominates leave (only labels at
     // least as costly as the cheapest survivor can be dominated)
@@ -591,7 +729,7 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
     long long first_dead = nB;
     const int js = lower_c(s.B, nB, s.C[0].x);
     if (!three) {
-        for (int j = js + threadIdx.x; j < nB; j += bd) {
+        for (int j = js + gp.tid; j < nB; j += bd) {
             const float4 b = s.B[j];
             const int kk = upper_c(s.C, nS2, b.x);
             const bool dead = kk > 0 && s.C[kk - 1].y <= b.y;
@@ -600,8 +738,8 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
             if (dead) first_dead = min(first_dead, (long long)j);
         }
     } else {
-        const bool seg = nS2 > 64 && seg_summary(s.C, nS2, s.segd, s.segm, s.segcap);
-        for (int j = js + threadIdx.x; j < nB; j += bd) {
+        const bool seg = nS2 > 64 && seg_summary(gp, s.C, nS2, s.segd, s.segm, s.segcap);
+        for (int j = js + gp.tid; j < nB; j += bd) {
             const float4 b = s.B[j];
             const int kk = upper_c(s.C, nS2, b.x);
             const bool dead = any_dominates(s.C, kk, b, s.segd, s.segm, seg, 1, 0, nullptr);
@@ -611,30 +749,39 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         }
     }
     int nBs = nB;
-    if (__syncthreads_or(any_dead)) {
+    if (gor(gp, any_dead)) {
         // labels below the first removed one keep their places
-        const int fd = (int)block_min_ll(first_dead, reinterpret_cast<long long *>(s.scan));
+        const int fd = (int)g_min_ll(gp, first_dead, reinterpret_cast<long long *>(s.scan));
         lo = min(lo, fd);
-        nBs = fd + compact_alive(s.B + fd, s.bdead + fd, nB - fd, s.scan);
+        nBs = fd + compact_alive(gp, s.B + fd, s.bdead + fd, nB - fd, s.scan);
     }
     // the first survivor's place: labels below it keep their places
     const int r0 = lex_rank(s.B, nBs, s.C[0]);
     lo = min(lo, r0);
     const int total = nBs + nS2;
+    if constexpr (kHalf) {
+        // a half has no spill space: the merge backs out (nothing was written
+        // to global memory) and the whole workgroup merges the target again
+        if (total > capB) {
+            nB = nBs;
+            gsync(gp);
+            return false;
+        }
+    }
     if (total > (s.spilled ? s.capG : capB) && (s.spilled || total > s.capG)) {
-        if (threadIdx.x == 0) atomicOr(err, kErrBucket);
+        if (gp.tid == 0) atomicOr(err, kErrBucket);
         nB = nBs;
-        __syncthreads();
-        return;
+        gsync(gp);
+        return true;
     }
     if (s.spilled || total > capB) {
         // 7a. merge out of place into the (other) spill buffer
         float4 *outb = (s.spilled && s.B == s.Bg0) ? s.Bg1 : s.Bg0;
-        for (int k = threadIdx.x; k < nBs; k += bd) {
+        for (int k = gp.tid; k < nBs; k += bd) {
             const float4 v = s.B[k];
             outb[k + lex_rank(s.C, nS2, v)] = v;
         }
-        for (int i = threadIdx.x; i < nS2; i += bd) {
+        for (int i = gp.tid; i < nS2; i += bd) {
             const float4 v = s.C[i];
             outb[i + lex_rank(s.B, nBs, v)] = v;
         }
@@ -642,31 +789,32 @@ __device__ void merge_chunk(MergeLds &s, int &nB, int nC, int capB, int near_sca
         s.bdead = s.bdeadg;
         s.spilled = true;
         nB = total;
-        __syncthreads();
-        return;
+        gsync(gp);
+        return true;
     }
     // 7b. merge the two sorted runs in place in LDS.  Positions by rank: the
     // survivors' places are found first (B still intact); B's labels only
     // move up, so B is moved chunk by chunk from the top (each chunk read,
     // then written, never over a label still to be read); the survivors go
     // to their places last.
-    for (int i = threadIdx.x; i < nS2; i += bd) s.u_idx[i] = i + lex_rank(s.B, nBs, s.C[i]);
-    __syncthreads();
+    for (int i = gp.tid; i < nS2; i += bd) s.u_idx[i] = i + lex_rank(s.B, nBs, s.C[i]);
+    gsync(gp);
     for (int top = nBs; top > r0; top -= bd) {
-        const int k = top - bd + (int)threadIdx.x;
+        const int k = top - bd + gp.tid;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         int pos = -1;
         if (k >= r0) {
             v = s.B[k];
             pos = k + lex_rank(s.C, nS2, v);
         }
-        __syncthreads();
+        gsync(gp);
         if (pos >= 0) s.B[pos] = v;
-        __syncthreads();
+        gsync(gp);
     }
-    for (int i = threadIdx.x; i < nS2; i += bd) s.B[s.u_idx[i]] = s.C[i];
+    for (int i = gp.tid; i < nS2; i += bd) s.B[s.u_idx[i]] = s.C[i];
     nB = total;
-    __syncthreads();
+    gsync(gp);
+    return true;
 }
 
 // ------------------------------------------------ single-wave merges (small fronts)
@@ -962,63 +1110,73 @@ __device__ bool wave_merge_node(const SearchArgs &a, int x, int wave, const Wave
     return true;
 }
 
-// Stage P(x) (pool region nbv) for merging: LDS if it fits, else spill space.
-__device__ bool stage_front(const SearchArgs &a, MergeLds &s, const int4 &nbv) {
-    s.spilled = nbv.z > a.capB;
+// Stage P(x) (pool region nbv) for merging: LDS if it fits, else spill space
+// (whole workgroup only: false for a half, which then leaves the target to
+// the whole workgroup, and false with an error when the spill space is too
+// small).
+template <bool kHalf>
+__device__ bool stage_front(const SearchArgs &a, MergeLds &s, Grp<kHalf> &gp, const int4 &nbv) {
+    s.spilled = nbv.z > s.capB;
+    if constexpr (kHalf) {
+        if (s.spilled) return false;
+    }
     s.B = s.spilled ? s.Bg0 : s.Bl;
     s.bdead = s.spilled ? s.bdeadg : s.bdeadl;
-    if (nbv.z > (s.spilled ? s.capG : a.capB)) {
-        if (threadIdx.x == 0) atomicOr(a.err, kErrBucket);
+    if (nbv.z > (s.spilled ? s.capG : s.capB)) {
+        if (gp.tid == 0) atomicOr(a.err, kErrBucket);
         return false;
     }
-    for (int i = threadIdx.x; i < nbv.z; i += blockDim.x)
-        s.B[i] = a.pool[(size_t)(unsigned)nbv.x + i];
-    __syncthreads();
+    for (int i = gp.tid; i < nbv.z; i += gp.nt) s.B[i] = a.pool[(size_t)(unsigned)nbv.x + i];
+    gsync(gp);
     return true;
 }
 
-template <bool kWide>
-__device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
+// Merges the children of x's in-neighbours' group labels into P(x).  Returns
+// false when a half backs out (the front outgrows the half's LDS stage;
+// nothing was written), true otherwise.
+template <bool kWide, bool kHalf>
+__device__ __forceinline__ bool merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
+                                           Grp<kHalf> &gp,
                            long long &st_cand) {
     const int4 nbx = a.nb[x];
     int nB = nbx.z;
     int lo = nB;  // first index the merges change
-    if (!stage_front(a, s, nbx)) return;
+    if (!stage_front(a, s, gp, nbx)) return !kHalf;
     const bool rst = (a.nflag[x] & 1u) != 0u;
     const int q = (a.nq > 1) ? query_of(a, x) : 0;
     const float beta = a.qbeta[q];
     const bool three = a.qnobj[q] >= 3;
     const float *edrift = a.qheur[q] ? a.sdrift : a.rdrift;
     const int e0 = a.rptr[x], e1 = a.rptr[x + 1];
-    bool changed = false;
+    bool changed = false, fits = true;
     // Children are made in rounds of up to one per thread and given the first
     // bucket test at once; those it does not kill gather in C (any order)
     // across rounds and in-edge tiles until C holds kChunkFill of them, then
     // the chunk is merged.  Testing against the front as it was before the
     // last chunk went in is sound: a label removed since is dominated by one
     // that stayed, which then dominates the child too.
-    if (threadIdx.x == 0) {
+    if (gp.tid == 0) {
         s.misc[4] = 0;  // children within the bound
         s.misc[5] = 0;  // candidates kept
         s.misc[6] = 0;  // undecided after the first test
         s.misc[7] = 0;  // survivors of the bucket test
     }
-    __syncthreads();
+    gsync(gp);
     int nC = 0;  // kept so far (from the barrier counts: the same in every thread)
     auto flush = [&]() {
-        merge_chunk<kWide>(s, nB, nC, a.capB, a.near_scan, three, lo, a.err, true);
+        fits = merge_chunk<kWide>(s, gp, nB, nC, a.near_scan, three, lo, a.err, true);
         changed = true;
         nC = 0;
-        if (threadIdx.x == 0) {
+        if (gp.tid == 0) {
             s.misc[5] = 0;
             s.misc[6] = 0;
             s.misc[7] = 0;
         }
-        __syncthreads();
+        gsync(gp);
     };
-    for (int t0 = e0; t0 < e1; t0 += blockDim.x) {
+    for (int t0 = e0; t0 < e1; t0 += gp.nt) {
         // in-edge tile: frontier label counts of each in-neighbour
-        const int e = t0 + threadIdx.x;
+        const int e = t0 + gp.tid;
         int cnt = 0, off = 0;
         float ce = 0.f, de = 0.f;
         if (e < e1) {
@@ -1032,22 +1190,23 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
             }
         }
         int tot;
-        const int ex = block_excl_scan(cnt, s.scan, &tot);
-        s.e_off[threadIdx.x] = off;
-        s.e_pre[threadIdx.x] = ex + cnt;
-        s.e_c[threadIdx.x] = ce;
-        s.e_d[threadIdx.x] = de;
-        __syncthreads();
-        const int ntile = min((int)blockDim.x, e1 - t0);
+        const int ex = g_excl_scan(gp, cnt, s.scan, &tot);
+        s.e_off[gp.tid] = off;
+        s.e_pre[gp.tid] = ex + cnt;
+        s.e_c[gp.tid] = ce;
+        s.e_d[gp.tid] = de;
+        gsync(gp);
+        const int ntile = min(gp.nt, e1 - t0);
         for (int j0 = 0; j0 < tot;) {
             if (nC >= kChunkFill) {
                 flush();
+                if (!fits) return false;
                 continue;
             }
             // children j0 .. j0+cnt-1 of this tile (C has room for all)
-            const int cnt = min(min((int)blockDim.x, a.capC - nC), tot - j0);
+            const int cnt = min(min(gp.nt, s.capC - nC), tot - j0);
             {
-                const int j = j0 + threadIdx.x;
+                const int j = j0 + gp.tid;
                 bool ok = false, keep = false;
                 int stop = 0;
                 float4 ch = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1082,19 +1241,22 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                 if (stop > 0) s.u_idx[us] = slot;
                 const uint64_t okm = ballot64(ok);
                 if (lane_id() == 0 && okm) atomicAdd(&s.misc[4], (int)__popcll(okm));
-                nC += __syncthreads_count(keep);
+                nC += gcount(gp, keep);
             }
             j0 += cnt;
         }
-        __syncthreads();
+        gsync(gp);
     }
-    if (nC > 0) flush();
+    if (nC > 0) {
+        flush();
+        if (!fits) return false;
+    }
     st_cand += s.misc[4];  // every append precedes the last barrier
-    if (!changed) return;
+    if (!changed) return true;
     // write the merged front back (fresh region if it outgrew the old one)
     int off = nbx.x, cap = nbx.y;
     if (nB > cap) {
-        if (threadIdx.x == 0) {
+        if (gp.tid == 0) {
             int nc = 16;
             while (nc < nB) nc <<= 1;
             const unsigned o = atomicAdd(a.pool_top, (unsigned)nc);
@@ -1106,16 +1268,16 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                 s.misc[1] = nc;
             }
         }
-        __syncthreads();
+        gsync(gp);
         off = s.misc[0];
         cap = s.misc[1];
-        __syncthreads();
-        if (off < 0) return;
+        gsync(gp);
+        if (off < 0) return true;
         lo = 0;  // a fresh region gets the whole front
     }
     float mn = MPAP_INF;
     int nopen = 0, first = nB;
-    for (int i = threadIdx.x; i < nB; i += blockDim.x) {
+    for (int i = gp.tid; i < nB; i += gp.nt) {
         const float4 L = s.B[i];
         if (i >= lo) a.pool[(size_t)(unsigned)off + i] = L;
         if (lab_open(L)) {
@@ -1128,14 +1290,14 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
     mn = wave_min(mn);
     nopen = wave_sum(nopen);
     first = -wave_max_i(-first);
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int w = gp.w, nw = gp.nw;
     if (lane_id() == 0) {
         s.e_c[w] = mn;
         s.e_off[w] = nopen;
         s.e_pre[w] = first;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    gsync(gp);
+    if (gp.tid == 0) {
         for (int i = 1; i < nw; ++i) {
             mn = fminf(mn, s.e_c[i]);
             nopen += s.e_off[i];
@@ -1146,7 +1308,8 @@ __device__ void merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
         reinterpret_cast<int *>(&a.fo[x])[3] = first;
         a.minopen[x] = mn;
     }
-    __syncthreads();
+    gsync(gp);
+    return true;
 }
 
 }  // namespace
@@ -1194,53 +1357,70 @@ __global__ void __launch_bounds__(256) k_search_roots(SearchArgs a) {
     a.qlast[q] = 0;
 }
 
-__device__ void carve_lds(unsigned char *lds, const SearchArgs &a, MergeLds &s) {
-    unsigned char *p = lds;
+// LDS of a merge group from `base`: a front stage of capB labels, a chunk of
+// capC candidates, per-thread in-edge tiles of nt entries; spill space (the
+// block's, in global memory) for the whole workgroup only.
+__device__ __forceinline__ void carve_group(unsigned char *base, const SearchArgs &a, MergeLds &s, int capB,
+                            int capC, int nt, bool spill) {
+    unsigned char *p = base;
     s.Bl = reinterpret_cast<float4 *>(p);
-    p += sizeof(float4) * a.capB;
+    p += sizeof(float4) * capB;
     s.C = reinterpret_cast<float4 *>(p);
-    p += sizeof(float4) * a.capC;
+    p += sizeof(float4) * capC;
     s.e_off = reinterpret_cast<int *>(p);
-    p += sizeof(int) * blockDim.x;
+    p += sizeof(int) * nt;
     s.e_pre = reinterpret_cast<int *>(p);
-    p += sizeof(int) * blockDim.x;
+    p += sizeof(int) * nt;
     s.e_c = reinterpret_cast<float *>(p);
-    p += sizeof(float) * blockDim.x;
+    p += sizeof(float) * nt;
     s.e_d = reinterpret_cast<float *>(p);
-    p += sizeof(float) * blockDim.x;
+    p += sizeof(float) * nt;
     s.u_idx = reinterpret_cast<int *>(p);
-    p += sizeof(int) * a.capC;
+    p += sizeof(int) * capC;
     s.u_end = reinterpret_cast<int *>(p);
-    p += sizeof(int) * a.capC;
+    p += sizeof(int) * capC;
     s.scan = reinterpret_cast<int *>(p);
     p += sizeof(long long) * 16;
     s.misc = reinterpret_cast<int *>(p);
     p += sizeof(int) * 8;
-    s.segcap = max(a.capB, a.capC) / 64 + 2;
-    s.capC = a.capC;
+    s.segcap = max(capB, capC) / 64 + 2;
+    s.capB = capB;
+    s.capC = capC;
     s.segd = reinterpret_cast<float *>(p);
     p += sizeof(float) * s.segcap;
     s.segm = reinterpret_cast<float *>(p);
     p += sizeof(float) * s.segcap;
     s.bdeadl = p;
-    p += a.capB;
+    p += capB;
     s.cdead = p;
-    s.capG = a.capG;
-    s.Bg0 = a.spill + (size_t)blockIdx.x * 2 * a.capG;
-    s.Bg1 = s.Bg0 + a.capG;
-    s.bdeadg = a.spill_flags + (size_t)blockIdx.x * a.capG;
+    s.capG = spill ? a.capG : 0;
+    s.Bg0 = spill ? a.spill + (size_t)blockIdx.x * 2 * a.capG : nullptr;
+    s.Bg1 = spill ? s.Bg0 + a.capG : nullptr;
+    s.bdeadg = spill ? a.spill_flags + (size_t)blockIdx.x * a.capG : nullptr;
     s.B = s.Bl;
     s.bdead = s.bdeadl;
     s.spilled = false;
 }
 
-template <bool kWaveMerges>
+__device__ __forceinline__ void carve_lds(unsigned char *lds, const SearchArgs &a, MergeLds &s) {
+    carve_group(lds, a, s, a.capB, a.capC, (int)blockDim.x, true);
+}
+
+// kHalves (workgroup-only build): iterations with at least a.halves_min
+// targets merge by halves
+template <bool kWaveMerges, bool kHalves>
 __device__ __forceinline__ void search_body(SearchArgs a) {
+    static_assert(!(kWaveMerges && kHalves), "merges by halves are a workgroup-only build");
     extern __shared__ __align__(16) unsigned char lds[];
-    MergeLds s;
-    carve_lds(lds, a, s);
+    // (the merge groups' LDS views are carved where they are used, so that
+    // their pointers do not stay live across the loop)
 
     __shared__ long long red_ll[16];
+    // merges by halves: each half's barrier words, and the control words
+    // {stop, backed-out target of half 0 and 1, carried claim of half 0 and 1,
+    // the next whole-workgroup command}
+    __shared__ int hbar[2][8];
+    __shared__ int hctl[8];
 
     const int G = (int)gridDim.x;
     const int b = (int)blockIdx.x;
@@ -1254,6 +1434,10 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
     int it = 0;            // loop trips (parity of the partial sums)
     long long st_merges = 0, st_cand = 0;  // workgroup merges (thread 0 counts)
     long long wv_merges = 0, wv_cand = 0;  // single-wave merges (lane 0 counts)
+    // merges by halves: per half {merges, candidates, back-outs} (kept in
+    // LDS by each half's first thread, so that they hold no registers)
+    __shared__ unsigned long long hstat[2][3];
+    if (threadIdx.x < 6) hstat[threadIdx.x / 3][threadIdx.x % 3] = 0;
     int status = kStatusOk;
 
     const bool tr0 = (b == 0 && threadIdx.x == 0);
@@ -1284,7 +1468,11 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
             }
             grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         }
-        phase_count(a, i_step, par, lo, hi, s.u_idx, s.scan, red_ll);
+        {
+            MergeLds s;
+            carve_lds(lds, a, s);
+            phase_count(a, i_step, par, lo, hi, s.u_idx, s.scan, red_ll);
+        }
         if (tr0 && tr) tr[kTrCountDone] = (long long)wall_clock64();
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) tr[kTrCounted] = (long long)wall_clock64();
@@ -1331,8 +1519,12 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
             if (b == 0 && threadIdx.x == 0) a.out[kOutNeed] = total;
             break;
         }
-        phase_select<kWaveMerges>(a, i_step, wave, abase, before, lo, hi, s.u_idx, s.u_end,
-                                  s.scan);
+        {
+            MergeLds s;
+            carve_lds(lds, a, s);
+            phase_select<kWaveMerges>(a, i_step, wave, abase, before, lo, hi, s.u_idx, s.u_end,
+                                      s.scan);
+        }
         if (tr0 && tr) tr[kTrSelectDone] = (long long)wall_clock64();
         grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         if (tr0 && tr) {
@@ -1370,6 +1562,8 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
             __syncthreads();  // the slices are the workgroup's LDS again
             grid_barrier(a.bar, G, epoch, a.err, kErrTimeout, kSpinLimit);
         }
+        // merges by halves in this iteration: enough targets for two per workgroup
+        const bool halves = kHalves && na >= a.halves_min;
         if constexpr (!kWaveMerges) {
             // weight classes: every target once, by the children queued to it
             // (final after the select barrier; cleared here for the next
@@ -1382,7 +1576,16 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                 if (k < na) {
                     x = a.alist[k];
                     if ((unsigned)x < (unsigned)a.n) {
-                        c = weight_class(a.wt[x]);
+                        const int wx = a.wt[x];
+                        c = weight_class(wx);
+                        // with merges by halves: large fronts and very many
+                        // children go to the whole workgroup's regions, the
+                        // heaviest to the first
+                        if (halves) {
+                            const int fz = a.nb[x].z;
+                            if (wx > 4 * a.big_children || fz > a.capBh) c = kWeightClasses;
+                            else if (wx > a.big_children || fz > a.big_front) c = kWeightClasses + 1;
+                        }
                         a.wt[x] = 0;
                     } else {
                         atomicOr(a.err, kErrTarget);
@@ -1405,16 +1608,19 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
         // one workgroup per target, taken dynamically (merges differ widely in
         // cost); the next one is claimed while the current one merges.  Wave
         // build: the large fronts (and the small ones when no wave took them);
-        // workgroup-only build: the heaviest weight class first
+        // workgroup-only build: the heaviest weight class first (with merges
+        // by halves: the whole workgroup's region first, then the classes by
+        // halves)
         int nbig = 0, nsmall = na;
         if constexpr (kWaveMerges) {
             nbig = __hip_atomic_load(&a.acnt[2 + wp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (by_wave) nsmall = 0;
         }
         int *const cursor = &a.mcur[kWaveMerges ? 2 + wp : wp];
-        // thread 0's walk over the class regions (claims only grow)
+        // thread 0's walk over the class regions (claims only grow); with
+        // merges by halves each half's first thread walks on its own
         int cls = kWeightClasses - 1, cbase = 0, ccnt = 0;
-        if (!kWaveMerges && threadIdx.x == 0)
+        if (!kWaveMerges && (threadIdx.x & (halves ? 511 : 1023)) == 0)
             ccnt = __hip_atomic_load(&a.acnt[2 * (1 + cls) + wp], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
         // list index of the k-th claim, -1 when none is left
@@ -1432,22 +1638,137 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                 return k < cbase + ccnt ? (1 + cls) * a.n + (k - cbase) : -1;
             }
         };
+        // Whole-workgroup merges come from one loop (one call site per
+        // build): thread 0 claims and hands out the next target, or -2 (run
+        // the merges by halves) or -1 (done).  With merges by halves: first
+        // the whole workgroup's region, then the halves; a half that backs
+        // out of a target (its front outgrew the half's stage) stops both
+        // halves after their current merges, the whole workgroup merges the
+        // target, and the halves go on.
+        // the whole workgroup's regions rb (heavy) and rb + 1 as one list
+        const int rb = 1 + kWeightClasses;
+        const int nw0 = halves ? __hip_atomic_load(&a.acnt[2 * rb + wp], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : 0;
+        const int nwhole = halves ? nw0 + __hip_atomic_load(&a.acnt[2 * (rb + 1) + wp],
+                                                            __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0;
+        int *const wcur = &a.mcur[2 * rb + wp];
+        // thread 0: 0 whole-workgroup region, 1 after the halves, 2 no halves
+        int phase = halves ? 0 : 2;
         int next = -1;
-        if (threadIdx.x == 0) next = locate(atomicAdd(cursor, 1));
+        if (threadIdx.x == 0) next = phase == 0 ? atomicAdd(wcur, 1) : locate(atomicAdd(cursor, 1));
+        // (the half and the wave index are uniform in a wave: read from the
+        // first lane, so that the half's LDS views stay in scalar registers)
+        const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 9);
+        if (threadIdx.x < 8) hctl[threadIdx.x] = threadIdx.x == 0 ? 0 : -1;
+        __syncthreads();
         for (;;) {
-            if (threadIdx.x == 0) s.misc[2] = next;
+            if (threadIdx.x == 0) {
+                int cmd = -1;
+                for (;;) {
+                    int x = -1;
+                    if (phase == 0) {
+                        if (next >= nwhole) {
+                            phase = 1;
+                            cmd = -2;
+                            break;
+                        }
+                        x = a.alist[(size_t)(next < nw0 ? rb : rb + 1) * a.n +
+                                    (next < nw0 ? next : next - nw0)];
+                        next = atomicAdd(wcur, 1);
+                    } else if (phase == 1) {
+                        if (hctl[1] >= 0) {
+                            x = hctl[1];
+                            hctl[1] = -1;
+                        } else if (hctl[2] >= 0) {
+                            x = hctl[2];
+                            hctl[2] = -1;
+                        } else if (hctl[0] != 0) {
+                            hctl[0] = 0;
+                            cmd = -2;
+                            break;
+                        } else {
+                            break;  // done
+                        }
+                    } else {
+                        const int idx = next;
+                        if (kWaveMerges ? idx >= nsmall + nbig : idx < 0) break;
+                        next = locate(atomicAdd(cursor, 1));
+                        x = kWaveMerges ? (idx < nsmall ? a.alist[idx] : a.alist[a.n + (idx - nsmall)])
+                                        : a.alist[idx];
+                    }
+                    if ((unsigned)x < (unsigned)a.n) {
+                        cmd = x;
+                        break;
+                    }
+                    atomicOr(a.err, kErrTarget);
+                }
+                hctl[5] = cmd;
+            }
             __syncthreads();
-            const int idx = s.misc[2];
+            const int cmd = hctl[5];
             __syncthreads();
-            if (kWaveMerges ? idx >= nsmall + nbig : idx < 0) break;
-            if (threadIdx.x == 0) next = locate(atomicAdd(cursor, 1));
-            const int x = kWaveMerges ? (idx < nsmall ? a.alist[idx] : a.alist[a.n + (idx - nsmall)])
-                                      : a.alist[idx];
-            if ((unsigned)x < (unsigned)a.n) {
-                merge_node<!kWaveMerges>(a, x, wave, s, st_cand);
+            if (cmd == -1) break;
+            if (cmd >= 0) {
+                MergeLds s;
+                carve_lds(lds, a, s);
+                Grp<false> gw = whole_group();
+                // (the halves build keeps the single-read survivor step: the
+                // four-read one needs more registers than it leaves)
+                merge_node<!kWaveMerges && !kHalves>(a, cmd, wave, s, gw, st_cand);
                 ++st_merges;
-            } else if (threadIdx.x == 0) {
-                atomicOr(a.err, kErrTarget);
+                continue;
+            }
+            // cmd == -2: the merges by halves, heaviest class first
+            if constexpr (kHalves) {
+                Grp<true> gh{(int)threadIdx.x & 511, 512,
+                             __builtin_amdgcn_readfirstlane(((int)threadIdx.x >> 6) & 7), 8, hbar[h],
+                             0, a.err};
+                MergeLds sh;
+                carve_group(lds + (size_t)h * a.half_lds, a, sh, a.capBh, a.capCh, 512, false);
+                if (threadIdx.x < 16) hbar[threadIdx.x >> 3][threadIdx.x & 7] = 0;
+                __syncthreads();
+                int hnext = -1;
+                if (gh.tid == 0) {
+                    hnext = hctl[3 + h] >= 0 ? hctl[3 + h] : locate(atomicAdd(cursor, 1));
+                    hctl[3 + h] = -1;
+                }
+                for (;;) {
+                    if (gh.tid == 0) {
+                        if (__hip_atomic_load(&hctl[0], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP) != 0) {
+                            hctl[3 + h] = hnext;  // claimed, not merged: carried over
+                            hnext = -2;
+                        }
+                        if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                            kErrTimeout)
+                            hnext = -1;  // a barrier wait gave up: the search ends with an error
+                        sh.misc[2] = hnext;
+                    }
+                    gsync(gh);
+                    const int idx = sh.misc[2];
+                    gsync(gh);
+                    if (idx < 0) break;
+                    if (gh.tid == 0) hnext = locate(atomicAdd(cursor, 1));
+                    const int x = a.alist[idx];
+                    long long cand = 0;
+                    if ((unsigned)x >= (unsigned)a.n) {
+                        if (gh.tid == 0) atomicOr(a.err, kErrTarget);
+                    } else if (merge_node<false>(a, x, wave, sh, gh, cand)) {
+                        if (gh.tid == 0) {
+                            hstat[h][0] += 1;
+                            hstat[h][1] += (unsigned long long)cand;
+                        }
+                    } else if (gh.tid == 0) {
+                        hctl[1 + h] = x;
+                        hstat[h][2] += 1;
+                        __hip_atomic_store(&hctl[0], 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                __syncthreads();
             }
         }
         if (threadIdx.x == 0 && tr) {
@@ -1466,10 +1787,20 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
         ++i_step;
     }
     if (lane_id() == 0) {
+        const bool t0 = threadIdx.x == 0;
         atomicAdd((unsigned long long *)&a.out[kOutMerges],
-                  (unsigned long long)(wv_merges + (threadIdx.x == 0 ? st_merges : 0)));
+                  (unsigned long long)(wv_merges + (t0 ? st_merges : 0)));
         atomicAdd((unsigned long long *)&a.out[kOutCandidates],
-                  (unsigned long long)(wv_cand + (threadIdx.x == 0 ? st_cand : 0)));
+                  (unsigned long long)(wv_cand + (t0 ? st_cand : 0)));
+    }
+    if (kHalves && threadIdx.x < 2) {
+        const unsigned long long *hs = hstat[threadIdx.x];
+        if (hs[0] | hs[2]) {
+            atomicAdd((unsigned long long *)&a.out[kOutMerges], hs[0]);
+            atomicAdd((unsigned long long *)&a.out[kOutCandidates], hs[1]);
+            atomicAdd((unsigned long long *)&a.out[kOutHalfMerges], hs[0]);
+            atomicAdd((unsigned long long *)&a.out[kOutBackouts], hs[2]);
+        }
     }
     if (threadIdx.x == 0) {
         if (b == 0) {
@@ -1480,11 +1811,16 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
     }
 }
 
-// The two builds of the persistent search: with single-wave merges for
-// iterations with many small targets (large batches), and without (the
-// workgroup path only, which the compiler then schedules on its own).
-__global__ void __launch_bounds__(1024) k_search(SearchArgs a) { search_body<false>(a); }
-__global__ void __launch_bounds__(1024) k_search_wave(SearchArgs a) { search_body<true>(a); }
+// The three builds of the persistent search: with single-wave merges for
+// iterations with many small targets (large batches); the workgroup path
+// only; and the workgroup path with merges by halves (two targets at once per
+// workgroup in iterations with enough of them).  Each build gets its own
+// register allocation.
+__global__ void __launch_bounds__(1024) k_search(SearchArgs a) { search_body<false, false>(a); }
+__global__ void __launch_bounds__(1024) k_search_halves(SearchArgs a) {
+    search_body<false, true>(a);
+}
+__global__ void __launch_bounds__(1024) k_search_wave(SearchArgs a) { search_body<true, false>(a); }
 
 __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
     // front labels X = sum_v |P(v)| and useful relaxations R = sum_v |P(v)| outdeg(v)
@@ -1590,8 +1926,8 @@ __global__ void __launch_bounds__(1024) k_goal_front(SearchArgs a, GoalArgs g) {
                     s.misc[7] = 0;
                 }
                 __syncthreads();
-                merge_chunk<false>(s, nB, nC, a.capB, a.near_scan, a.qnobj[q] >= 3, glo, a.err,
-                                   false);
+                Grp<false> gw = whole_group();
+                merge_chunk<false>(s, gw, nB, nC, a.near_scan, a.qnobj[q] >= 3, glo, a.err, false);
             }
         }
         const long long o = g.lab_off[q];

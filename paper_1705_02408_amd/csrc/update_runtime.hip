@@ -353,7 +353,8 @@ int mpap_search_update(const mpap_result *prev, const mpap_graph *gc,
     int r = search_prep(g, sp, 1, p);
     if (r) return r;
     SearchShape L;
-    if ((r = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L))) return r;
+    if ((r = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L, p.merge_halves)))
+        return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const Workspace *ow = prev->ws;
     const int n = g->n;

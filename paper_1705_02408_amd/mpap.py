@@ -56,7 +56,7 @@ class mpap_search_params(ctypes.Structure):
                 ("near_scan", ctypes.c_int32), ("stage_cap", ctypes.c_int32),
                 ("heuristic", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("wave_min_targets", ctypes.c_int32), ("skip", ctypes.c_int32),
-                ("early_stop", ctypes.c_int32)]
+                ("early_stop", ctypes.c_int32), ("merge_halves", ctypes.c_int32)]
 
 
 class mpap_stats(ctypes.Structure):
@@ -66,7 +66,9 @@ class mpap_stats(ctypes.Structure):
                 ("relaxations", ctypes.c_int64), ("gpu_ms", ctypes.c_float),
                 ("lds_front_cap", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("max_front", ctypes.c_int32), ("wave_build", ctypes.c_int32),
-                ("judged_failed", ctypes.c_int32), ("fallback_ms", ctypes.c_float)]
+                ("judged_failed", ctypes.c_int32), ("fallback_ms", ctypes.c_float),
+                ("half_front_cap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("half_merges", ctypes.c_int64), ("half_backouts", ctypes.c_int64)]
 
 
 class mpap_mc_params(ctypes.Structure):
@@ -359,21 +361,23 @@ class Result:
 def search_params(beta: float, n_obj: int, radius: float, lam: float = 0.5,
                   init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
                   stage_cap: int = 0, heuristic: int = 0, block_threads: int = 0,
-                  wave_min_targets: int = 0, skip: int = 0, early_stop: int = 0):
+                  wave_min_targets: int = 0, skip: int = 0, early_stop: int = 0,
+                  merge_halves: int = 0):
     return mpap_search_params(float(beta), float(lam), float(radius), int(n_obj),
                               int(init_node), int(max_waves), int(near_scan), int(stage_cap),
                               int(heuristic), int(block_threads), int(wave_min_targets),
-                              int(skip), int(early_stop))
+                              int(skip), int(early_stop), int(merge_halves))
 
 
 def mpap_search(graph: Graph, beta: float, n_obj: int, radius: float, lam: float = 0.5,
                 init_node: int = 0, max_waves: int = 0, near_scan: int = 0,
                 stage_cap: int = 0, heuristic: int = 0, stream=None,
                 block_threads: int = 0, wave_min_targets: int = 0,
-                early_stop: int = 0) -> Result:
+                early_stop: int = 0, merge_halves: int = 0) -> Result:
     lib = load()
     sp = search_params(beta, n_obj, radius, lam, init_node, max_waves, near_scan, stage_cap,
-                       heuristic, block_threads, wave_min_targets, early_stop=early_stop)
+                       heuristic, block_threads, wave_min_targets, early_stop=early_stop,
+                       merge_halves=merge_halves)
     h = ctypes.c_void_p()
     _check(lib.mpap_search(graph.handle, ctypes.byref(sp), _stream(stream), ctypes.byref(h)))
     return Result(h, graph)
@@ -568,7 +572,7 @@ def mpap_result_stats(res: Result) -> dict:
     lib = load()
     s = mpap_stats()
     _check(lib.mpap_result_stats(res.handle, ctypes.byref(s)))
-    return {k: getattr(s, k) for k, _ in mpap_stats._fields_}
+    return {k: getattr(s, k) for k, _ in mpap_stats._fields_ if k != "reserved"}
 
 
 def mpap_wave_trace(res: Result) -> np.ndarray:

@@ -158,6 +158,40 @@ def test_smaller_workgroups_give_the_same_fronts(full3d, threads):
     r2.close()
 
 
+def test_merges_by_halves_full_size(full3d):
+    """The default launch merges two targets at once per workgroup (one per
+    half, each in half the LDS); whole workgroups only must give the same
+    fronts, and both must be the stored oracle result."""
+    env, g, dg, res, fronts = full3d
+    st = res.stats()
+    print("default:", {k: st[k] for k in ("gpu_ms", "merges", "half_merges", "half_backouts",
+                                            "half_front_cap")}, flush=True)
+    assert st["half_front_cap"] >= 1024 and st["half_merges"] > st["merges"] // 2
+    r2 = mpap.mpap_search(dg, env.beta, 3, env.radius, env.lam, merge_halves=-1)
+    s2 = r2.stats()
+    print("whole workgroups:", {k: s2[k] for k in ("gpu_ms", "merges", "half_merges")}, flush=True)
+    assert s2["half_merges"] == 0 and s2["half_front_cap"] == 0
+    f2 = [r2.node_front(v) for v in range(len(fronts))]
+    assert_fronts_match_golden(f2, s2, r2.goal_front().vecs, "whole workgroups")
+    r2.close()
+
+
+def test_halves_back_out_of_fronts_that_outgrow_their_stage(full3d):
+    """With a 1,024-label stage a half takes fronts of up to 768 labels; a
+    merge that grows one beyond 1,024 backs out (nothing written) and the
+    whole workgroup merges it again, spilling beyond its own 1,024-label
+    stage.  Every front must still be the stored oracle result."""
+    env, g, dg, res, fronts = full3d
+    r2 = mpap.mpap_search(dg, env.beta, 3, env.radius, env.lam, stage_cap=1024)
+    s2 = r2.stats()
+    print("stage 1024:", {k: s2[k] for k in ("gpu_ms", "merges", "half_merges", "half_backouts",
+                                               "half_front_cap", "lds_front_cap")}, flush=True)
+    assert s2["half_front_cap"] == 1024 and s2["half_backouts"] > 0
+    f2 = [r2.node_front(v) for v in range(len(fronts))]
+    assert_fronts_match_golden(f2, s2, r2.goal_front().vecs, "stage 1024")
+    r2.close()
+
+
 def test_single_wave_merges_full_size(full3d):
     """Every iteration of the full-size search with single-wave merges for the
     small fronts: the same fronts."""

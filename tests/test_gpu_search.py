@@ -356,17 +356,45 @@ def hub_graph(seed, n_b=10, n_a=40, n_spoke=1500, fan=6, p_reset=0.1):
     return from_edges(n, edges, reset, goal_mask), hub
 
 
-@pytest.mark.parametrize("n_obj,threads,lam", [(3, 256, 1e6), (3, 1024, 1e6), (2, 256, 1e6),
-                                               (3, 1024, 0.5)])
-def test_hub_with_many_in_edge_tiles(n_obj, threads, lam):
+@pytest.mark.parametrize("n_obj,threads,lam,halves", [
+    (3, 256, 1e6, 0), (3, 1024, 1e6, 0), (2, 256, 1e6, 0), (3, 1024, 0.5, 0),
+    (3, 1024, 1e6, 1 << 20), (2, 1024, 1e6, 1 << 20)])
+def test_hub_with_many_in_edge_tiles(n_obj, threads, lam, halves):
+    """halves > 0 forces merges by halves with no children limit: the 1,500
+    spokes are merged two at a time per workgroup and the hub (thousands of
+    children in several in-edge tiles) by one half."""
     g, hub = hub_graph(7)
     assert g["col"].tolist().count(hub) > 1024
     beta = 0.5
     ref = osearch.search(g, beta, n_obj)
-    dg, res = run(g, beta, n_obj, radius=0.5, lam=lam, block_threads=threads)
+    dg, res = run(g, beta, n_obj, radius=0.5, lam=lam, block_threads=threads,
+                  merge_halves=halves)
     st = check_against_oracle(g, res, ref, beta, n_obj)
     print(f"hub n_obj {n_obj} threads {threads}: X {st['front_labels']}, hub front "
-          f"{res.node_front(hub).shape[0]}, candidates {st['candidates']}", flush=True)
+          f"{res.node_front(hub).shape[0]}, candidates {st['candidates']}, half merges "
+          f"{st['half_merges']}", flush=True)
+    if halves:
+        assert st["half_merges"] > 0
+    res.close()
+    dg.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_merges_by_halves_match_the_oracle(road2d, seed):
+    """The build with merges by halves forced on the 2,000-sample roadmaps
+    (which default to whole workgroups): every front against the oracle.  A
+    group factor of 4 (the fronts do not depend on it) gives iterations with
+    the 512 targets that merging by halves needs."""
+    env, g = road2d[seed]
+    ref = osearch.search(g, env.beta, 2)
+    dg = upload(g)
+    res = mpap.mpap_search(dg, env.beta, 2, env.radius, 4.0, merge_halves=8192)
+    st = res.stats()
+    assert st["half_front_cap"] > 0 and st["half_merges"] > 0, st
+    check_against_oracle(g, res, ref, env.beta, 2)
+    r0 = mpap.mpap_search(dg, env.beta, 2, env.radius, env.lam)
+    assert r0.stats()["half_merges"] == 0 and r0.stats()["half_front_cap"] == 0
+    r0.close()
     res.close()
     dg.close()
 
