@@ -171,13 +171,13 @@ typedef struct {
                                  of P_candidates at that point (entry 0 = P_soln), which
                                  depends on lambda and need not be the exact front */
     int32_t merge_halves;     /* tuning: merges by halves.  With 1024-thread workgroups,
-                                 in iterations with at least two merge targets per
-                                 workgroup, each half of a workgroup merges its own
-                                 targets (two at once per CU); large fronts and targets
-                                 with more than merge_halves children (0: 8192) take the
-                                 whole workgroup.  0 = on for roadmaps of at least
-                                 16 x (workgroups) nodes; > 0 = on; < 0 = off.  Never
-                                 changes the result. */
+                                 in iterations with at least eight merge targets per
+                                 workgroup (two when forced), each half of a workgroup
+                                 merges its own targets (two at once per CU); large
+                                 fronts and targets with more than merge_halves children
+                                 (0: 8192) take the whole workgroup.  0 = on for roadmaps
+                                 of at least 16 x (workgroups) nodes; > 0 = on (forced);
+                                 < 0 = off.  Never changes the result. */
 } mpap_search_params;
 
 /*

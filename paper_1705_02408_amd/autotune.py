@@ -2,13 +2,14 @@
 
 None of the tuned settings changes a result: the fronts are the same for any
 group factor (lambda), near-scan length, LDS staging size of a front (the
-bucket stage), workgroup size and single-wave threshold (the tile of one
-merge: a workgroup or a wave).  They trade the number of Explore iterations
-(grid barriers) against wasted expansions, scan work against staging, and
-large merges against many small ones.  The tuner times the search launch
-with its device clock over one setting at a time (coordinate descent in the
-order lambda, near-scan, workgroup size, single-wave threshold, LDS stage),
-keeps the fastest, and caches the choice in a JSON file keyed by device and a
+bucket stage), workgroup size, single-wave threshold and merges by halves
+(the tile of one merge: a workgroup, half a workgroup or a wave).  They
+trade the number of Explore iterations (grid barriers) against wasted
+expansions, scan work against staging, and large merges against many small
+ones.  The tuner times the search launch with its device clock over one
+setting at a time (coordinate descent in the order lambda, near-scan,
+workgroup size, single-wave threshold, LDS stage, merges by halves), keeps
+the fastest, and caches the choice in a JSON file keyed by device and a
 workload class (dimension mix, objective count and a size bucket).
 """
 from __future__ import annotations
@@ -28,9 +29,11 @@ NEAR_SCANS = (8, 16, 32)
 BLOCK_THREADS = (1024, 512)
 WAVE_MIN_TARGETS = (0, -1, 1)   # default threshold, never, every iteration
 STAGE_CAPS = (0, 2048)          # 0 = all the LDS holds
+MERGE_HALVES = (0, -1, 8192)    # by roadmap size, never, always
 
 # the tuned fields of mpap_search_params, in descent order
-FIELDS = ("lambda_", "near_scan", "block_threads", "wave_min_targets", "stage_cap")
+FIELDS = ("lambda_", "near_scan", "block_threads", "wave_min_targets", "stage_cap",
+          "merge_halves")
 
 
 @dataclasses.dataclass
@@ -42,10 +45,12 @@ class Choice:
     block_threads: int = 0
     wave_min_targets: int = 0
     stage_cap: int = 0
+    merge_halves: int = 0
 
     def fields(self) -> dict:
         return dict(lambda_=self.lam, near_scan=self.near_scan, block_threads=self.block_threads,
-                    wave_min_targets=self.wave_min_targets, stage_cap=self.stage_cap)
+                    wave_min_targets=self.wave_min_targets, stage_cap=self.stage_cap,
+                    merge_halves=self.merge_halves)
 
 
 def workload_key(device: str, dims, n_obj: int, nodes: int) -> str:
@@ -83,7 +88,8 @@ def _copy(p, **over):
 def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_CACHE,
          repeats: int = 2, lambdas=LAMBDAS, near_scans=NEAR_SCANS,
          block_threads=BLOCK_THREADS, wave_min_targets=WAVE_MIN_TARGETS,
-         stage_caps=STAGE_CAPS, use_cache: bool = True, log=None) -> Choice:
+         stage_caps=STAGE_CAPS, merge_halves=MERGE_HALVES, use_cache: bool = True,
+         log=None) -> Choice:
     """Pick the settings for ``graph`` searched with ``base_params`` (one
     mpap_search_params, or one per query; their tuned fields are overridden).
     Returns the choice; the cache is updated.  ``log`` (optional) receives one
@@ -98,11 +104,13 @@ def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_
         c = cache[key]
         return Choice(c["lam"], c["near_scan"], c["kernel_ms"], c.get("tried", []),
                       c.get("block_threads", 0), c.get("wave_min_targets", 0),
-                      c.get("stage_cap", 0))
+                      c.get("stage_cap", 0), c.get("merge_halves", 0))
     base = base_params if isinstance(base_params, list) else [base_params]
-    cur = dict(lambda_=0.5, near_scan=16, block_threads=1024, wave_min_targets=0, stage_cap=0)
+    cur = dict(lambda_=0.5, near_scan=16, block_threads=1024, wave_min_targets=0, stage_cap=0,
+               merge_halves=0)
     grid = dict(lambda_=lambdas, near_scan=near_scans, block_threads=block_threads,
-                wave_min_targets=wave_min_targets, stage_cap=stage_caps)
+                wave_min_targets=wave_min_targets, stage_cap=stage_caps,
+                merge_halves=merge_halves)
     tried = []
     seen = {}
 
@@ -126,11 +134,13 @@ def tune(graph, base_params, dims, n_obj: int, cache_path: str | None = DEFAULT_
                 best_v, best_ms = v, ms
         cur[f] = best_v
     choice = Choice(cur["lambda_"], cur["near_scan"], seen[tuple(cur[f] for f in FIELDS)], tried,
-                    cur["block_threads"], cur["wave_min_targets"], cur["stage_cap"])
+                    cur["block_threads"], cur["wave_min_targets"], cur["stage_cap"],
+                    cur["merge_halves"])
     if cache_path:
         cache[key] = dict(lam=choice.lam, near_scan=choice.near_scan,
                           block_threads=choice.block_threads,
                           wave_min_targets=choice.wave_min_targets, stage_cap=choice.stage_cap,
+                          merge_halves=choice.merge_halves,
                           kernel_ms=choice.kernel_ms, tried=tried, when=time.time())
         tmp = cache_path + f".tmp{os.getpid()}"
         with open(tmp, "w") as fh:

@@ -643,7 +643,10 @@ int search_shape(int stage_cap, int block_threads, int wave_min_targets, SearchS
             L.capCh = ch;
             L.big_front = (int)(3 * cb / 4);
             L.big_children = merge_halves > 0 ? std::min(merge_halves, 1 << 24) : 8192;
-            L.halves_min = 2 * L.nblocks;
+            // iterations with fewer targets than eight per workgroup merge
+            // by whole workgroups: each half would get a few, and one heavy
+            // merge by a half sets the pace (two per workgroup when forced)
+            L.halves_min = (merge_halves > 0 ? 2 : 8) * L.nblocks;
             L.halves_forced = merge_halves > 0;
         }
     }

@@ -395,11 +395,11 @@ int acquire_workspace(mpap_graph *g, const SearchShape &L, Workspace **out);
 GoalArgs goal_args(const mpap_graph *g, Workspace *w);
 // The search kernel build for a launch on g: with single-wave merges only
 // when some iteration can have wmin targets (or the caller asked for them).
-// The build with merges by halves runs on roadmaps of at least 8 halves_min
-// nodes (smaller ones rarely have iterations with halves_min targets), or
+// The build with merges by halves runs on roadmaps of at least 16 nodes per
+// workgroup (smaller ones rarely have iterations with enough targets), or
 // when the caller asked for it.
 inline bool halves_build(const SearchShape &L, int n) {
-    return L.halves && (L.halves_forced || n >= 8 * (long long)L.halves_min);
+    return L.halves && (L.halves_forced || n >= 16 * (long long)L.nblocks);
 }
 inline const void *search_kernel_for(const SearchShape &L, int n) {
     const bool wave = L.wcap > 0 && (L.explicit_wmin || n >= 4 * (long long)L.wmin);

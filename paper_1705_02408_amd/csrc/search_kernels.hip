@@ -282,20 +282,21 @@ struct MergeLds {
 // A merge runs on a group of threads: the whole workgroup (workgroup
 // barriers), or one half of it, so that the two halves merge two targets at
 // once.  A half synchronises through LDS words of its own: an arrival count
-// and a generation (the last wave to arrive resets the count and advances the
-// generation; the others wait for the advance), and three count slots used in
-// rotation.  A half's merge reads global memory but writes it only in its
-// write-back, which no other thread of the half reads, so its barriers order
-// LDS only.
+// that only grows (each wave adds one per barrier without waiting for the
+// result, then waits until the count reaches the waves' total for this
+// barrier), and three count slots used in rotation.  A half's merge reads
+// global memory but writes it only in its write-back, which no other thread
+// of the half reads, so its barriers order LDS only.
 template <bool kHalf>
 struct Grp {
     int tid;   // thread index in the group
     int nt;    // threads in the group
     int w;     // wave index in the group
     int nw;    // waves in the group
-    int *bar;  // kHalf: LDS words {arrivals, generation, three count slots}
+    int *bar;  // kHalf: LDS words {arrivals, unused, three count slots}
     int k;     // kHalf: gcount calls so far, modulo 3 (selects the slot)
     int *err;  // kHalf: error word (a barrier wait beyond its bound sets kErrTimeout)
+    unsigned arrive;  // kHalf: the arrival count that ends the last barrier
 };
 
 // polls of a half's barrier before it gives up (about 0.1 s; a wait is
@@ -305,7 +306,7 @@ constexpr unsigned kHalfSpinLimit = 1u << 20;
 __device__ __forceinline__ Grp<false> whole_group() {
     return Grp<false>{(int)threadIdx.x, (int)blockDim.x,
                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)),
-                      (int)(blockDim.x >> 6), nullptr, 0, nullptr};
+                      (int)(blockDim.x >> 6), nullptr, 0, nullptr, 0};
 }
 
 template <bool kHalf>
@@ -313,24 +314,21 @@ __device__ __forceinline__ void gsync(Grp<kHalf> &gp) {
     if constexpr (!kHalf) {
         __syncthreads();
     } else {
+        // this wave's LDS writes complete before it arrives
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        gp.arrive += (unsigned)gp.nw;
         if (lane_id() == 0) {
-            int *cnt = gp.bar, *gen = gp.bar + 1;
-            // the generation is read before arriving: it cannot advance until
-            // this wave has arrived
-            const int my = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (__hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) ==
-                gp.nw - 1) {
-                __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_store(gen, my + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            } else {
-                unsigned polls = 0;
-                while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == my) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++polls > kHalfSpinLimit) {
-                        atomicOr(gp.err, kErrTimeout);
-                        break;
-                    }
+            int *cnt = gp.bar;
+            __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            unsigned polls = 0;
+            // (the difference, not the values, is compared: the count may wrap)
+            while ((int)((unsigned)__hip_atomic_load(cnt, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP) -
+                         gp.arrive) < 0) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++polls > kHalfSpinLimit) {
+                    atomicOr(gp.err, kErrTimeout);
+                    break;
                 }
             }
         }
@@ -1725,7 +1723,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
             if constexpr (kHalves) {
                 Grp<true> gh{(int)threadIdx.x & 511, 512,
                              __builtin_amdgcn_readfirstlane(((int)threadIdx.x >> 6) & 7), 8, hbar[h],
-                             0, a.err};
+                             0, a.err, 0};
                 MergeLds sh;
                 carve_group(lds + (size_t)h * a.half_lds, a, sh, a.capBh, a.capCh, 512, false);
                 if (threadIdx.x < 16) hbar[threadIdx.x >> 3][threadIdx.x & 7] = 0;

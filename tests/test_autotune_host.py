@@ -14,10 +14,10 @@ class FakeGraph:
 def cost(params):
     p = params[0]
     # a separable cost whose minimum is lambda 1.0, near_scan 32, 512 threads,
-    # wave threshold -1, stage cap 0
+    # wave threshold -1, stage cap 0, merges by halves always
     return ((p.lambda_ - 1.0) ** 2 + abs(p.near_scan - 32) / 8 +
             (0 if p.block_threads == 512 else 1) + (0 if p.wave_min_targets == -1 else 0.5) +
-            (0 if p.stage_cap == 0 else 0.25) + 10.0)
+            (0 if p.stage_cap == 0 else 0.25) + (0 if p.merge_halves == 8192 else 0.125) + 10.0)
 
 
 def test_descent_finds_the_separable_minimum(tmp_path, monkeypatch):
@@ -31,8 +31,8 @@ def test_descent_finds_the_separable_minimum(tmp_path, monkeypatch):
     base = [mpap.search_params(0.3, 2, 0.05, 0.5, heuristic=1) for _ in range(3)]
     cache = str(tmp_path / "cache.json")
     ch = autotune.tune(FakeGraph(), base, [2, 3], 2, cache_path=cache, repeats=1)
-    assert (ch.lam, ch.near_scan, ch.block_threads, ch.wave_min_targets, ch.stage_cap) == \
-        (1.0, 32, 512, -1, 0)
+    assert (ch.lam, ch.near_scan, ch.block_threads, ch.wave_min_targets, ch.stage_cap,
+            ch.merge_halves) == (1.0, 32, 512, -1, 0, 8192)
     assert ch.kernel_ms == pytest.approx(10.0)
     # every timed setting keeps the caller's other fields
     for ps in calls:
@@ -44,3 +44,4 @@ def test_descent_finds_the_separable_minimum(tmp_path, monkeypatch):
     out = autotune.apply(base, ch)
     assert [p.block_threads for p in out] == [512] * 3 and out[0].heuristic == 1
     assert out[0].lambda_ == 1.0 and out[0].near_scan == 32 and out[0].wave_min_targets == -1
+    assert out[0].merge_halves == 8192
