@@ -59,7 +59,14 @@ def search_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(profile: str = "k_search_plain3d_n20000.md"):
+def search_kernel(st: dict) -> str:
+    """Name of the search build that ran (from a result's statistics)."""
+    if st.get("wave_build"):
+        return "k_search_wave"
+    return "k_search_halves" if st.get("half_front_cap", 0) > 0 else "k_search"
+
+
+def measured_traffic(profile: str = "k_search_halves_plain3d_n20000.md"):
     """HBM bytes per search launch from a committed rocprofv3 counter summary
     under profiles/, or None when the kernel sources have changed since the
     counters were taken."""
@@ -150,7 +157,9 @@ def measure_single(env, steps: int, warmup: int, with_trace: bool = True):
         "goal_front": int(fr.vecs.shape[0]), "kernel_ms_mean": k_ms, "kernel_ms_min": min(kms),
         "step_ms_median": 1000 * statistics.median(times), "blocks": st["blocks"],
         "lds_front_cap": st["lds_front_cap"], "max_front": st["max_front"],
-        "wave_build": st["wave_build"], "alg_bytes_per_launch": B,
+        "wave_build": st["wave_build"], "kernel": search_kernel(st),
+        "half_merges": st["half_merges"], "half_backouts": st["half_backouts"],
+        "alg_bytes_per_launch": B,
         "achieved_GBps": B / (k_ms * 1e-3) / 1e9,
     }
     if with_trace and "t" in trace:
@@ -491,7 +500,8 @@ def measure_batch(args, with_surrogate: bool = True):
                 "latency_ms": {"p50": float(np.percentile(lat, 50)),
                                "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
                 "X_front_labels": st["front_labels"], "R_relaxations": st["relaxations"],
-                "waves": st["waves"], "wave_build": st["wave_build"]}
+                "waves": st["waves"], "wave_build": st["wave_build"],
+                "half_front_cap": st["half_front_cap"], "kernel": search_kernel(st)}
 
     res_sur = None
     if with_surrogate:
@@ -538,7 +548,7 @@ def measure_batch(args, with_surrogate: bool = True):
         "nodes": info["n"], "edges": info["e"],
         "roofline": {"bound": "hbm", "achieved": B / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": B / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "kernel": "k_search_wave" if res_ana["wave_build"] else "k_search",
+                     "kernel": search_kernel(res_ana),
                      "alg_bytes_per_launch": B,
                      "traffic": measured_traffic("k_search_wave_batch256.md")
                      if args.queries == 256 and args.seed == 0 else None},
@@ -668,7 +678,7 @@ def main():
                      "traffic": measured_traffic() if headline_3d else None,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "scaled by a plain copy's counts)",
-                     "kernel": "k_search_wave" if head["wave_build"] else "k_search",
+                     "kernel": head["kernel"],
                      "alg_bytes_per_launch": head["alg_bytes_per_launch"]},
         "cpu_baseline": cpu,
     }

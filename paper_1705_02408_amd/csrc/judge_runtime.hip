@@ -184,6 +184,7 @@ int mpap_judge(mpap_result *r, float tol, int32_t fallback, void *stream, uint8_
     SearchShape L;
     int rc = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L, p.merge_halves);
     if (rc) return rc;
+    L.obj = uniform_objectives(p);
     Workspace *w = nullptr;
     if ((rc = acquire_workspace(g, L, &w))) return rc;
     mpap_result *fb = new mpap_result();

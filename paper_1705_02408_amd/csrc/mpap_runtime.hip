@@ -755,9 +755,8 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
     res->stats.lds_front_cap = L.capB;
     res->stats.max_front = (int32_t)dev_out[kOutMaxFront];
     res->stats.blocks = L.nblocks;
-    res->stats.wave_build = search_kernel_for(L, g->n) == reinterpret_cast<const void *>(k_search_wave);
-    res->stats.half_front_cap =
-        search_kernel_for(L, g->n) == reinterpret_cast<const void *>(k_search_halves) ? L.capBh : 0;
+    res->stats.wave_build = wave_build(L, g->n);
+    res->stats.half_front_cap = !wave_build(L, g->n) && halves_build(L, g->n) ? L.capBh : 0;
     res->stats.reserved = 0;
     res->stats.half_merges = dev_out[kOutHalfMerges];
     res->stats.half_backouts = dev_out[kOutBackouts];
@@ -947,6 +946,7 @@ int mpap_search_batch(const mpap_graph *gc, const mpap_search_params *sp, int32_
     SearchShape L;
     if ((r = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L, p.merge_halves)))
         return r;
+    L.obj = uniform_objectives(p);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     Workspace *w = nullptr;

@@ -139,6 +139,7 @@ extern "C" int mpap_search_noalloc(const mpap_graph *gc, const mpap_search_param
                           x.block_threads ? x.block_threads : 1024, x.wave_min_targets, L,
                           x.merge_halves)))
         return r;
+    L.obj = x.n_obj == 2 || x.n_obj == 3 ? x.n_obj : 0;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     // carve: per-node state, fixed words, then the label stores.  No spill

@@ -240,6 +240,7 @@ int mpap_plan_create(mpap_graph *g, const mpap_search_params *sp, int32_t nsp,
     int r = search_prep(g, sp, nsp, p->prep);
     if (!r) r = search_shape(p->prep.stage_cap, p->prep.block_threads, p->prep.wave_min_targets,
                              p->shape, p->prep.merge_halves);
+    if (!r) p->shape.obj = uniform_objectives(p->prep);
     auto bail = [&](int st) {
         mpap_plan_free(p);
         return st;

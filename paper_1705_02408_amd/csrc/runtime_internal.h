@@ -372,6 +372,7 @@ struct SearchShape {
     int halves = 0, half_lds = 0, capBh = 0, capCh = 0, big_front = 0, big_children = 0;
     int halves_min = 0;  // least targets of an iteration that merges by halves
     bool halves_forced = false;  // the halves build whatever the roadmap's size
+    int obj = 0;  // 2 or 3: every query has that many objectives (a build for it); 0: mixed
     size_t lds = 0;
 };
 int search_prep(const mpap_graph *g, const mpap_search_params *sp, int32_t nsp, SearchPrep &p);
@@ -401,11 +402,34 @@ GoalArgs goal_args(const mpap_graph *g, Workspace *w);
 inline bool halves_build(const SearchShape &L, int n) {
     return L.halves && (L.halves_forced || n >= 16 * (long long)L.nblocks);
 }
+inline bool wave_build(const SearchShape &L, int n) {
+    return L.wcap > 0 && (L.explicit_wmin || n >= 4 * (long long)L.wmin);
+}
+// The search build for a launch on g (see search_kernels.h).
 inline const void *search_kernel_for(const SearchShape &L, int n) {
-    const bool wave = L.wcap > 0 && (L.explicit_wmin || n >= 4 * (long long)L.wmin);
-    return wave ? reinterpret_cast<const void *>(k_search_wave)
-           : halves_build(L, n) ? reinterpret_cast<const void *>(k_search_halves)
-                                : reinterpret_cast<const void *>(k_search);
+    const void *k;
+    if (wave_build(L, n))
+        k = L.obj == 2 ? reinterpret_cast<const void *>(k_search_wave_o2)
+                       : reinterpret_cast<const void *>(k_search_wave);
+    else if (halves_build(L, n))
+        k = L.obj == 2   ? reinterpret_cast<const void *>(k_search_halves_o2)
+            : L.obj == 3 ? reinterpret_cast<const void *>(k_search_halves_o3)
+                         : reinterpret_cast<const void *>(k_search_halves);
+    else
+        k = L.obj == 2   ? reinterpret_cast<const void *>(k_search_o2)
+            : L.obj == 3 ? reinterpret_cast<const void *>(k_search_o3)
+                         : reinterpret_cast<const void *>(k_search);
+    return k;
+}
+// 2 or 3 when every searched query of p has that many objectives, else 0
+inline int uniform_objectives(const SearchPrep &p) {
+    int o = -1;
+    for (int q = 0; q < p.nq; ++q) {
+        if (q < (int)p.skip.size() && p.skip[q]) continue;
+        if (o < 0) o = p.nobj[q];
+        else if (o != p.nobj[q]) return 0;
+    }
+    return o == 2 || o == 3 ? o : 0;
 }
 
 // Fills res's fronts, statistics, trace and latencies from host copies.

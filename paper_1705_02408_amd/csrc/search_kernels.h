@@ -167,9 +167,16 @@ __global__ void k_rescore(const int2 *arena, const int *optr, const int *ocol,
                           int maxlen, float4 *out, int *err, const float4 *sur, float tol,
                           uint8_t *pass);
 __global__ void k_search_roots(SearchArgs a);
+// builds of the persistent search (_o2 / _o3: every query has two / three
+// objectives; without: decided per query)
 __global__ void k_search(SearchArgs a);
+__global__ void k_search_o2(SearchArgs a);
+__global__ void k_search_o3(SearchArgs a);
 __global__ void k_search_halves(SearchArgs a);  // with merges by halves
+__global__ void k_search_halves_o2(SearchArgs a);
+__global__ void k_search_halves_o3(SearchArgs a);
 __global__ void k_search_wave(SearchArgs a);  // with single-wave merges
+__global__ void k_search_wave_o2(SearchArgs a);
 __global__ void k_count_front(SearchArgs a);
 // After a search with early stops: the plans still open at the goal nodes of
 // every stopped query get arena ids (after the expanded ones) so that goal

@@ -511,7 +511,20 @@ __device__ __forceinline__ bool any_dominates(const float4 *arr, int end, const 
     for (int sg = (end - 1) >> 6; sg >= 0; --sg) {
         if (use_seg && !(sd[sg] <= q.y && sm[sg] <= q.z)) continue;
         const int lo = sg << 6;
-        for (int j = min(end, lo + 64) - 1 - sub; j >= lo; j -= gs)
+        int j = min(end, lo + 64) - 1 - sub;
+        // four independent reads of (d, m) per step: a label that does not
+        // dominate is usually followed by more such, and the answer does not
+        // depend on the order of the tests
+        for (; j - 3 * gs >= lo; j -= 4 * gs) {
+            const float d0 = arr[j].y, m0 = arr[j].z;
+            const float d1 = arr[j - gs].y, m1 = arr[j - gs].z;
+            const float d2 = arr[j - 2 * gs].y, m2 = arr[j - 2 * gs].z;
+            const float d3 = arr[j - 3 * gs].y, m3 = arr[j - 3 * gs].z;
+            if ((int)(d0 <= q.y && m0 <= q.z) | (int)(d1 <= q.y && m1 <= q.z) |
+                (int)(d2 <= q.y && m2 <= q.z) | (int)(d3 <= q.y && m3 <= q.z))
+                return true;
+        }
+        for (; j >= lo; j -= gs)
             if (dm_le(arr[j], q)) return true;
         if (flag && *(volatile const uint8_t *)flag) return false;
     }
@@ -875,7 +888,9 @@ __device__ void wave_seg_summary(const WaveLds &W, int n) {
 }
 
 // Returns false when the front would outgrow the slice (the target then
-// goes to the workgroup path; nothing has been written).
+// goes to the workgroup path; nothing has been written).  kObj: 2 or 3 when
+// every query has that many objectives, 0 when the query decides.
+template <int kObj>
 __device__ bool wave_merge_node(const SearchArgs &a, int x, int wave, const WaveLds &W,
                                 long long &cand_out) {
     const int l = lane_id();
@@ -887,7 +902,7 @@ __device__ bool wave_merge_node(const SearchArgs &a, int x, int wave, const Wave
     const bool rst = (a.nflag[x] & 1u) != 0u;
     const int q = (a.nq > 1) ? query_of(a, x) : 0;
     const float beta = a.qbeta[q];
-    const bool three = a.qnobj[q] >= 3;
+    const bool three = kObj == 0 ? a.qnobj[q] >= 3 : kObj == 3;
     const float *edrift = a.qheur[q] ? a.sdrift : a.rdrift;
     if (three) wave_seg_summary(W, nB);
     int lo = nB;
@@ -1132,7 +1147,7 @@ __device__ bool stage_front(const SearchArgs &a, MergeLds &s, Grp<kHalf> &gp, co
 // Merges the children of x's in-neighbours' group labels into P(x).  Returns
 // false when a half backs out (the front outgrows the half's LDS stage;
 // nothing was written), true otherwise.
-template <bool kWide, bool kHalf>
+template <bool kWide, int kObj, bool kHalf>
 __device__ __forceinline__ bool merge_node(const SearchArgs &a, int x, int wave, MergeLds &s,
                                            Grp<kHalf> &gp,
                            long long &st_cand) {
@@ -1143,7 +1158,7 @@ __device__ __forceinline__ bool merge_node(const SearchArgs &a, int x, int wave,
     const bool rst = (a.nflag[x] & 1u) != 0u;
     const int q = (a.nq > 1) ? query_of(a, x) : 0;
     const float beta = a.qbeta[q];
-    const bool three = a.qnobj[q] >= 3;
+    const bool three = kObj == 0 ? a.qnobj[q] >= 3 : kObj == 3;
     const float *edrift = a.qheur[q] ? a.sdrift : a.rdrift;
     const int e0 = a.rptr[x], e1 = a.rptr[x + 1];
     bool changed = false, fits = true;
@@ -1405,8 +1420,9 @@ __device__ __forceinline__ void carve_lds(unsigned char *lds, const SearchArgs &
 }
 
 // kHalves (workgroup-only build): iterations with at least a.halves_min
-// targets merge by halves
-template <bool kWaveMerges, bool kHalves>
+// targets merge by halves.  kObj: the objective count of every query (2 or
+// 3), or 0 when it differs between queries.
+template <bool kWaveMerges, bool kHalves, int kObj>
 __device__ __forceinline__ void search_body(SearchArgs a) {
     static_assert(!(kWaveMerges && kHalves), "merges by halves are a workgroup-only build");
     extern __shared__ __align__(16) unsigned char lds[];
@@ -1550,7 +1566,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                 const int x = a.alist[k];
                 if ((unsigned)x >= (unsigned)a.n) {
                     if (lane_id() == 0) atomicOr(a.err, kErrTarget);
-                } else if (wave_merge_node(a, x, wave, W, wv_cand)) {
+                } else if (wave_merge_node<kObj>(a, x, wave, W, wv_cand)) {
                     ++wv_merges;
                 } else if (lane_id() == 0) {
                     const int kb = atomicAdd(&a.acnt[2 + wp], 1);
@@ -1715,7 +1731,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                 Grp<false> gw = whole_group();
                 // (the halves build keeps the single-read survivor step: the
                 // four-read one needs more registers than it leaves)
-                merge_node<!kWaveMerges && !kHalves>(a, cmd, wave, s, gw, st_cand);
+                merge_node<!kWaveMerges && !kHalves, kObj>(a, cmd, wave, s, gw, st_cand);
                 ++st_merges;
                 continue;
             }
@@ -1754,7 +1770,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                     long long cand = 0;
                     if ((unsigned)x >= (unsigned)a.n) {
                         if (gh.tid == 0) atomicOr(a.err, kErrTarget);
-                    } else if (merge_node<false>(a, x, wave, sh, gh, cand)) {
+                    } else if (merge_node<false, kObj>(a, x, wave, sh, gh, cand)) {
                         if (gh.tid == 0) {
                             hstat[h][0] += 1;
                             hstat[h][1] += (unsigned long long)cand;
@@ -1809,16 +1825,34 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
     }
 }
 
-// The three builds of the persistent search: with single-wave merges for
+// The builds of the persistent search: with single-wave merges for
 // iterations with many small targets (large batches); the workgroup path
 // only; and the workgroup path with merges by halves (two targets at once per
-// workgroup in iterations with enough of them).  Each build gets its own
-// register allocation.
-__global__ void __launch_bounds__(1024) k_search(SearchArgs a) { search_body<false, false>(a); }
-__global__ void __launch_bounds__(1024) k_search_halves(SearchArgs a) {
-    search_body<false, true>(a);
+// workgroup in iterations with enough of them); each for queries of two
+// objectives, of three, or of either (decided per query).  Each build gets
+// its own register allocation.
+__global__ void __launch_bounds__(1024) k_search(SearchArgs a) { search_body<false, false, 0>(a); }
+__global__ void __launch_bounds__(1024) k_search_o2(SearchArgs a) {
+    search_body<false, false, 2>(a);
 }
-__global__ void __launch_bounds__(1024) k_search_wave(SearchArgs a) { search_body<true, false>(a); }
+__global__ void __launch_bounds__(1024) k_search_o3(SearchArgs a) {
+    search_body<false, false, 3>(a);
+}
+__global__ void __launch_bounds__(1024) k_search_halves(SearchArgs a) {
+    search_body<false, true, 0>(a);
+}
+__global__ void __launch_bounds__(1024) k_search_halves_o2(SearchArgs a) {
+    search_body<false, true, 2>(a);
+}
+__global__ void __launch_bounds__(1024) k_search_halves_o3(SearchArgs a) {
+    search_body<false, true, 3>(a);
+}
+__global__ void __launch_bounds__(1024) k_search_wave(SearchArgs a) {
+    search_body<true, false, 0>(a);
+}
+__global__ void __launch_bounds__(1024) k_search_wave_o2(SearchArgs a) {
+    search_body<true, false, 2>(a);
+}
 
 __global__ void __launch_bounds__(256) k_count_front(SearchArgs a) {
     // front labels X = sum_v |P(v)| and useful relaxations R = sum_v |P(v)| outdeg(v)

@@ -355,6 +355,7 @@ int mpap_search_update(const mpap_result *prev, const mpap_graph *gc,
     SearchShape L;
     if ((r = search_shape(p.stage_cap, p.block_threads, p.wave_min_targets, L, p.merge_halves)))
         return r;
+    L.obj = uniform_objectives(p);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const Workspace *ow = prev->ws;
     const int n = g->n;
