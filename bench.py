@@ -62,11 +62,14 @@ def search_source_hash() -> str:
 def search_kernel(st: dict) -> str:
     """Name of the search build that ran (from a result's statistics)."""
     if st.get("wave_build"):
-        return "k_search_wave"
-    return "k_search_halves" if st.get("half_front_cap", 0) > 0 else "k_search"
+        base = "k_search_wave"
+    else:
+        base = "k_search_halves" if st.get("half_front_cap", 0) > 0 else "k_search"
+    o = st.get("build_objectives", 0)
+    return f"{base}_o{o}" if o in (2, 3) else base
 
 
-def measured_traffic(profile: str = "k_search_halves_plain3d_n20000.md"):
+def measured_traffic(profile: str = "k_search_halves_o3_plain3d_n20000.md"):
     """HBM bytes per search launch from a committed rocprofv3 counter summary
     under profiles/, or None when the kernel sources have changed since the
     counters were taken."""
@@ -501,7 +504,8 @@ def measure_batch(args, with_surrogate: bool = True):
                                "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
                 "X_front_labels": st["front_labels"], "R_relaxations": st["relaxations"],
                 "waves": st["waves"], "wave_build": st["wave_build"],
-                "half_front_cap": st["half_front_cap"], "kernel": search_kernel(st)}
+                "half_front_cap": st["half_front_cap"],
+                "build_objectives": st["build_objectives"], "kernel": search_kernel(st)}
 
     res_sur = None
     if with_surrogate:
@@ -550,7 +554,7 @@ def measure_batch(args, with_surrogate: bool = True):
                      "unit": "GB/s", "frac": B / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "kernel": search_kernel(res_ana),
                      "alg_bytes_per_launch": B,
-                     "traffic": measured_traffic("k_search_wave_batch256.md")
+                     "traffic": measured_traffic("k_search_wave_o2_batch256.md")
                      if args.queries == 256 and args.seed == 0 else None},
     })
     if not args.no_cpu_baseline:

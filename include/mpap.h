@@ -313,7 +313,8 @@ typedef struct {
     float fallback_ms;        /* device time of the analytic re-search of those queries */
     int32_t half_front_cap;   /* front stage of a half workgroup when merges ran by halves
                                  (two targets at once per workgroup), else 0 */
-    int32_t reserved;
+    int32_t build_objectives; /* 2 or 3: the search build for queries of that many
+                                 objectives ran; 0: the build that decides per query */
     int64_t half_merges;      /* merges done by half workgroups */
     int64_t half_backouts;    /* targets whose front outgrew a half's stage: the half backed
                                  out (nothing written) and the whole workgroup merged them */

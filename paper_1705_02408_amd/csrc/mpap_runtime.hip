@@ -757,7 +757,7 @@ void search_finish(mpap_result *res, const SearchPrep &p, const long long *dev_o
     res->stats.blocks = L.nblocks;
     res->stats.wave_build = wave_build(L, g->n);
     res->stats.half_front_cap = !wave_build(L, g->n) && halves_build(L, g->n) ? L.capBh : 0;
-    res->stats.reserved = 0;
+    res->stats.build_objectives = wave_build(L, g->n) ? (L.obj == 2 ? 2 : 0) : L.obj;
     res->stats.half_merges = dev_out[kOutHalfMerges];
     res->stats.half_backouts = dev_out[kOutBackouts];
     res->stats.gpu_ms = ms;

@@ -67,7 +67,7 @@ class mpap_stats(ctypes.Structure):
                 ("lds_front_cap", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("max_front", ctypes.c_int32), ("wave_build", ctypes.c_int32),
                 ("judged_failed", ctypes.c_int32), ("fallback_ms", ctypes.c_float),
-                ("half_front_cap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("half_front_cap", ctypes.c_int32), ("build_objectives", ctypes.c_int32),
                 ("half_merges", ctypes.c_int64), ("half_backouts", ctypes.c_int64)]
 
 
@@ -572,7 +572,7 @@ def mpap_result_stats(res: Result) -> dict:
     lib = load()
     s = mpap_stats()
     _check(lib.mpap_result_stats(res.handle, ctypes.byref(s)))
-    return {k: getattr(s, k) for k, _ in mpap_stats._fields_ if k != "reserved"}
+    return {k: getattr(s, k) for k, _ in mpap_stats._fields_}
 
 
 def mpap_wave_trace(res: Result) -> np.ndarray:

@@ -19,7 +19,7 @@ def test_algorithmic_bytes():
 
 
 def test_traffic_follows_the_profiled_sources(monkeypatch):
-    with open(os.path.join(ROOT, "profiles", "k_search_plain3d_n20000.md")) as f:
+    with open(os.path.join(ROOT, "profiles", "k_search_halves_o3_plain3d_n20000.md")) as f:
         line = next(l for l in f if l.startswith("traffic:"))
     kv = dict(t.split("=", 1) for t in line.split()[1:])
     expect = int(1024 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
