@@ -1675,6 +1675,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
         if (threadIdx.x == 0) next = phase == 0 ? atomicAdd(wcur, 1) : locate(atomicAdd(cursor, 1));
         // (the half and the wave index are uniform in a wave: read from the
         // first lane, so that the half's LDS views stay in scalar registers)
+        // (merges by halves run in 1024-thread workgroups: halves of 512)
         const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 9);
         if (threadIdx.x < 8) hctl[threadIdx.x] = threadIdx.x == 0 ? 0 : -1;
         __syncthreads();
@@ -1729,9 +1730,10 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                 MergeLds s;
                 carve_lds(lds, a, s);
                 Grp<false> gw = whole_group();
-                // (the halves build keeps the single-read survivor step: the
-                // four-read one needs more registers than it leaves)
-                merge_node<!kWaveMerges && !kHalves, kObj>(a, cmd, wave, s, gw, st_cand);
+                // (the wave-first build and the halves builds for two or
+                // either objective count keep the single-read survivor step:
+                // the four-read one needs more registers than they leave)
+                merge_node<!kWaveMerges && (!kHalves || kObj == 3), kObj>(a, cmd, wave, s, gw, st_cand);
                 ++st_merges;
                 continue;
             }
@@ -1770,7 +1772,7 @@ __device__ __forceinline__ void search_body(SearchArgs a) {
                     long long cand = 0;
                     if ((unsigned)x >= (unsigned)a.n) {
                         if (gh.tid == 0) atomicOr(a.err, kErrTarget);
-                    } else if (merge_node<false, kObj>(a, x, wave, sh, gh, cand)) {
+                    } else if (merge_node<kObj == 3, kObj>(a, x, wave, sh, gh, cand)) {
                         if (gh.tid == 0) {
                             hstat[h][0] += 1;
                             hstat[h][1] += (unsigned long long)cand;
