@@ -4,6 +4,8 @@
 // launches the kernels, grows capacities and retries when the device reports
 // an overflow, and copies results back.  No part of the search itself runs on
 // the host.
+#include <cstring>
+
 #include "runtime_internal.h"
 #include "steer_kernels.h"
 
@@ -663,19 +665,29 @@ int search_upload(Workspace *w, const SearchPrep &p, hipStream_t s) {
     int r;
     if ((r = ws_queries(w, p.nq))) return r;
     const size_t nq = p.nq;
-    HIP_TRY(hipMemcpyAsync(w->qheur, p.heur.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w->qbeta, p.beta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w->qdelta, p.delta.data(), sizeof(float) * nq, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w->qnobj, p.nobj.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
-    std::vector<int> early(nq, 0);
-    for (size_t q = 0; q < nq && q < p.early.size(); ++q) early[q] = p.early[q];
-    HIP_TRY(hipMemcpyAsync(w->qearly, early.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
-    // a skipped query's root is not seeded (-1)
-    std::vector<int> root(p.root);
-    for (size_t q = 0; q < nq; ++q)
-        if (q < p.skip.size() && p.skip[q]) root[q] = -1;
-    HIP_TRY(hipMemcpyAsync(w->qroot, root.data(), sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    // the six per-query arrays, staged in pinned memory (4-byte words each);
+    // the staging is free again once the stream has passed these copies
+    // (every caller synchronises the stream before it stages anything else)
     HIP_TRY(hipStreamSynchronize(s));
+    // (and room after them for the status read-back of the search)
+    if ((r = ws_pinned(w, (((size_t)24 * nq + 15) & ~(size_t)15) + 256))) return r;
+    int *st = reinterpret_cast<int *>(w->hpin);
+    float *stf = reinterpret_cast<float *>(w->hpin);
+    for (size_t q = 0; q < nq; ++q) {
+        st[q] = p.heur[q];
+        stf[nq + q] = p.beta[q];
+        stf[2 * nq + q] = p.delta[q];
+        st[3 * nq + q] = p.nobj[q];
+        st[4 * nq + q] = q < p.early.size() ? p.early[q] : 0;
+        // a skipped query's root is not seeded (-1)
+        st[5 * nq + q] = (q < p.skip.size() && p.skip[q]) ? -1 : p.root[q];
+    }
+    HIP_TRY(hipMemcpyAsync(w->qheur, st, sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qbeta, stf + nq, sizeof(float) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qdelta, stf + 2 * nq, sizeof(float) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qnobj, st + 3 * nq, sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qearly, st + 4 * nq, sizeof(int) * nq, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->qroot, st + 5 * nq, sizeof(int) * nq, hipMemcpyHostToDevice, s));
     return MPAP_OK;
 }
 
@@ -791,12 +803,20 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
     long long capG = std::max<long long>(w->spill_cap, std::max(4 * L.capB, 32768));
     long long dev_out[kOutWords];
     int dev_err = 0;
+    long long gtotal = 0;
     int retries = 0;
     float ms = 0.f;
     SearchArgs a{};
+    // read-back staging after the uploads (search_upload sized it): status
+    // words, error word, goal bound
+    const size_t up = (24 * (size_t)nq + 15) & ~(size_t)15;
+    static_assert(sizeof(long long) * kOutWords + 16 <= 256, "status read-back staging");
     for (;;) {
         if ((r = ws_grow(w, pool_cap, arena_cap, F_cap, 0))) return r;
         if ((r = ws_spill(w, capG))) return r;
+        long long *h_out = reinterpret_cast<long long *>(w->hpin + up);
+        int *h_err = reinterpret_cast<int *>(w->hpin + up + sizeof(dev_out));
+        long long *h_total = reinterpret_cast<long long *>(w->hpin + up + sizeof(dev_out) + 8);
         a = search_args(g, w, p, L);
         k_search_init<<<div_up(g->n, 256), 256, 0, s>>>(a);
         k_search_roots<<<div_up(nq, 256), 256, 0, s>>>(a);
@@ -808,10 +828,22 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         HIP_TRY(hipEventRecord(w->ev1, s));
         if (p.early_any) k_close_stopped<<<1, 1024, 0, s>>>(a);
         k_count_front<<<std::max(1, std::min(div_up(g->n, 256), 1024)), 256, 0, s>>>(a);
+        // the goal-front bound in the same pass (meaningful only when the
+        // search completed)
+        {
+            GoalArgs ga = goal_args(g, w);
+            k_zero_i32<<<div_up(nq, 256), 256, 0, s>>>(w->g_count, nq);
+            k_zero_i32<<<1, 32, 0, s>>>(w->g_overflow, 1);
+            k_goal_bound<<<1, 1024, 0, s>>>(a, ga, 0x7fffffffffffffffll, w->g_total);
+        }
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(dev_out, w->out, sizeof(dev_out), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&dev_err, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_out, w->out, sizeof(dev_out), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_err, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_total, w->g_total, sizeof(long long), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        std::memcpy(dev_out, h_out, sizeof(dev_out));
+        dev_err = *h_err;
+        gtotal = *h_total;
         HIP_TRY(hipEventElapsedTime(&ms, w->ev0, w->ev1));
         const int status = (int)dev_out[kOutStatus];
         if (status == kStatusOk && dev_err == 0) break;
@@ -838,68 +870,81 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         }
     }
 
-    return search_goal_finish(g, p, L, w, s, res, a, dev_out, ms, retries);
+    return search_goal_finish(g, p, L, w, s, res, a, dev_out, ms, retries, gtotal);
 }
 
 int search_goal_finish(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Workspace *w,
                        hipStream_t s, mpap_result *res, const SearchArgs &a,
-                       const long long *dev_out, float ms, int retries) {
+                       const long long *dev_out, float ms, int retries, long long total) {
     const int nq = p.nq;
     int r;
     // goal fronts (a7): exact per-query regions, the fronts, then packed
     std::vector<int> counts(nq, 0), qlast(nq, 0), qstop(nq, -2);
-    {
-        GoalArgs ga = goal_args(g, w);
-        long long total = 0;
+    GoalArgs ga = goal_args(g, w);
+    if (total < 0) {
         k_zero_i32<<<div_up(nq, 256), 256, 0, s>>>(w->g_count, nq);
         k_zero_i32<<<1, 32, 0, s>>>(w->g_overflow, 1);
         k_goal_bound<<<1, 1024, 0, s>>>(a, ga, 0x7fffffffffffffffll, w->g_total);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(&total, w->g_total, sizeof(long long), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if ((r = ws_grow(w, 0, 0, 0, std::max<long long>(total, 1)))) return r;
-        ga = goal_args(g, w);
-        int ovf = 0, gerr = 0;
-        if (total > 0) {
-            k_goal_front<<<std::min(nq, L.nblocks), L.threads, L.lds, s>>>(a, ga);
-            HIP_TRY(hipGetLastError());
-        }
-        HIP_TRY(hipMemcpyAsync(counts.data(), w->g_count, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&gerr, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (ovf || gerr) return fail(MPAP_ERR_OVERFLOW, "goal front overflow");
-        long long packed = 0;
-        for (int q = 0; q < nq; ++q) packed += counts[q];
-        if ((r = ws_pack(w, std::max<long long>(packed, 1)))) return r;
-        if (packed > 0) {
-            k_goal_pack<<<std::min(nq, 1024), 256, 0, s>>>(ga, w->p_lab, w->p_node, w->p_cap);
-            HIP_TRY(hipGetLastError());
-        }
-        std::vector<float4> plab(packed);
-        std::vector<int> pnode(packed);
-        if (packed > 0) {
-            HIP_TRY(hipMemcpyAsync(plab.data(), w->p_lab, sizeof(float4) * packed,
-                                   hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(pnode.data(), w->p_node, sizeof(int) * packed,
-                                   hipMemcpyDeviceToHost, s));
-        }
-        HIP_TRY(hipMemcpyAsync(qlast.data(), w->qlast, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(qstop.data(), w->qstop, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
-        unsigned ptop = 0;
-        HIP_TRY(hipMemcpyAsync(&ptop, w->pool_top, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (ovf) return fail(MPAP_ERR_OVERFLOW, "goal front pack overflow");
-        const int tw = std::min<int>((int)dev_out[kOutWaves], kTraceCap);
-        std::vector<long long> trace((size_t)std::max(tw, 0) * kTraceWords);
-        if (tw > 0)
-            HIP_TRY(hipMemcpy(trace.data(), w->wstat, sizeof(long long) * trace.size(),
-                              hipMemcpyDeviceToHost));
-        search_finish(res, p, dev_out, counts.data(), plab.data(), pnode.data(), qlast.data(),
-                      qstop.data(), trace.data(), ms, retries, L);
-        res->pool_used = ptop;
     }
+    // (the stream is idle from here on until the launches below)
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((r = ws_grow(w, 0, 0, 0, std::max<long long>(total, 1)))) return r;
+    // the packed fronts fit in the per-query regions' total
+    if ((r = ws_pack(w, std::max<long long>(total, 1)))) return r;
+    const int tw = std::min<int>((int)dev_out[kOutWaves], kTraceCap);
+    const size_t trace_words = (size_t)std::max(tw, 0) * kTraceWords;
+    // staging: counts, qlast, qstop (nq ints each), then pool top, overflow,
+    // error, then the trace
+    const size_t o_small = 0, o_words = ((12 * (size_t)nq) + 15) & ~(size_t)15;
+    const size_t o_trace = o_words + 16;
+    if ((r = ws_pinned(w, o_trace + 8 * trace_words))) return r;
+    ga = goal_args(g, w);
+    if (total > 0) {
+        k_goal_front<<<std::min(nq, L.nblocks), L.threads, L.lds, s>>>(a, ga);
+        k_goal_pack<<<std::min(nq, 1024), 256, 0, s>>>(ga, w->p_lab, w->p_node, w->p_cap);
+        HIP_TRY(hipGetLastError());
+    }
+    int *h_counts = reinterpret_cast<int *>(w->hpin + o_small);
+    int *h_qlast = h_counts + nq, *h_qstop = h_counts + 2 * nq;
+    unsigned *h_ptop = reinterpret_cast<unsigned *>(w->hpin + o_words);
+    int *h_ovf = reinterpret_cast<int *>(w->hpin + o_words + 4);
+    int *h_gerr = reinterpret_cast<int *>(w->hpin + o_words + 8);
+    long long *h_trace = reinterpret_cast<long long *>(w->hpin + o_trace);
+    HIP_TRY(hipMemcpyAsync(h_counts, w->g_count, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_qlast, w->qlast, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_qstop, w->qstop, sizeof(int) * nq, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_ptop, w->pool_top, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_ovf, w->g_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_gerr, w->err, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (trace_words)
+        HIP_TRY(hipMemcpyAsync(h_trace, w->wstat, sizeof(long long) * trace_words,
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (*h_ovf || *h_gerr) return fail(MPAP_ERR_OVERFLOW, "goal front overflow");
+    std::memcpy(counts.data(), h_counts, sizeof(int) * nq);
+    std::memcpy(qlast.data(), h_qlast, sizeof(int) * nq);
+    std::memcpy(qstop.data(), h_qstop, sizeof(int) * nq);
+    const unsigned ptop = *h_ptop;
+    std::vector<long long> trace(h_trace, h_trace + trace_words);
+    long long packed = 0;
+    for (int q = 0; q < nq; ++q) packed += counts[q];
+    std::vector<float4> plab(packed);
+    std::vector<int> pnode(packed);
+    if (packed > 0) {
+        if ((r = ws_pinned(w, 20 * (size_t)packed))) return r;
+        float4 *h_lab = reinterpret_cast<float4 *>(w->hpin);
+        int *h_node = reinterpret_cast<int *>(w->hpin + 16 * (size_t)packed);
+        HIP_TRY(hipMemcpyAsync(h_lab, w->p_lab, sizeof(float4) * packed, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_node, w->p_node, sizeof(int) * packed, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::memcpy(plab.data(), h_lab, sizeof(float4) * packed);
+        std::memcpy(pnode.data(), h_node, sizeof(int) * packed);
+    }
+    search_finish(res, p, dev_out, counts.data(), plab.data(), pnode.data(), qlast.data(),
+                  qstop.data(), trace.data(), ms, retries, L);
+    res->pool_used = ptop;
     return MPAP_OK;
 }
 

@@ -189,6 +189,11 @@ struct Workspace {
     int *p_node = nullptr;
     long long p_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // pinned host staging of the small uploads and read-backs of a search
+    // (asynchronous copies without the runtime's pageable bounce); its bytes
+    // are in use until the stream has passed the copies that name them
+    unsigned char *hpin = nullptr;
+    size_t hpin_cap = 0;
 
     void free_all() {
         dfree(pool); dfree(pool_top); dfree(nb); dfree(minopen); dfree(gcnt); dfree(fo);
@@ -204,8 +209,24 @@ struct Workspace {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         ev0 = ev1 = nullptr;
+        if (hpin) (void)hipHostFree(hpin);
+        hpin = nullptr;
+        hpin_cap = 0;
     }
 };
+
+// At least `bytes` of pinned staging (the stream must have passed every copy
+// that uses the old buffer).
+inline int ws_pinned(Workspace *w, size_t bytes) {
+    if (bytes <= w->hpin_cap) return MPAP_OK;
+    size_t cap = std::max<size_t>(bytes, 64 * 1024);
+    if (w->hpin) (void)hipHostFree(w->hpin);
+    w->hpin = nullptr;
+    w->hpin_cap = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&w->hpin), cap, hipHostMallocDefault));
+    w->hpin_cap = cap;
+    return MPAP_OK;
+}
 
 inline int ws_alloc_nodes(Workspace *w, int32_t n, int nblocks) {
     int r;
@@ -388,9 +409,11 @@ SearchArgs search_args(const mpap_graph *g, Workspace *w, const SearchPrep &p,
                        const SearchShape &L);
 // After a successful search launch with arguments a (device status words in
 // dev_out): goal fronts, host copies and statistics into res.
+// total: the goal-front bound k_goal_bound already wrote to w->g_total (read
+// back by the caller), or -1 (this function runs k_goal_bound).
 int search_goal_finish(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Workspace *w,
                        hipStream_t s, mpap_result *res, const SearchArgs &a,
-                       const long long *dev_out, float ms, int retries);
+                       const long long *dev_out, float ms, int retries, long long total = -1);
 // A search workspace of g for launch shape L (a spare one when it fits).
 int acquire_workspace(mpap_graph *g, const SearchShape &L, Workspace **out);
 GoalArgs goal_args(const mpap_graph *g, Workspace *w);
