@@ -155,7 +155,13 @@ __device__ __forceinline__ void phase_select(const SearchArgs &a, long long iste
         for (int i = w; i < nflag; i += nw) {
             const int vv = list[i];
             const int goff = list_off[i];
+            // the node's record, its first open label, and its out-edges (the
+            // row and its first 64 targets) are read together: none depends
+            // on another
             const int4 nbv = a.nb[vv];
+            const int fo_w = a.fo[vv].w;
+            const int eb = a.optr[vv], ee = a.optr[vv + 1];
+            const int x_first = eb + l < ee ? a.ocol[eb + l] : -1;
             const float T = threshold(istep, step_of(a, vv));
             int run = 0;
             float rmin = MPAP_INF;
@@ -163,7 +169,7 @@ __device__ __forceinline__ void phase_select(const SearchArgs &a, long long iste
             // the bucket is sorted by cost: group labels lie below T from the
             // first open label on; past T only the first open label (the least
             // remaining open cost) matters, and it is the next first open one
-            for (int k0 = a.fo[vv].w; k0 < nbv.z; k0 += 64) {
+            for (int k0 = fo_w; k0 < nbv.z; k0 += 64) {
                 const int k = k0 + l;
                 bool in = false, op = false, le = false;
                 float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -199,12 +205,12 @@ __device__ __forceinline__ void phase_select(const SearchArgs &a, long long iste
             }
             // queue out-neighbours as merge targets of this wave, by the size
             // of their front (one slot reservation per wave of 64 out-edges)
-            for (int e0 = a.optr[vv]; e0 < a.optr[vv + 1]; e0 += 64) {
+            for (int e0 = eb; e0 < ee; e0 += 64) {
                 const int e = e0 + l;
                 int x = -1;
                 bool fresh = false, big = false;
-                if (e < a.optr[vv + 1]) {
-                    x = a.ocol[e];
+                if (e < ee) {
+                    x = e0 == eb ? x_first : a.ocol[e];
                     if constexpr (kSplit) {
                         fresh = atomicExch(&a.mark[x], wave) != wave;
                         if (fresh) big = a.nb[x].z > a.wcap;
