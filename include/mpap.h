@@ -478,7 +478,7 @@ int mpap_surrogate_load(mpap_surrogate *s, const char *path);
  *   Blocks until the front is in the caller's buffers.
  * Errors: MPAP_ERR_INVAL (as mpap_search; also a batched roadmap, skip != 0,
  * a roadmap whose per-node state leaves under 4 MiB of the scratch for labels
- * -- about 680,000 nodes), MPAP_ERR_OVERFLOW (the search needs more label
+ * -- about 620,000 nodes), MPAP_ERR_OVERFLOW (the search needs more label
  * storage than the scratch holds, or a front beyond the LDS stage of a
  * workgroup: there is no spill space; use mpap_search), MPAP_ERR_CAPACITY,
  * MPAP_ERR_NOCONVERGE, MPAP_ERR_HIP, MPAP_ERR_DEVICE.
