@@ -122,3 +122,32 @@ def test_rewalk_of_all_queries(small_batch):
         o += k
     assert o == allq["cost"].shape[0]
     res.close()
+
+
+@pytest.mark.parametrize("halves", [8192, -1])
+def test_mixed_objective_counts_in_one_launch(small_batch, halves):
+    """Two- and three-objective queries in one launch run the builds that
+    read the objective count per query: merges by halves forced
+    (`k_search_halves`) or whole workgroups only (`k_search`), single-wave
+    merges off.  Every goal front against the oracle; a group factor of 2
+    (the fronts do not depend on it) gives iterations with enough targets for
+    the halves."""
+    envs, graphs, parts, union = small_batch
+    nobj = [3 if e.dim == 3 else 2 for e in envs]
+    assert 2 in nobj and 3 in nobj
+    ps = [mpap.search_params(e.beta, k, e.radius, 2.0, wave_min_targets=-1, merge_halves=halves)
+          for e, k in zip(envs, nobj)]
+    res = mpap.mpap_search_batch(union, ps)
+    st = res.stats()
+    print({k: st[k] for k in ("gpu_ms", "wave_build", "build_objectives", "half_front_cap",
+                              "half_merges", "merges")}, flush=True)
+    assert st["wave_build"] == 0 and st["build_objectives"] == 0
+    if halves > 0:
+        assert st["half_front_cap"] > 0 and st["half_merges"] > 0
+    else:
+        assert st["half_front_cap"] == 0 and st["half_merges"] == 0
+    for q, (e, g, k) in enumerate(zip(envs, graphs, nobj)):
+        ref = osearch.search(g, e.beta, k)
+        rv, _, _ = osearch.goal_front(ref, g["goal"])
+        assert np.array_equal(bits(res.goal_front(q).vecs), bits(rv)), q
+    res.close()
