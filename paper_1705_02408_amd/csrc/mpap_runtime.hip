@@ -848,7 +848,7 @@ int search_eager(mpap_graph *g, const SearchPrep &p, const SearchShape &L, Works
         const int status = (int)dev_out[kOutStatus];
         if (status == kStatusOk && dev_err == 0) break;
         if (dev_err & kErrTimeout)
-            return fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)");
+            return fail(MPAP_ERR_HIP, "a grid or half-workgroup barrier wait timed out");
         if (dev_err & kErrTarget)
             return fail(MPAP_ERR_HIP, "internal error: a queued merge target is not a node");
         if (status == kStatusNoConverge)

@@ -235,7 +235,7 @@ extern "C" int mpap_search_noalloc(const mpap_graph *gc, const mpap_search_param
     HIP_TRY(hipStreamSynchronize(s));
     const int status = (int)dev_out[kOutStatus];
     if (dev_err & kErrTimeout)
-        return fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)");
+        return fail(MPAP_ERR_HIP, "a grid or half-workgroup barrier wait timed out");
     if (dev_err & kErrTarget)
         return fail(MPAP_ERR_HIP, "internal error: a queued merge target is not a node");
     if (status == kStatusNoConverge)

@@ -304,7 +304,7 @@ int mpap_plan_run(mpap_plan *p, void *stream, mpap_result **out) {
     const int status = (int)p->h_out[kOutStatus];
     const int err = *p->h_err;
     if (err & kErrTimeout)
-        return fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)");
+        return fail(MPAP_ERR_HIP, "a grid or half-workgroup barrier wait timed out");
     if (err & kErrTarget)
         return fail(MPAP_ERR_HIP, "internal error: a queued merge target is not a node");
     if (status == kStatusNoConverge)

@@ -440,7 +440,7 @@ int mpap_search_update(const mpap_result *prev, const mpap_graph *gc,
         const int status = (int)dev_out[kOutStatus];
         if (status == kStatusOk && dev_err == 0) break;
         if (dev_err & kErrTimeout)
-            return bail(fail(MPAP_ERR_HIP, "grid barrier timed out (blocks not co-resident?)"));
+            return bail(fail(MPAP_ERR_HIP, "a grid or half-workgroup barrier wait timed out"));
         if (dev_err & kErrTarget)
             return bail(fail(MPAP_ERR_HIP, "internal error: a queued merge target is not a node"));
         if (status == kStatusNoConverge)
