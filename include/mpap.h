@@ -76,6 +76,11 @@ typedef struct {
     int32_t k_out;      /* dim 6: out-degree (1..64) */
     float horizon;      /* dim 6: steering time T (> 0) */
     int32_t traj_steps; /* dim 6: check steps K per trajectory (1..255) */
+    int32_t near_grid;  /* dim 2/3, how Near finds its candidates (the edges are the
+                           same either way): 0 chooses, 1 a uniform grid of cells at
+                           least radius wide (rows sorted by target id afterwards;
+                           a row longer than 256 candidates makes the fill compare
+                           all pairs), -1 all pairs */
 } mpap_graph_params;
 
 /*

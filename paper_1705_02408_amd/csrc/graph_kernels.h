@@ -58,6 +58,32 @@ __device__ __forceinline__ double blob_quality_f64(const BuildArgs &g, const dou
     return fmin(fmax(acc, 0.0), 1.0);
 }
 
+// Uniform grid over the bounding box of the positions for Near: cells of
+// edge h >= r (1 + 2^-7) on each used axis, so any pair with Cost < r lies
+// in the same or adjacent cells even after the float32 roundings of the
+// distance and of the cell coordinates.  Nodes are counting-sorted by cell
+// (x fastest), so the three x-neighbour cells of a cell are one contiguous
+// run of the sorted arrays.
+struct GridArgs {
+    int gx, gy, gz;       // cells per axis (1 on an unused axis)
+    float lo[3];          // bounding-box corner (minimum of each coordinate)
+    float inv;            // 1 / h
+    int ncell;            // gx * gy * gz
+    int *ccount;          // [ncell] nodes per cell
+    int *cstart;          // [ncell] exclusive scan of ccount
+    int *sid;             // [n] node id at each sorted slot
+    float4 *spos;         // [n] its position (unused coordinates 0)
+};
+
+// rows the grid fill sorts in place (insertion by target id); a longer row
+// makes the host fill with the all-pairs kernel instead
+constexpr int kGridSortMax = 256;
+
+__global__ void k_grid_bin(BuildArgs g, GridArgs gr, int *cell, int *slot);
+__global__ void k_grid_scatter(BuildArgs g, GridArgs gr, const int *cell, const int *slot);
+__global__ void k_near_count_grid(BuildArgs g, GridArgs gr, int *cnt, int *max_cnt);
+__global__ void k_near_fill_grid(BuildArgs g, GridArgs gr, const int *off, int *cand_u,
+                                 int *cand_v, float *cand_c);
 __global__ void k_near_count(BuildArgs g, int *cnt);
 __global__ void k_near_fill(BuildArgs g, const int *off, int *cand_u, int *cand_v,
                             float *cand_c);

@@ -23,8 +23,123 @@ __device__ __forceinline__ float sqdist(const float *a, const float *b, int dim)
     return s;
 }
 
+// cell coordinate on one axis: floor((x - lo) / h), clamped to the grid
+// (monotone in x, so cells of points less than one cell apart differ by at
+// most one)
+__device__ __forceinline__ int cell_axis(float x, float lo, float inv, int cells) {
+    const float t = floorf((x - lo) * inv);
+    return (int)fminf(fmaxf(t, 0.0f), (float)(cells - 1));
+}
+
+__device__ __forceinline__ int cell_coords(const GridArgs &gr, const float *x, int dim, int &cx,
+                                           int &cy, int &cz) {
+    cx = cell_axis(x[0], gr.lo[0], gr.inv, gr.gx);
+    cy = cell_axis(x[1], gr.lo[1], gr.inv, gr.gy);
+    cz = dim == 3 ? cell_axis(x[2], gr.lo[2], gr.inv, gr.gz) : 0;
+    return (cz * gr.gy + cy) * gr.gx + cx;
+}
+
+// f(j) for every sorted slot j of the cells adjacent to (cx, cy, cz), the
+// cell itself included: per (y, z) row of cells one contiguous run
+template <class F>
+__device__ __forceinline__ void for_adjacent(const GridArgs &gr, int cx, int cy, int cz, F f) {
+    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, gr.gx - 1);
+    const int z1 = min(cz + 1, gr.gz - 1), y1 = min(cy + 1, gr.gy - 1);
+    for (int z = max(cz - 1, 0); z <= z1; ++z)
+        for (int y = max(cy - 1, 0); y <= y1; ++y) {
+            const int row = (z * gr.gy + y) * gr.gx;
+            const int b = gr.cstart[row + x0];
+            const int e = gr.cstart[row + x1] + gr.ccount[row + x1];
+            for (int j = b; j < e; ++j) f(j);
+        }
+}
 
 }  // namespace
+
+// Grid Near, step 1: each node's cell and its slot among the cell's nodes.
+__global__ void __launch_bounds__(256) k_grid_bin(BuildArgs g, GridArgs gr, int *cell, int *slot) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= g.n) return;
+    float x[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < g.dim; ++k) x[k] = g.pos[u * g.dim + k];
+    int cx, cy, cz;
+    const int c = cell_coords(gr, x, g.dim, cx, cy, cz);
+    cell[u] = c;
+    slot[u] = atomicAdd(&gr.ccount[c], 1);
+}
+
+// Step 2 (after the scan of the cell counts): nodes and positions in cell
+// order.
+__global__ void __launch_bounds__(256) k_grid_scatter(BuildArgs g, GridArgs gr, const int *cell,
+                                                      const int *slot) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= g.n) return;
+    float x[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < g.dim; ++k) x[k] = g.pos[u * g.dim + k];
+    const int i = gr.cstart[cell[u]] + slot[u];
+    gr.sid[i] = u;
+    gr.spos[i] = make_float4(x[0], x[1], x[2], 0.0f);
+}
+
+// Step 3: the Near count of each node (the same test as the all-pairs
+// kernel on the candidates of the adjacent cells); threads take nodes in
+// cell order so the lanes of a wave scan the same cells.  max_cnt gets the
+// longest row.
+__global__ void __launch_bounds__(256) k_near_count_grid(BuildArgs g, GridArgs gr, int *cnt,
+                                                         int *max_cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = 0;
+    if (i < g.n) {
+        const int u = gr.sid[i];
+        const float4 p = gr.spos[i];
+        const float xu[3] = {p.x, p.y, p.z};
+        int cx, cy, cz;
+        cell_coords(gr, xu, g.dim, cx, cy, cz);
+        for_adjacent(gr, cx, cy, cz, [&](int j) {
+            const float4 q = gr.spos[j];
+            const float xv[3] = {q.x, q.y, q.z};
+            const float cost = sqrtf(sqdist(xu, xv, g.dim));
+            c += (cost < g.r && gr.sid[j] != u) ? 1 : 0;
+        });
+        cnt[u] = c;
+    }
+    for (int o = 32; o > 0; o >>= 1) c = max(c, __shfl_xor(c, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, c);
+}
+
+// Step 4: the candidates of each node written to its row at off[u], kept in
+// target-id order by insertion (rows of at most kGridSortMax entries), so
+// the rows equal the all-pairs kernel's.
+__global__ void __launch_bounds__(256) k_near_fill_grid(BuildArgs g, GridArgs gr, const int *off,
+                                                        int *cand_u, int *cand_v, float *cand_c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int u = gr.sid[i];
+    const float4 p = gr.spos[i];
+    const float xu[3] = {p.x, p.y, p.z};
+    int cx, cy, cz;
+    cell_coords(gr, xu, g.dim, cx, cy, cz);
+    const int o = off[u];
+    int k = 0;
+    for_adjacent(gr, cx, cy, cz, [&](int j) {
+        const int v = gr.sid[j];
+        const float4 q = gr.spos[j];
+        const float xv[3] = {q.x, q.y, q.z};
+        const float cost = sqrtf(sqdist(xu, xv, g.dim));
+        if (cost < g.r && v != u) {
+            int at = k;
+            while (at > 0 && cand_v[o + at - 1] > v) {
+                cand_v[o + at] = cand_v[o + at - 1];
+                cand_c[o + at] = cand_c[o + at - 1];
+                --at;
+            }
+            cand_v[o + at] = v;
+            cand_c[o + at] = cost;
+            cand_u[o + k] = u;
+            ++k;
+        }
+    });
+}
 
 // Near: number of v != u with Cost(u, v) < r.  Positions are staged in LDS
 // tiles shared by the block.

@@ -269,10 +269,48 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
         (env->n_boxes > 0 && (!env->box_lo || !env->box_hi)) ||
         (env->n_blobs > 0 && (!env->blob_mu || !env->blob_sigma || !env->blob_amp)))
         return fail(MPAP_ERR_INVAL, "null obstacle or blob arrays");
-    for (long long i = 0; i < (long long)n * dim; ++i)
-        if (!std::isfinite(env->pos[i])) return fail(MPAP_ERR_INVAL, "non-finite position");
+    if (gp->near_grid < -1 || gp->near_grid > 1)
+        return fail(MPAP_ERR_INVAL, "near_grid must be -1, 0 or 1");
+    float plo[3] = {0.f, 0.f, 0.f}, phi[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < dim; ++k) plo[k] = phi[k] = env->pos[k];
+    for (long long i = 0; i < (long long)n * dim; ++i) {
+        const float x = env->pos[i];
+        if (!std::isfinite(x)) return fail(MPAP_ERR_INVAL, "non-finite position");
+        plo[i % dim] = std::min(plo[i % dim], x);
+        phi[i % dim] = std::max(phi[i % dim], x);
+    }
     for (int j = 0; j < env->n_blobs; ++j)
         if (!(env->blob_sigma[j] > 0.0f)) return fail(MPAP_ERR_INVAL, "blob sigma must be > 0");
+    // Grid for Near: cells of edge h >= r (1 + 2^-7), at most 16,000 per axis
+    // and max(64, min(2n, 2^30)) in all.  The 2^-7 margin covers the float32 roundings
+    // of Cost and of the cell coordinates (relative errors of a few 2^-24
+    // at coordinates below 16,384 cells), so a pair with Cost < r is never
+    // more than one cell apart on any axis.
+    GridArgs gr{};
+    gr.gx = gr.gy = gr.gz = 1;
+    bool use_grid = false;
+    if (gp->near_grid >= 0) {
+        double h = (double)gp->radius * (1.0 + 1.0 / 128.0);
+        for (int k = 0; k < dim; ++k) h = std::max(h, ((double)phi[k] - plo[k]) / 16000.0);
+        const double cap = std::max(64.0, std::min(2.0 * n, 1073741824.0));
+        int cells[3] = {1, 1, 1};
+        for (;;) {
+            double tot = 1.0;
+            for (int k = 0; k < dim; ++k) {
+                cells[k] = (int)(std::floor(((double)phi[k] - plo[k]) / h) + 1.0);
+                tot *= cells[k];
+            }
+            if (tot <= cap) break;
+            h *= 1.25;
+        }
+        gr.gx = cells[0]; gr.gy = cells[1]; gr.gz = cells[2];
+        gr.ncell = gr.gx * gr.gy * gr.gz;
+        for (int k = 0; k < 3; ++k) gr.lo[k] = plo[k];
+        gr.inv = (float)(1.0 / h);
+        // chosen when the adjacent cells are a small part of the box
+        const int adj = dim == 3 ? 27 : 9;
+        use_grid = gp->near_grid == 1 || (n >= 512 && gr.ncell >= 4 * adj);
+    }
     DeviceInfo di;
     int r = device_info(&di);
     if (r) return r;
@@ -281,12 +319,14 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
     float *d_pos = nullptr, *d_blo = nullptr, *d_bhi = nullptr, *d_mu = nullptr,
           *d_sig = nullptr, *d_amp = nullptr, *cand_c = nullptr;
     int *cnt = nullptr, *coff = nullptr, *cand_u = nullptr, *cand_v = nullptr, *keep = nullptr,
-        *kscan = nullptr, *tmp = nullptr, *ngoal = nullptr;
+        *kscan = nullptr, *tmp = nullptr, *ngoal = nullptr, *gcell = nullptr, *gslot = nullptr,
+        *maxc = nullptr;
     mpap_graph *g = nullptr;
     auto cleanup = [&]() {
         dfree(d_pos); dfree(d_blo); dfree(d_bhi); dfree(d_mu); dfree(d_sig); dfree(d_amp);
         dfree(cand_c); dfree(cnt); dfree(coff); dfree(cand_u); dfree(cand_v); dfree(keep);
-        dfree(kscan); dfree(tmp); dfree(ngoal);
+        dfree(kscan); dfree(tmp); dfree(ngoal); dfree(gcell); dfree(gslot); dfree(maxc);
+        dfree(gr.ccount); dfree(gr.cstart); dfree(gr.sid); dfree(gr.spos);
     };
     auto bail = [&](int st) {
         cleanup();
@@ -297,8 +337,14 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
     if ((r = dalloc(&d_pos, (size_t)n * dim)) || (r = dalloc(&d_blo, nb_)) ||
         (r = dalloc(&d_bhi, nb_)) || (r = dalloc(&d_mu, nf_ * dim)) ||
         (r = dalloc(&d_sig, nf_)) || (r = dalloc(&d_amp, nf_)) || (r = dalloc(&cnt, n)) ||
-        (r = dalloc(&coff, n)) || (r = dalloc(&tmp, div_up(std::max(n, 1), kScanTile) + 1)) ||
+        (r = dalloc(&coff, n)) ||
+        (r = dalloc(&tmp, div_up(std::max({n, gr.ncell, 1}), kScanTile) + 1)) ||
         (r = dalloc(&ngoal, 1)))
+        return bail(r);
+    if (use_grid &&
+        ((r = dalloc(&gcell, n)) || (r = dalloc(&gslot, n)) || (r = dalloc(&maxc, 1)) ||
+         (r = dalloc(&gr.ccount, gr.ncell)) || (r = dalloc(&gr.cstart, gr.ncell)) ||
+         (r = dalloc(&gr.sid, n)) || (r = dalloc(&gr.spos, n))))
         return bail(r);
     hipError_t he = hipSuccess;
     auto cp = [&](void *d, const void *h, size_t bytes) {
@@ -320,11 +366,22 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
     a.goal_r = env->goal_radius;
 
     const int nblk = div_up(n, 256);
-    k_near_count<<<nblk, 256, 0, s>>>(a, cnt);
+    if (use_grid) {
+        k_zero_i32<<<div_up(gr.ncell, 256), 256, 0, s>>>(gr.ccount, gr.ncell);
+        k_zero_i32<<<1, 256, 0, s>>>(maxc, 1);
+        k_grid_bin<<<nblk, 256, 0, s>>>(a, gr, gcell, gslot);
+        if ((r = scan_i32(gr.ccount, gr.cstart, gr.ncell, tmp, s))) return bail(r);
+        k_grid_scatter<<<nblk, 256, 0, s>>>(a, gr, gcell, gslot);
+        k_near_count_grid<<<nblk, 256, 0, s>>>(a, gr, cnt, maxc);
+    } else {
+        k_near_count<<<nblk, 256, 0, s>>>(a, cnt);
+    }
     if ((r = scan_i32(cnt, coff, n, tmp, s))) return bail(r);
-    int last_cnt = 0, last_off = 0;
+    int last_cnt = 0, last_off = 0, max_row = 0;
     HIP_TRY(hipMemcpyAsync(&last_cnt, cnt + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&last_off, coff + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    if (use_grid)
+        HIP_TRY(hipMemcpyAsync(&max_row, maxc, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const long long m = (long long)last_cnt + last_off;
     if ((r = dalloc(&cand_u, m)) || (r = dalloc(&cand_v, m)) || (r = dalloc(&cand_c, m)) ||
@@ -332,7 +389,10 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
         return bail(r);
     dfree(tmp);
     if ((r = dalloc(&tmp, div_up(std::max(m, 1LL), kScanTile) + 1))) return bail(r);
-    k_near_fill<<<nblk, 256, 0, s>>>(a, coff, cand_u, cand_v, cand_c);
+    if (use_grid && max_row <= kGridSortMax)
+        k_near_fill_grid<<<nblk, 256, 0, s>>>(a, gr, coff, cand_u, cand_v, cand_c);
+    else
+        k_near_fill<<<nblk, 256, 0, s>>>(a, coff, cand_u, cand_v, cand_c);
     if (m > 0) {
         const size_t lds = sizeof(float) * 2 * nb_;
         k_collide<<<div_up(m, 256), 256, lds, s>>>(a, m, cand_u, cand_v, cand_c, keep);

@@ -46,7 +46,8 @@ class mpap_env(ctypes.Structure):
 class mpap_graph_params(ctypes.Structure):
     _fields_ = [("radius", ctypes.c_float), ("check_step", ctypes.c_float),
                 ("reset_q", ctypes.c_float), ("k_out", ctypes.c_int32),
-                ("horizon", ctypes.c_float), ("traj_steps", ctypes.c_int32)]
+                ("horizon", ctypes.c_float), ("traj_steps", ctypes.c_int32),
+                ("near_grid", ctypes.c_int32)]
 
 
 class mpap_search_params(ctypes.Structure):
@@ -264,8 +265,11 @@ def mpap_graph_from_csr(row_ptr, col, cost, drift, reset, goal, stream=None) -> 
     return Graph(h)
 
 
-def mpap_build_graph(env, radius=None, check_step=None, reset_q=None, stream=None) -> Graph:
-    """Build the roadmap of an environment (synth.Env or alike) on the GPU."""
+def mpap_build_graph(env, radius=None, check_step=None, reset_q=None, stream=None,
+                     near_grid: int = 0) -> Graph:
+    """Build the roadmap of an environment (synth.Env or alike) on the GPU.
+    near_grid: 0 lets the library choose how Near finds candidates, 1 a
+    uniform grid, -1 all pairs (the same edges either way)."""
     lib = load()
     pos = np.ascontiguousarray(env.pos, np.float32)
     lo = np.ascontiguousarray(env.box_lo, np.float32)
@@ -298,7 +302,7 @@ def mpap_build_graph(env, radius=None, check_step=None, reset_q=None, stream=Non
                            float(env.check_step if check_step is None else check_step),
                            float(env.reset_q if reset_q is None else reset_q),
                            int(getattr(env, "k_out", 0)), float(getattr(env, "horizon", 0.0)),
-                           int(getattr(env, "traj_steps", 0)))
+                           int(getattr(env, "traj_steps", 0)), int(near_grid))
     h = ctypes.c_void_p()
     _check(lib.mpap_build_graph(ctypes.byref(e), ctypes.byref(gp), _stream(stream),
                                 ctypes.byref(h)))

@@ -4,6 +4,8 @@ Bar: bit-exact per-node fronts and goal fronts (the label vectors are unique,
 see the oracle's header); witnesses may differ and are checked by re-walking
 their paths.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -278,6 +280,112 @@ def test_build_graph_matches_oracle(dim, n, seed):
     bad = np.nonzero(bits(got["drift"]) != bits(ref["drift"]))[0]
     assert bad.size == 0, (bad.size, bad[:8])
     assert np.array_equal(got["reset"], ref["reset"])
+
+
+def near_env(pos, radius, boxes=False, blobs=True):
+    """An environment with the given float32 positions: its last node is the
+    goal (a build needs one); no boxes unless asked, so its edges are the Near
+    pairs themselves."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    dim = pos.shape[1]
+    env = synth.plain2d(0, n=200) if dim == 2 else synth.plain3d(0, n=200)
+    kw = dict(pos=pos, radius=float(np.float32(radius)), goal=pos[-1].copy(),
+              goal_radius=float(np.float32(1e-3)))
+    if not boxes:
+        kw.update(box_lo=np.zeros((0, dim), np.float32), box_hi=np.zeros((0, dim), np.float32))
+    if not blobs:
+        kw.update(blob_mu=np.zeros((0, dim), np.float32), blob_sigma=np.zeros(0, np.float32),
+                  blob_amp=np.zeros(0, np.float32))
+    return dataclasses.replace(env, **kw)
+
+
+def assert_same_roadmap(env, near_grid):
+    ref = ograph.build_graph(env)
+    dg = mpap.mpap_build_graph(env, near_grid=near_grid)
+    got = dg.export()
+    dg.close()
+    assert np.array_equal(got["row_ptr"], ref["row_ptr"]), near_grid
+    assert np.array_equal(got["col"], ref["col"]), near_grid
+    assert np.array_equal(bits(got["cost"]), bits(ref["cost"])), near_grid
+    assert np.array_equal(bits(got["drift"]), bits(ref["drift"])), near_grid
+    assert np.array_equal(got["goal"], ref["goal"]), near_grid
+    return ref
+
+
+@pytest.mark.parametrize("near_grid", [1, -1])
+@pytest.mark.parametrize("dim,n,seed", [(2, 2000, 0), (3, 3000, 1)])
+def test_near_by_grid_and_by_all_pairs_match_oracle(dim, n, seed, near_grid):
+    env = synth.plain2d(seed, n=n) if dim == 2 else synth.plain3d(seed, n=n)
+    assert_same_roadmap(env, near_grid)
+
+
+@pytest.mark.parametrize("near_grid", [0, 1])
+def test_near_grid_on_clustered_samples(near_grid):
+    """Dense clusters among sparse samples: cells of very different fill,
+    rows of the cluster beyond the in-place sort's 256 entries (then the
+    fill compares all pairs), and a second, milder cluster."""
+    rng = np.random.default_rng(7)
+    a = rng.uniform(0.0, 1.0, (1500, 3))
+    b = 0.5 + 0.03 * rng.standard_normal((900, 3))
+    c = 0.2 + 0.08 * rng.uniform(0.0, 1.0, (400, 3))
+    pos = np.concatenate([a, b, c])
+    ref = assert_same_roadmap(near_env(pos, 0.07), near_grid)
+    assert np.diff(ref["row_ptr"]).max() > 256
+
+
+def test_near_grid_rows_at_the_sort_limit():
+    """Every row below 256 candidates: the grid fill sorts all of them."""
+    rng = np.random.default_rng(11)
+    a = rng.uniform(0.0, 1.0, (3000, 3))
+    b = 0.5 + 0.04 * rng.standard_normal((300, 3))
+    ref = assert_same_roadmap(near_env(np.concatenate([a, b]), 0.06), 1)
+    deg = np.diff(ref["row_ptr"])
+    assert 100 < deg.max() <= 256
+
+
+def test_near_grid_with_one_cell():
+    """A radius wider than the sample box: one cell, every pair a neighbour,
+    rows beyond the sort limit."""
+    rng = np.random.default_rng(3)
+    pos = rng.uniform(0.0, 1.0, (300, 2))
+    ref = assert_same_roadmap(near_env(pos, 2.0, blobs=False), 1)
+    assert ref["row_ptr"][-1] == 300 * 299
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_near_grid_on_chains_just_under_the_radius(dim):
+    """Samples along a diagonal, consecutive ones about r apart (some just
+    below, some just above in float32), far from the origin: pairs straddle
+    cell boundaries wherever the cells fall."""
+    r = np.float32(0.05)
+    k = np.arange(2000, dtype=np.float64)
+    step = float(r) * (1.0 - 3e-7 * ((k % 7) - 3)) / np.sqrt(dim)
+    t = np.cumsum(step)
+    pos = 100.0 + np.repeat(t[:, None], dim, axis=1)
+    pos[:, 0] += 1e-4 * (k % 3)
+    ref = assert_same_roadmap(near_env(pos, r, blobs=False), 1)
+    assert 0 < ref["row_ptr"][-1] < 4 * 2000
+
+
+def test_near_grid_on_collinear_samples():
+    """Every sample on one line: one cell across, many along."""
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.0, 1.0, 2000)
+    pos = np.stack([x, np.full_like(x, 0.5)], axis=1)
+    assert_same_roadmap(near_env(pos, 0.004), 1)
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_near_grid_on_one_or_two_nodes(n):
+    pos = np.array([[0.1, 0.2, 0.3], [0.11, 0.2, 0.3]])[:n]
+    assert_same_roadmap(near_env(pos, 0.05), 1)
+
+
+def test_build_graph_rejects_a_bad_near_grid_mode():
+    env = synth.plain2d(0, n=300)
+    with pytest.raises(mpap.MpapError) as ei:
+        mpap.mpap_build_graph(env, near_grid=2)
+    assert ei.value.status == mpap.MPAP_ERR_INVAL
 
 
 def test_build_graph_without_goal_sample_fails():
