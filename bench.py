@@ -106,9 +106,46 @@ def host_cores() -> int:
 
 
 # ------------------------------------------------------------ single queries
-def measure_single(env, steps: int, warmup: int, with_trace: bool = True):
+def measure_tuned(dg, env, steps: int, ref_front):
+    """The same searches with the autotuner's settings for this roadmap
+    (chosen here, not read from a cache): times, the choice, and whether the
+    goal front is the default settings' bit for bit."""
+    import numpy as np
+    from paper_1705_02408_amd import autotune, mpap
+    base = mpap.search_params(env.beta, env.n_obj, env.radius, env.lam)
+    t0 = time.perf_counter()
+    ch = autotune.tune(dg, base, [env.dim], env.n_obj, cache_path=None, repeats=2)
+    tune_s = time.perf_counter() - t0
+    f = ch.fields()
+    kw = dict(near_scan=f["near_scan"], block_threads=f["block_threads"],
+              wave_min_targets=f["wave_min_targets"], stage_cap=f["stage_cap"],
+              merge_halves=f["merge_halves"])
+    times, kms, same = [], [], True
+    for i in range(steps + 1):
+        ts = time.perf_counter()
+        res = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, f["lambda_"], **kw)
+        fr = res.goal_front()
+        st = res.stats()
+        res.close()
+        if i == 0:
+            continue  # the first call sizes the workspace for the new settings
+        times.append(time.perf_counter() - ts)
+        kms.append(st["gpu_ms"])
+        same = same and np.array_equal(fr.vecs.view(np.uint32), ref_front.vecs.view(np.uint32))
+    total = sum(times)
+    out = {"choice": {k.rstrip("_"): v for k, v in f.items()}, "tune_s": tune_s,
+           "ms_per_step": 1000.0 * total / steps, "labels_per_s": st["front_labels"] * steps / total,
+           "kernel_ms_mean": statistics.mean(kms), "kernel_ms_min": min(kms),
+           "waves": st["waves"], "kernel": search_kernel(st), "X_front_labels": st["front_labels"],
+           "same_goal_front": bool(same)}
+    log(f"# {env.name} autotuned: {out}")
+    return out
+
+
+def measure_single(env, steps: int, warmup: int, with_trace: bool = True, tune: bool = False):
     """Whole searches of one roadmap built on the GPU: returns a dict of the
-    step and kernel times, counts and per-phase device times."""
+    step and kernel times, counts and per-phase device times (and, with
+    ``tune``, the same for the autotuner's settings)."""
     import numpy as np
     import torch
     from paper_1705_02408_amd import mpap
@@ -143,6 +180,7 @@ def measure_single(env, steps: int, warmup: int, with_trace: bool = True):
         stats.append(st)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    tuned = measure_tuned(dg, env, steps, fr) if tune else None
     dg.close()
     st = stats[-1]
     X, R = st["front_labels"], st["relaxations"]
@@ -165,6 +203,8 @@ def measure_single(env, steps: int, warmup: int, with_trace: bool = True):
         "alg_bytes_per_launch": B,
         "achieved_GBps": B / (k_ms * 1e-3) / 1e9,
     }
+    if tuned is not None:
+        out["autotuned"] = tuned
     if with_trace and "t" in trace:
         tr = trace["t"].astype(np.float64)
         out["phases"] = {
@@ -629,6 +669,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="time budget of each CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuned leg of the single-query workloads")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -653,7 +695,7 @@ def main():
     env = {"plain3d": lambda: synth.plain3d(args.seed, n=args.n),
            "plain2d": lambda: synth.plain2d(args.seed, n=args.n),
            "plain6d": lambda: synth.plain6d(args.seed, n=args.n)}[args.workload]()
-    head = measure_single(env, args.steps, args.warmup)
+    head = measure_single(env, args.steps, args.warmup, tune=not args.no_tune)
     for k in ("phases",):
         log(f"# {k} {head.get(k)}")
     headline_3d = args.workload == "plain3d" and args.n == 20000 and args.seed == 0
@@ -690,7 +732,8 @@ def main():
         rows = {}
         for name, env2 in (("plain2d_n2000", synth.plain2d(0)), ("plain6d_n50000",
                                                                 synth.plain6d(0))):
-            r = measure_single(env2, args.steps, args.warmup, with_trace=False)
+            r = measure_single(env2, args.steps, args.warmup, with_trace=False,
+                               tune=not args.no_tune)
             if not args.no_cpu_baseline and env2.dim == 2:
                 r["cpu_baseline"] = cpu_whole_search(env2)
             rows[name] = r

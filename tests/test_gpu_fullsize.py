@@ -357,6 +357,29 @@ def test_6d_fixpoint_at_every_state(road6d):
     res.close()
 
 
+@pytest.mark.parametrize("lam,wmin,stage,near", [(2.0, 4096, 2048, 8), (8.0, 16384, 0, 16),
+                                                  (2.0, 1, 0, 32)])
+def test_6d_tuned_settings_give_the_same_fronts(road6d, lam, wmin, stage, near):
+    """Settings of the kind the autotuner picks on this roadmap (a larger
+    group factor, merges by single waves, a smaller LDS stage) give every
+    state the default settings' front, bit for bit, in fewer iterations."""
+    env, dg = road6d
+    r0 = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, env.lam)
+    r1 = mpap.mpap_search(dg, env.beta, env.n_obj, env.radius, lam, wave_min_targets=wmin,
+                          stage_cap=stage, near_scan=near)
+    s0, s1 = r0.stats(), r1.stats()
+    print({k: (s0[k], s1[k]) for k in ("gpu_ms", "waves", "wave_build", "front_labels")},
+          flush=True)
+    assert s1["wave_build"] == 1 and s1["waves"] < s0["waves"]
+    assert s1["front_labels"] == s0["front_labels"]
+    for v in range(env.n_nodes):
+        a, b = sort_lex(r0.node_front(v)), sort_lex(r1.node_front(v))
+        assert np.array_equal(bits(a), bits(b)), v
+    assert np.array_equal(bits(r0.goal_front().vecs), bits(r1.goal_front().vecs))
+    r0.close()
+    r1.close()
+
+
 def test_6d_surrogate_trained_on_a_million_edges(road6d):
     """The learned drift on the 6D roadmap: trained on 2^20 edges, scored on
     all, error on the held-out rest; the search on it is judged by the
