@@ -75,8 +75,8 @@ struct GridArgs {
     float4 *spos;         // [n] its position (unused coordinates 0)
 };
 
-// rows the grid fill sorts in place (insertion by target id); a longer row
-// makes the host fill with the all-pairs kernel instead
+// longest row the grid path sorts (one wave per row, staged in LDS); a
+// longer row makes the host fill with the all-pairs kernel instead
 constexpr int kGridSortMax = 256;
 
 __global__ void k_grid_bin(BuildArgs g, GridArgs gr, int *cell, int *slot);
@@ -84,6 +84,7 @@ __global__ void k_grid_scatter(BuildArgs g, GridArgs gr, const int *cell, const 
 __global__ void k_near_count_grid(BuildArgs g, GridArgs gr, int *cnt, int *max_cnt);
 __global__ void k_near_fill_grid(BuildArgs g, GridArgs gr, const int *off, int *cand_u,
                                  int *cand_v, float *cand_c);
+__global__ void k_sort_rows(int n, const int *off, const int *cnt, int *cand_v, float *cand_c);
 __global__ void k_near_count(BuildArgs g, int *cnt);
 __global__ void k_near_fill(BuildArgs g, const int *off, int *cand_u, int *cand_v,
                             float *cand_c);

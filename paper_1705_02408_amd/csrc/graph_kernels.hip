@@ -107,9 +107,8 @@ __global__ void __launch_bounds__(256) k_near_count_grid(BuildArgs g, GridArgs g
     if ((threadIdx.x & 63) == 0) atomicMax(max_cnt, c);
 }
 
-// Step 4: the candidates of each node written to its row at off[u], kept in
-// target-id order by insertion (rows of at most kGridSortMax entries), so
-// the rows equal the all-pairs kernel's.
+// Step 4: the candidates of each node written to its row at off[u] in the
+// order the cells are scanned.
 __global__ void __launch_bounds__(256) k_near_fill_grid(BuildArgs g, GridArgs gr, const int *off,
                                                         int *cand_u, int *cand_v, float *cand_c) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -127,18 +126,38 @@ __global__ void __launch_bounds__(256) k_near_fill_grid(BuildArgs g, GridArgs gr
         const float xv[3] = {q.x, q.y, q.z};
         const float cost = sqrtf(sqdist(xu, xv, g.dim));
         if (cost < g.r && v != u) {
-            int at = k;
-            while (at > 0 && cand_v[o + at - 1] > v) {
-                cand_v[o + at] = cand_v[o + at - 1];
-                cand_c[o + at] = cand_c[o + at - 1];
-                --at;
-            }
-            cand_v[o + at] = v;
-            cand_c[o + at] = cost;
             cand_u[o + k] = u;
+            cand_v[o + k] = v;
+            cand_c[o + k] = cost;
             ++k;
         }
     });
+}
+
+// Step 5: each row put in target-id order, one wave per row (rows of at
+// most kGridSortMax entries, staged in LDS): an entry's place is the number
+// of smaller ids in its row (the ids of a row are distinct), so the rows
+// equal the all-pairs kernel's.
+__global__ void __launch_bounds__(256) k_sort_rows(int n, const int *off, const int *cnt,
+                                                   int *cand_v, float *cand_c) {
+    __shared__ int sv[4][kGridSortMax];
+    __shared__ float sc[4][kGridSortMax];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int u = blockIdx.x * 4 + w;
+    const int o = u < n ? off[u] : 0;
+    const int d = u < n ? min(cnt[u], kGridSortMax) : 0;
+    for (int i = l; i < d; i += 64) {
+        sv[w][i] = cand_v[o + i];
+        sc[w][i] = cand_c[o + i];
+    }
+    __syncthreads();
+    for (int i = l; i < d; i += 64) {
+        const int v = sv[w][i];
+        int rank = 0;
+        for (int j = 0; j < d; ++j) rank += sv[w][j] < v ? 1 : 0;
+        cand_v[o + rank] = v;
+        cand_c[o + rank] = sc[w][i];
+    }
 }
 
 // Near: number of v != u with Cost(u, v) < r.  Positions are staged in LDS

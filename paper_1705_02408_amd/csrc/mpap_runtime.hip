@@ -389,9 +389,10 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
         return bail(r);
     dfree(tmp);
     if ((r = dalloc(&tmp, div_up(std::max(m, 1LL), kScanTile) + 1))) return bail(r);
-    if (use_grid && max_row <= kGridSortMax)
+    if (use_grid && max_row <= kGridSortMax) {
         k_near_fill_grid<<<nblk, 256, 0, s>>>(a, gr, coff, cand_u, cand_v, cand_c);
-    else
+        k_sort_rows<<<div_up(n, 4), 256, 0, s>>>(n, coff, cnt, cand_v, cand_c);
+    } else
         k_near_fill<<<nblk, 256, 0, s>>>(a, coff, cand_u, cand_v, cand_c);
     if (m > 0) {
         const size_t lds = sizeof(float) * 2 * nb_;
