@@ -236,17 +236,31 @@ __global__ void __launch_bounds__(256) k_collide(BuildArgs g, long long m, const
     int K = (int)ceilf(cand_c[e] / g.step);
     if (K < 1) K = 1;
     const float fK = (float)K;
+    // Each rounded coordinate xa + t df is monotone in s (t = s/K rounded,
+    // t = 1 at s = K), so the points lie between the first (xa) and the
+    // last (xa + df rounded) on every axis: a box missing that range on an
+    // axis holds none of them.  The boxes are taken one at a time and only
+    // those meeting the range are tested point by point (the same set of
+    // point-in-box tests, grouped by box).
+    float plo[3] = {0.f, 0.f, 0.f}, phi[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < g.dim; ++k) {
+        const float last = xa[k] + df[k];
+        plo[k] = fminf(xa[k], last);
+        phi[k] = fmaxf(xa[k], last);
+    }
     bool hit = false;
-    for (int s = 0; s <= K && !hit; ++s) {
-        const float t = (float)s / fK;
-        float p[3];
-        for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + t * df[k];
-        for (int j = 0; j < g.nbox && !hit; ++j) {
+    for (int j = 0; j < g.nbox && !hit; ++j) {
+        const float *lo = &boxes[j * g.dim];
+        const float *hi = &boxes[g.nbox * g.dim + j * g.dim];
+        bool meets = true;
+        for (int k = 0; k < g.dim; ++k) meets = meets && phi[k] >= lo[k] && plo[k] <= hi[k];
+        if (!meets) continue;
+        for (int s = 0; s <= K && !hit; ++s) {
+            const float t = (float)s / fK;
             bool in = true;
             for (int k = 0; k < g.dim; ++k) {
-                const float lo = boxes[j * g.dim + k];
-                const float hi = boxes[g.nbox * g.dim + j * g.dim + k];
-                in = in && (p[k] >= lo) && (p[k] <= hi);
+                const float p = xa[k] + t * df[k];
+                in = in && (p >= lo[k]) && (p <= hi[k]);
             }
             hit = in;
         }
