@@ -96,6 +96,11 @@ __global__ void k_row_ptr(int n, long long m, const int *cand_off, const int *ks
                           const int *keep, int *row_ptr);
 __global__ void k_edge_drift(BuildArgs g, int n, const int *row_ptr, const int *col,
                              const float *cost, float *drift);
+// symmetric roadmaps: one thread per id-ordered pair, both edges written;
+// uptr[u] = entries v > u in rows before u (k_upper_count + exclusive scan)
+__global__ void k_edge_drift_pairs(BuildArgs g, int n, const int *row_ptr, const int *col,
+                                   const float *cost, const int *uptr, float *drift);
+__global__ void k_upper_count(int n, const int *row_ptr, const int *col, int *cnt);
 __global__ void k_node_flags(BuildArgs g, uint8_t *flag);
 __global__ void k_flag_list(int n, const uint8_t *flag, unsigned bit, int *list, int *count);
 __global__ void k_scan_block_sums(const int *in, long long n, int *bsum);
@@ -107,5 +112,8 @@ __global__ void k_zero_i32(int *p, long long n);
 // of (1 - q) along it (base, nullable)
 __global__ void k_edge_features(BuildArgs g, int n, const int *row_ptr, const int *col,
                                 const float *cost, uint16_t *X, float *base);
+__global__ void k_edge_features_pairs(BuildArgs g, int n, const int *row_ptr, const int *col,
+                                      const float *cost, const int *uptr, uint16_t *X,
+                                      float *base);
 __global__ void k_drift_ratio(long long m, const float *drift, const float *cost,
                               const float *base, float scale, float *t);

@@ -54,6 +54,96 @@ __device__ __forceinline__ void for_adjacent(const GridArgs &gr, int cx, int cy,
         }
 }
 
+// source row of the t-th id-ordered pair (a, b), a < b, of a symmetric
+// roadmap: the last row u with uptr[u] <= t
+__device__ __forceinline__ int pair_row(const int *uptr, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (uptr[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// index of edge v -> u in row v (rows sorted by target id), -1 if absent
+__device__ __forceinline__ int reverse_edge(const int *row_ptr, const int *col, int v, int u) {
+    const int end = row_ptr[v + 1];
+    int lo = row_ptr[v], hi = end;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    return (lo < end && col[lo] == u) ? lo : -1;
+}
+
+// blob parameters staged in LDS (mu[nblob*dim], sig[nblob], amp[nblob]);
+// returns g reading them from there
+__device__ __forceinline__ BuildArgs stage_blobs(const BuildArgs &g, float *blob) {
+    for (int i = threadIdx.x; i < g.nblob * g.dim; i += blockDim.x) blob[i] = g.mu[i];
+    for (int i = threadIdx.x; i < g.nblob; i += blockDim.x) {
+        blob[g.nblob * g.dim + i] = g.sig[i];
+        blob[g.nblob * g.dim + g.nblob + i] = g.amp[i];
+    }
+    __syncthreads();
+    BuildArgs gl = g;
+    gl.mu = blob;
+    gl.sig = blob + g.nblob * g.dim;
+    gl.amp = blob + g.nblob * g.dim + g.nblob;
+    return gl;
+}
+
+// drift of the id-ordered pair (a, b) of length len: sum_j (len/K)(1 - q(mid_j))
+// over the K sub-step midpoints x_a + ((j + 1/2)/K)(x_b - x_a), in float64
+// in j order from the float32 positions and length, rounded once to float32
+__device__ __forceinline__ float pair_drift(const BuildArgs &gl, int a, int b, float len) {
+    double xa[3] = {0.0, 0.0, 0.0}, df[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < gl.dim; ++k) {
+        xa[k] = (double)gl.pos[a * gl.dim + k];
+        df[k] = (double)gl.pos[b * gl.dim + k] - xa[k];
+    }
+    int K = (int)ceilf(len / gl.step);
+    if (K < 1) K = 1;
+    const double dK = (double)K;
+    const double w = (double)len / dK;
+    double acc = 0.0;
+    for (int j = 0; j < K; ++j) {
+        const double s = ((double)j + 0.5) / dK;
+        double p[3];
+        for (int k = 0; k < gl.dim; ++k) p[k] = xa[k] + s * df[k];
+        acc = acc + w * (1.0 - blob_quality_f64(gl, p));
+    }
+    return (float)acc;
+}
+
+// surrogate inputs of the id-ordered pair (a, b) of length len: x_a (3), x_b
+// (3, zero z in 2D), the length, q at the 8 segment points (k + 1/2)/8, q(x_b);
+// bfloat16.  Returns the 8-point estimate of the mean of (1 - q).
+__device__ __forceinline__ float pair_features(const BuildArgs &gl, int a, int b, float len,
+                                               uint16_t *f) {
+    float xa[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < gl.dim; ++k) {
+        xa[k] = gl.pos[a * gl.dim + k];
+        xb[k] = gl.pos[b * gl.dim + k];
+        df[k] = xb[k] - xa[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        f[k] = f2bf(xa[k]);
+        f[3 + k] = f2bf(xb[k]);
+    }
+    f[6] = f2bf(len);
+    float acc = 0.0f;
+    for (int j = 0; j < 8; ++j) {
+        const float s = ((float)j + 0.5f) / 8.0f;
+        float p[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < gl.dim; ++k) p[k] = xa[k] + s * df[k];
+        const float w = 1.0f - blob_quality(gl, p);
+        f[7 + j] = f2bf(w);
+        acc = acc + w;
+    }
+    f[15] = f2bf(1.0f - blob_quality(gl, xb));
+    return acc * 0.125f;
+}
+
 }  // namespace
 
 // Grid Near, step 1: each node's cell and its slot among the cell's nodes.
@@ -288,25 +378,13 @@ __global__ void __launch_bounds__(256) k_row_ptr(int n, long long m, const int *
     row_ptr[u] = (o < m) ? kscan[o] : (m > 0 ? kscan[m - 1] + keep[m - 1] : 0);
 }
 
-// drift of edge row u -> col[e]: sum_j (len/K)(1 - q(mid_j)) over the K
-// sub-step midpoints x_a + ((j + 1/2)/K)(x_b - x_a) of the id-ordered pair
-// (a, b) (the same value for both directions of an edge), evaluated in
-// float64 in j order from the float32 positions and length and rounded once
-// to float32.
+// drift of edge row u -> col[e] (pair_drift of the id-ordered pair: the same
+// value for both directions of an edge)
 __global__ void __launch_bounds__(256) k_edge_drift(BuildArgs g, int n, const int *row_ptr,
                                                     const int *col, const float *cost,
                                                     float *drift) {
     extern __shared__ float blob[];  // mu[nblob*dim], sig[nblob], amp[nblob]
-    for (int i = threadIdx.x; i < g.nblob * g.dim; i += blockDim.x) blob[i] = g.mu[i];
-    for (int i = threadIdx.x; i < g.nblob; i += blockDim.x) {
-        blob[g.nblob * g.dim + i] = g.sig[i];
-        blob[g.nblob * g.dim + g.nblob + i] = g.amp[i];
-    }
-    __syncthreads();
-    BuildArgs gl = g;
-    gl.mu = blob;
-    gl.sig = blob + g.nblob * g.dim;
-    gl.amp = blob + g.nblob * g.dim + g.nblob;
+    const BuildArgs gl = stage_blobs(g, blob);
     // one thread per edge; its source u: last row with row_ptr[u] <= e
     const int m = row_ptr[n];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -316,29 +394,47 @@ __global__ void __launch_bounds__(256) k_edge_drift(BuildArgs g, int n, const in
         const int mid = (lo + hi + 1) >> 1;
         if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
     }
-    const int u = lo;
-    {
-        const int v = col[e];
-        const int a = min(u, v), b = max(u, v);
-        double xa[3] = {0.0, 0.0, 0.0}, df[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < g.dim; ++k) {
-            xa[k] = (double)g.pos[a * g.dim + k];
-            df[k] = (double)g.pos[b * g.dim + k] - xa[k];
-        }
-        const float len = cost[e];
-        int K = (int)ceilf(len / g.step);
-        if (K < 1) K = 1;
-        const double dK = (double)K;
-        const double w = (double)len / dK;
-        double acc = 0.0;
-        for (int j = 0; j < K; ++j) {
-            const double s = ((double)j + 0.5) / dK;
-            double p[3];
-            for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + s * df[k];
-            acc = acc + w * (1.0 - blob_quality_f64(gl, p));
-        }
-        drift[e] = (float)acc;
+    const int u = lo, v = col[e];
+    drift[e] = pair_drift(gl, min(u, v), max(u, v), cost[e]);
+}
+
+// The same drift on a symmetric roadmap (rows sorted by target id), one
+// thread per id-ordered pair: the t-th pair's value is evaluated once and
+// written to both of its edges.  uptr[u] counts the entries v > u of the
+// rows before u (uptr[n] pairs in all).
+__global__ void __launch_bounds__(256) k_edge_drift_pairs(BuildArgs g, int n, const int *row_ptr,
+                                                          const int *col, const float *cost,
+                                                          const int *uptr, float *drift) {
+    extern __shared__ float blob[];
+    const BuildArgs gl = stage_blobs(g, blob);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= uptr[n]) return;
+    const int u = pair_row(uptr, n, t);
+    const int e = row_ptr[u + 1] - (uptr[u + 1] - t);
+    const int v = col[e];
+    const float d = pair_drift(gl, u, v, cost[e]);
+    drift[e] = d;
+    const int r = reverse_edge(row_ptr, col, v, u);
+    if (r >= 0) drift[r] = d;
+}
+
+// uptr helper: cnt[u] = entries v > u of row u (u < n), cnt[n] = 0; rows
+// sorted by target id, no self loops
+__global__ void __launch_bounds__(256) k_upper_count(int n, const int *row_ptr, const int *col,
+                                                     int *cnt) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n) return;
+    if (u == n) {
+        cnt[n] = 0;
+        return;
     }
+    const int end = row_ptr[u + 1];
+    int lo = row_ptr[u], hi = end;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    cnt[u] = end - lo;
 }
 
 __global__ void __launch_bounds__(256) k_node_flags(BuildArgs g, uint8_t *flag) {
@@ -439,25 +535,16 @@ __global__ void __launch_bounds__(256) k_zero_i32(int *p, long long n) {
         p[i] = 0;
 }
 
-// Inputs of the learned drift surrogate for edge row u -> col[e], from the
-// id-ordered pair (a, b) so both directions agree: x_a (3), x_b (3, zero z in
-// 2D), the length, q at the 8 segment points (k + 1/2)/8, q(x_b); bfloat16.
-// One thread per edge (its source found by a binary search of row_ptr), so
-// every lane has an edge whatever the node degrees.
+// Inputs of the learned drift surrogate for edge row u -> col[e]
+// (pair_features of the id-ordered pair, so both directions agree) and, if
+// base is not null, the 8-point estimate.  One thread per edge (its source
+// found by a binary search of row_ptr), so every lane has an edge whatever
+// the node degrees.
 __global__ void __launch_bounds__(256) k_edge_features(BuildArgs g, int n, const int *row_ptr,
                                                        const int *col, const float *cost,
                                                        uint16_t *X, float *base) {
     extern __shared__ float blob[];
-    for (int i = threadIdx.x; i < g.nblob * g.dim; i += blockDim.x) blob[i] = g.mu[i];
-    for (int i = threadIdx.x; i < g.nblob; i += blockDim.x) {
-        blob[g.nblob * g.dim + i] = g.sig[i];
-        blob[g.nblob * g.dim + g.nblob + i] = g.amp[i];
-    }
-    __syncthreads();
-    BuildArgs gl = g;
-    gl.mu = blob;
-    gl.sig = blob + g.nblob * g.dim;
-    gl.amp = blob + g.nblob * g.dim + g.nblob;
+    const BuildArgs gl = stage_blobs(g, blob);
     const int m = row_ptr[n];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
@@ -466,33 +553,40 @@ __global__ void __launch_bounds__(256) k_edge_features(BuildArgs g, int n, const
         const int mid = (lo + hi + 1) >> 1;
         if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
     }
-    const int u = lo;
-    {
-        const int v = col[e];
-        const int a = min(u, v), b = max(u, v);
-        float xa[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, df[3] = {0.f, 0.f, 0.f};
-        for (int k = 0; k < g.dim; ++k) {
-            xa[k] = g.pos[a * g.dim + k];
-            xb[k] = g.pos[b * g.dim + k];
-            df[k] = xb[k] - xa[k];
-        }
-        uint16_t *f = X + (size_t)e * 16;
-        for (int k = 0; k < 3; ++k) {
-            f[k] = f2bf(xa[k]);
-            f[3 + k] = f2bf(xb[k]);
-        }
-        f[6] = f2bf(cost[e]);
-        float acc = 0.0f;
-        for (int j = 0; j < 8; ++j) {
-            const float s = ((float)j + 0.5f) / 8.0f;
-            float p[3] = {0.f, 0.f, 0.f};
-            for (int k = 0; k < g.dim; ++k) p[k] = xa[k] + s * df[k];
-            const float w = 1.0f - blob_quality(gl, p);
-            f[7 + j] = f2bf(w);
-            acc = acc + w;
-        }
-        f[15] = f2bf(1.0f - blob_quality(gl, xb));
-        if (base) base[e] = acc * 0.125f;
+    const int u = lo, v = col[e];
+    const float b8 = pair_features(gl, min(u, v), max(u, v), cost[e], X + (size_t)e * 16);
+    if (base) base[e] = b8;
+}
+
+// The same inputs on a symmetric roadmap, one thread per id-ordered pair,
+// written to both of its edges (uptr as for k_edge_drift_pairs).
+__global__ void __launch_bounds__(256) k_edge_features_pairs(BuildArgs g, int n,
+                                                             const int *row_ptr, const int *col,
+                                                             const float *cost, const int *uptr,
+                                                             uint16_t *X, float *base) {
+    extern __shared__ float blob[];
+    const BuildArgs gl = stage_blobs(g, blob);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= uptr[n]) return;
+    const int u = pair_row(uptr, n, t);
+    const int e = row_ptr[u + 1] - (uptr[u + 1] - t);
+    const int v = col[e];
+    uint16_t f[16];
+    const float b8 = pair_features(gl, u, v, cost[e], f);
+    const int r = reverse_edge(row_ptr, col, v, u);
+    uint4 *xe = reinterpret_cast<uint4 *>(X + (size_t)e * 16);
+    const uint4 w0 = make_uint4(f[0] | ((unsigned)f[1] << 16), f[2] | ((unsigned)f[3] << 16),
+                                f[4] | ((unsigned)f[5] << 16), f[6] | ((unsigned)f[7] << 16));
+    const uint4 w1 = make_uint4(f[8] | ((unsigned)f[9] << 16), f[10] | ((unsigned)f[11] << 16),
+                                f[12] | ((unsigned)f[13] << 16), f[14] | ((unsigned)f[15] << 16));
+    xe[0] = w0;
+    xe[1] = w1;
+    if (base) base[e] = b8;
+    if (r >= 0) {
+        uint4 *xr = reinterpret_cast<uint4 *>(X + (size_t)r * 16);
+        xr[0] = w0;
+        xr[1] = w1;
+        if (base) base[r] = b8;
     }
 }
 

@@ -420,11 +420,13 @@ int mpap_build_graph(const mpap_env *env, const mpap_graph_params *gp, void *str
         k_compact_edges<<<div_up(m, 256), 256, 0, s>>>(m, keep, kscan, cand_v, cand_c, g->ocol,
                                                        g->ocost);
     k_row_ptr<<<div_up(n + 1, 256), 256, 0, s>>>(n, m, coff, kscan, keep, g->optr);
+    if ((r = build_pair_index(g, s))) return bail(r);
     {
+        // one thread per id-ordered pair, both directions written
         const size_t lds = sizeof(float) * (nf_ * dim + 2 * nf_);
         if (n > 0 && g->e > 0)
-            k_edge_drift<<<div_up(g->e, 256), 256, lds, s>>>(a, n, g->optr, g->ocol, g->ocost,
-                                                             g->odrift);
+            k_edge_drift_pairs<<<div_up(g->e / 2 + 1, 256), 256, lds, s>>>(
+                a, n, g->optr, g->ocol, g->ocost, g->uptr, g->odrift);
     }
     k_node_flags<<<nblk, 256, 0, s>>>(a, g->nflag);
     k_flag_list<<<1, 1024, 0, s>>>(n, g->nflag, 2u, g->goal_list, ngoal);
@@ -1265,6 +1267,23 @@ void mpap_result_free(mpap_result *r) {
 
 }  // extern "C"
 
+int build_pair_index(mpap_graph *g, hipStream_t s) {
+    int *cnt = nullptr, *tmp = nullptr;
+    int r;
+    if ((r = dalloc(&g->uptr, (size_t)g->n + 1)) || (r = dalloc(&cnt, (size_t)g->n + 1)) ||
+        (r = dalloc(&tmp, div_up((long long)g->n + 1, kScanTile) + 1))) {
+        dfree(cnt); dfree(tmp); dfree(g->uptr);
+        return r;
+    }
+    k_upper_count<<<div_up((long long)g->n + 1, 256), 256, 0, s>>>(g->n, g->optr, g->ocol, cnt);
+    r = scan_i32(cnt, g->uptr, (long long)g->n + 1, tmp, s);
+    const hipError_t he = hipStreamSynchronize(s);  // before the temporaries go
+    dfree(cnt); dfree(tmp);
+    if (!r && he != hipSuccess) r = fail(MPAP_ERR_HIP, hipGetErrorString(he));
+    if (r) dfree(g->uptr);
+    return r;
+}
+
 void graph_release(mpap_graph *g) {
     for (Workspace *w : g->spare) {
         w->free_all();
@@ -1278,6 +1297,6 @@ void graph_release(mpap_graph *g) {
     dfree(g->nflag); dfree(g->goal_list); dfree(g->qoff); dfree(g->qgoff);
     dfree(g->pos); dfree(g->bmu); dfree(g->bsig); dfree(g->bamp); dfree(g->feat); dfree(g->sbase); dfree(g->sdrift);
     dfree(g->blo); dfree(g->bhi);
-    dfree(g->vel); dfree(g->elen); dfree(g->rperm); dfree(g->srdrift);
+    dfree(g->vel); dfree(g->elen); dfree(g->rperm); dfree(g->srdrift); dfree(g->uptr);
     delete g;
 }

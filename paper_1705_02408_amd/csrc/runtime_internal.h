@@ -126,9 +126,16 @@ struct mpap_graph {
     uint16_t *feat = nullptr;  // [E][16] bf16 surrogate inputs, computed on demand
     float *sbase = nullptr;    // [E] 8-point estimate of the mean of (1 - q) per edge
     float *sdrift = nullptr;   // [E] surrogate drift (forward edge order)
+    // symmetric roadmaps with an environment: uptr[u] = entries v > u in the
+    // rows before u ([n+1]; uptr[n] id-ordered pairs), so the per-edge inputs
+    // and drifts are evaluated once per pair
+    int32_t *uptr = nullptr;
     std::vector<Workspace *> spare;
     std::mutex mu;
 };
+
+// g->uptr of a symmetric roadmap (rows sorted by target id); synchronises s
+int build_pair_index(mpap_graph *g, hipStream_t s);
 
 inline int graph_set_single_query(mpap_graph *g) {
     g->nq = 1;

@@ -141,7 +141,10 @@ int enqueue_features(mpap_graph *g, hipStream_t st) {
         a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
         a.reset_q = g->reset_q;
         const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
-        if (g->e > 0)
+        if (g->e > 0 && g->uptr)
+            k_edge_features_pairs<<<div_up(g->e / 2 + 1, 256), 256, lds, st>>>(
+                a, g->n, g->optr, g->ocol, g->ocost, g->uptr, g->feat, g->sbase);
+        else if (g->e > 0)
             k_edge_features<<<div_up(g->e, 256), 256, lds, st>>>(a, g->n, g->optr, g->ocol,
                                                                  g->ocost, g->feat, g->sbase);
     }
@@ -504,8 +507,12 @@ int enqueue_analytic_drift(const mpap_graph *g, float *out, hipStream_t st) {
         a.sig = g->bsig; a.amp = g->bamp; a.r = g->radius; a.step = g->check_step;
         a.reset_q = g->reset_q;
         const size_t lds = sizeof(float) * ((size_t)g->nblob * g->dim + 2 * (size_t)g->nblob);
-        k_edge_drift<<<div_up(g->e, 256), 256, lds, st>>>(a, g->n, g->optr, g->ocol, g->ocost,
-                                                          out);
+        if (g->uptr)
+            k_edge_drift_pairs<<<div_up(g->e / 2 + 1, 256), 256, lds, st>>>(
+                a, g->n, g->optr, g->ocol, g->ocost, g->uptr, out);
+        else
+            k_edge_drift<<<div_up(g->e, 256), 256, lds, st>>>(a, g->n, g->optr, g->ocol,
+                                                              g->ocost, out);
     }
     HIP_TRY(hipGetLastError());
     return MPAP_OK;

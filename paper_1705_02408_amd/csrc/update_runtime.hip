@@ -311,6 +311,7 @@ int mpap_graph_add_boxes(const mpap_graph *gc, int32_t n_boxes, const float *box
     ng->rptr = ng->optr; ng->rsrc = ng->ocol; ng->rcost = ng->ocost; ng->rdrift = ng->odrift;
     ng->dim = dim; ng->nbox = g->nbox + n_boxes; ng->nblob = g->nblob;
     ng->check_step = g->check_step; ng->reset_q = g->reset_q; ng->radius = g->radius;
+    if ((r = build_pair_index(ng, s))) return bail(r);
     HIP_TRY(hipStreamSynchronize(s));
     cleanup();
     if ((r = graph_set_single_query(ng))) {
