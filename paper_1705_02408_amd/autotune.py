@@ -27,10 +27,10 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 LAMBDAS = (0.25, 0.5, 1.0, 2.0, 4.0, 8.0)
 NEAR_SCANS = (8, 16, 32)
 BLOCK_THREADS = (1024, 512)
-# default threshold, never, every iteration, iterations of at least 4,096 or
-# 16,384 targets (the last two also choose the single-wave build where the
+# default threshold, never, every iteration, iterations of at least 4,096,
+# 16,384 or 32,768 targets (these also choose the single-wave build where the
 # default would not, as on roadmaps of many tiny fronts)
-WAVE_MIN_TARGETS = (0, -1, 1, 4096, 16384)
+WAVE_MIN_TARGETS = (0, -1, 1, 4096, 16384, 32768)
 STAGE_CAPS = (0, 2048)          # 0 = all the LDS holds
 MERGE_HALVES = (0, -1, 8192)    # by roadmap size, never, always
 
