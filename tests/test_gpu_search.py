@@ -367,6 +367,23 @@ def test_near_grid_on_chains_just_under_the_radius(dim):
     assert 0 < ref["row_ptr"][-1] < 4 * 2000
 
 
+@pytest.mark.parametrize("dim,offset,length,n,r", [(2, 1e3, 1.0, 4000, 0.02),
+                                                   (3, 1e4, 1.0, 3000, 0.06),
+                                                   (2, 1e4, 1000.0, 4000, 0.5)])
+def test_near_grid_far_from_the_origin(dim, offset, length, n, r):
+    """Samples offset far from the origin, where float32 coordinates are
+    coarse (spacing 6e-5 at 1e3, 1e-3 at 1e4), in a square or cube of side
+    1, or along a strip 1000 long and 0.3 wide (about 2,000 cells on its
+    axis): the grid keeps every pair of the all-pairs set."""
+    rng = np.random.default_rng(int(offset) + dim + n)
+    u = rng.uniform(0.0, 1.0, (n, dim))
+    if length > 1.0:
+        u[:, 0] *= length
+        u[:, 1:] *= 0.3
+    ref = assert_same_roadmap(near_env(offset + u, r, blobs=False), 1)
+    assert ref["row_ptr"][-1] > 0
+
+
 def test_near_grid_on_collinear_samples():
     """Every sample on one line: one cell across, many along."""
     rng = np.random.default_rng(5)
